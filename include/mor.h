@@ -1,0 +1,231 @@
+/*
+ * mor.h - C ABI of the MI355X reduced-frequency Lippmann-Schwinger solver.
+ *
+ * Method: Gierden, Waimann, Svendsen, Reese, "A geometrically adapted reduced
+ * set of frequencies for a FFT-based microstructure simulation" (arXiv
+ * 2103.10203).  Section references below are to that paper.
+ *
+ * General conventions
+ *  - Every call returns a mor_status.  No exception or signal crosses the ABI.
+ *    On a status other than MOR_OK, mor_last_error() returns a thread-local,
+ *    NUL-terminated message that stays valid until the next call on the same
+ *    thread.
+ *  - Grids are C-ordered: n[0] is the slowest axis.  Array axis a is the
+ *    physical direction x_{a+1}; strain component "11" is the normal strain
+ *    along axis 0.
+ *  - Tensor components are tensor (not engineering) components, ordered
+ *      2D (plane strain): strain [11, 22, 12], stress [11, 22, 12, 33]
+ *      3D:                strain and stress [11, 22, 33, 23, 13, 12].
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory on the current device (e.g. torch CUDA tensors' data_ptr()).
+ *  - Units are the caller's (the tests use GPa).
+ *  - The caller owns every buffer it passes; the library owns plans.
+ *  - All work is issued on the stream given in the options (NULL = the null
+ *    stream).  Calls that return host results synchronise that stream.
+ */
+#ifndef MOR_H
+#define MOR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MOR_OK = 0,
+  MOR_E_INVALID_ARG = 1,   /* argument outside its documented domain          */
+  MOR_E_OUT_OF_MEMORY = 2, /* a device allocation failed                      */
+  MOR_E_DEVICE = 3,        /* a HIP runtime call or kernel launch failed      */
+  MOR_E_NOT_CONVERGED = 4, /* max_iter reached; outputs hold the last iterate */
+  MOR_E_NONFINITE = 5,     /* a NaN/Inf appeared in the iteration             */
+  MOR_E_UNSUPPORTED = 6    /* valid input this build does not handle          */
+} mor_status;
+
+/* Opaque plan: the adapted sampling pattern of one microstructure and the
+ * device tables derived from it.  Immutable after creation, so one plan may
+ * serve concurrent solves on different streams. */
+typedef struct mor_plan* mor_plan_t;
+
+typedef struct {
+  int32_t ndim;   /* 2 or 3 */
+  int32_t pad_;
+  int64_t n[3];   /* points per axis; 2D uses n[0], n[1] */
+} mor_grid;
+
+enum { MOR_GAMMA_ROTATED = 0,     /* rotated first-order finite differences (Sec. 3, default) */
+       MOR_GAMMA_CONTINUOUS = 1 };/* classic continuous wave vector                            */
+
+typedef struct {
+  int32_t gamma_kind; /* MOR_GAMMA_* */
+  int32_t pad_;
+  void* stream;       /* hipStream_t for the plan kernels, NULL = null stream */
+} mor_plan_opts;
+
+typedef struct {
+  int64_t N;               /* grid points                                       */
+  int64_t M;               /* requested number of frequencies                   */
+  int64_t M_actual;        /* selected after conjugate-pair closure (M or M+1)  */
+  int64_t n_coeff;         /* stored coefficients per strain component (the
+                              half-spectrum part of the pattern)                */
+  int64_t n_columns;       /* distinct frequency columns of the transform       */
+  int64_t n_last;          /* distinct last-axis frequencies (3D), = n_columns in 2D */
+  int64_t inclusion_count; /* voxels with g = 1                                 */
+  int32_t ncomp;           /* strain components: 3 (2D) or 6 (3D)               */
+  int32_t nstress;         /* stress components: 4 (2D) or 6 (3D)               */
+} mor_plan_info;
+
+/*
+ * mor_plan_create - geometrically adapted sampling pattern (Sec. 4.2).
+ *
+ * Computes the FP64 power spectrum P(m) = |FFT(g)(m)|^2 of the phase
+ * indicator g (1 = inclusion, 0 = matrix), ranks the frequencies by
+ * amplitude and keeps the first M (whole conjugate pairs; xi = 0 always),
+ * then builds the transform and Green-operator tables of the reduced scheme
+ * (Sec. 4, steps b-d).  Ranking: key(m) = float32_rn(P(m)/P(0)), or 0 where
+ * P(m) <= 2^-80 P(0), descending; ties by |s(m)|^2 ascending (s = signed
+ * centred frequency, N/2 counted +N/2), then by the lexicographic rank of the
+ * pair's representative (the member with the smaller rank over
+ * u_a = s_a + (n_a-1)/2, axis 0 most significant).
+ *
+ *   grid      host; ndim 2 or 3; every n even, n = 2^a 3^b, 4 <= n <= 1024
+ *             (other sizes: MOR_E_UNSUPPORTED).
+ *   phase_map host uint8 [N], values 0 or 1 (else MOR_E_INVALID_ARG).
+ *   M         1 <= M <= N.
+ *   opts      NULL for defaults.
+ *   out       receives the plan; release with mor_plan_destroy.
+ */
+mor_status mor_plan_create(const mor_grid* grid, const uint8_t* phase_map, int64_t M,
+                           const mor_plan_opts* opts, mor_plan_t* out);
+
+mor_status mor_plan_get_info(mor_plan_t plan, mor_plan_info* info);
+
+/*
+ * mor_plan_pattern - copy the pattern to host memory.
+ *   sorted_idx host int64 [cap] or NULL: linear FFT indices, ascending.
+ *   rank_idx   host int64 [cap] or NULL: the same set in selection order
+ *              (each pair's representative, then its partner).
+ *   cap must be >= M_actual when either array is given.
+ */
+mor_status mor_plan_pattern(mor_plan_t plan, int64_t* sorted_idx, int64_t* rank_idx,
+                            int64_t cap, int64_t* M_actual);
+
+/*
+ * mor_plan_coeff_index - linear FFT index of every stored coefficient, in
+ * the library's coefficient order (host int64 [n_coeff]).  Lets a caller
+ * read or seed the coefficient arrays of mor_solve.
+ */
+mor_status mor_plan_coeff_index(mor_plan_t plan, int64_t* lin_idx, int64_t cap);
+
+mor_status mor_plan_destroy(mor_plan_t plan);
+
+/* Phase material (Sec. 2): isotropic Lame constants; J2 plasticity with
+ * initial yield stress sigma_y0 and linear isotropic hardening modulus H when
+ * plastic != 0.  phase[0] is the matrix (g = 0), phase[1] the inclusion. */
+typedef struct {
+  double lambda, mu, sigma_y0, H;
+  int32_t plastic;
+  int32_t pad_;
+} mor_phase;
+
+enum { MOR_PREC_FP32 = 0,     /* FP32 transforms and fields (default)            */
+       MOR_PREC_BF16X3 = 1 }; /* split-bf16 partial DFT on MFMA, FP32 accumulate */
+enum { MOR_TRANSFORM_AUTO = 0, MOR_TRANSFORM_FFT = 1, MOR_TRANSFORM_DFT = 2 };
+
+typedef struct {
+  int32_t max_iter;     /* 0 -> 10000                                            */
+  int32_t precision;    /* MOR_PREC_*                                            */
+  int32_t transform;    /* MOR_TRANSFORM_*                                       */
+  int32_t check_every;  /* iterations between device->host convergence polls;
+                           0 -> library default                                  */
+  const float* warm_start; /* device complex64 [B][ncomp][n_coeff] strain
+                              coefficients in plan coefficient order (the
+                              zero frequency entry is ignored and set to
+                              N * macro strain), or NULL for the cold start
+                              eps0 = macro strain                                */
+  void* stream;         /* hipStream_t, NULL = null stream                       */
+  int32_t use_graph;    /* replay the iteration chunk from a captured hipGraph   */
+  int32_t pad_;
+} mor_solve_opts;
+
+typedef struct {
+  double* eff_stress;   /* host [B][nstress] or NULL: grid mean of sigma(eps_final), FP64 sum */
+  float* strain;        /* device [B][ncomp][N] or NULL                                      */
+  float* stress;        /* device [B][nstress][N] or NULL                                    */
+  int32_t* iterations;  /* host [B] or NULL: Green-operator applications                     */
+  double* residual;     /* host [B] or NULL: last residual                                   */
+  float* coeffs;        /* device complex64 [B][ncomp][n_coeff] or NULL: final strain
+                           coefficients (unnormalised DFT of eps_final)                      */
+} mor_outputs;
+
+/*
+ * mor_solve - reduced basic fixed-point scheme (Sec. 4, steps a-d) for B
+ * RVEs of one microstructure with different macro strains.
+ *
+ * Per iteration: a) tau = sigma(eps) - C0:eps at every grid point (C0 = mean
+ * of the two phases' Lame constants, Sec. 3); b) tau^ on the pattern;
+ * c) eps^ = -Gamma0^ : tau^ (eps^(0) = N eps_bar); d) eps on the grid.
+ * Stops per RVE at the first residual
+ *     r = sqrt(mean_x ||eps^{i+1}-eps^i||_F^2) / ||eps_bar||_F < tol
+ * (denominator 1 if eps_bar = 0); r is evaluated in FP64 from the
+ * coefficients (Parseval).  Then sigma(eps_final) and its FP64 grid mean.
+ *
+ *   macro_strain host double [B][ncomp].
+ *   phase        host [2].
+ *   tol > 0.
+ * Returns MOR_E_NOT_CONVERGED (outputs = last iterate) if an RVE hits
+ * max_iter, MOR_E_NONFINITE if an RVE's residual became NaN/Inf.
+ */
+mor_status mor_solve(mor_plan_t plan, const double* macro_strain, int64_t B,
+                     const mor_phase phase[2], double tol, const mor_solve_opts* opts,
+                     mor_outputs* out);
+
+/*
+ * mor_solve_multi - as mor_solve for B RVEs that may use different plans
+ * (different microstructures and grid sizes) in one call.  RVE b uses
+ * plans[plan_of_rve[b]] (host arrays).  Field outputs are packed: RVE b's
+ * strain starts at element offset ncomp * (sum of N of RVEs before b), and
+ * likewise stress with nstress; eff_stress rows have 6 entries per RVE
+ * (2D RVEs use the first 4).  Coefficient outputs/warm starts are packed the
+ * same way with n_coeff.
+ */
+mor_status mor_solve_multi(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of_rve,
+                           const double* macro_strain_packed, int64_t B, const mor_phase phase[2],
+                           double tol, const mor_solve_opts* opts, mor_outputs* out);
+
+/*
+ * mor_solve_path - elasto-plastic load path (Secs. 2 and 5.2): `steps`
+ * macro strains applied in order, one RVE.  Step n starts from the converged
+ * strain of step n-1 plus the macro increment; the J2 state committed at the
+ * end of step n-1 is held fixed during step n's iterations and replaced by
+ * the state of step n's final constitutive evaluation.
+ *
+ *   macro_strain host double [steps][ncomp].
+ *   state        device float [nstate][N], caller-owned, in/out; nstate = 5
+ *                in 2D (eps_p 11, 22, 12, 33, accumulated plastic strain)
+ *                and 7 in 3D (eps_p 11, 22, 33, 23, 13, 12, accumulated).
+ *                Zero it for a virgin material.
+ *   out          eff_stress host [steps][nstress], iterations/residual host
+ *                [steps]; field outputs hold the last step.
+ */
+mor_status mor_solve_path(mor_plan_t plan, const double* macro_strain, int32_t steps,
+                          const mor_phase phase[2], double tol, const mor_solve_opts* opts,
+                          float* state, mor_outputs* out);
+
+/* Per-kernel timing over solves while enabled: HIP events bracket every launch
+ * of the named kernel on the solve stream; `items` counts the work units the
+ * launches processed (converged RVEs exit early and are not counted) and
+ * `bytes` the algorithmic HBM bytes of those units. */
+mor_status mor_profile_enable(int32_t on);
+mor_status mor_profile_reset(void);
+mor_status mor_profile_query(const char* kernel, double* total_ms, int64_t* launches,
+                             int64_t* items, double* bytes);
+
+const char* mor_last_error(void);
+const char* mor_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOR_H */

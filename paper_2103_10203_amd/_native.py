@@ -1,0 +1,339 @@
+"""ctypes binding of libmor.so (include/mor.h).  Argument marshalling only:
+every step of the solver runs in the library's HIP kernels.  Device buffers are
+torch CUDA tensors (ROCm); streams are torch's current stream unless given.
+The library must be built first (``python -m paper_2103_10203_amd.build``);
+importing this module raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmor.so")
+
+MOR_OK = 0
+MOR_E_INVALID_ARG = 1
+MOR_E_OUT_OF_MEMORY = 2
+MOR_E_DEVICE = 3
+MOR_E_NOT_CONVERGED = 4
+MOR_E_NONFINITE = 5
+MOR_E_UNSUPPORTED = 6
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_CONVERGED",
+                5: "NONFINITE", 6: "UNSUPPORTED"}
+
+GAMMA_ROTATED = 0
+GAMMA_CONTINUOUS = 1
+PREC_FP32 = 0
+PREC_BF16X3 = 1
+TRANSFORM_AUTO = 0
+TRANSFORM_FFT = 1
+TRANSFORM_DFT = 2
+
+
+class MorError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class mor_grid(ct.Structure):
+    _fields_ = [("ndim", ct.c_int32), ("pad_", ct.c_int32), ("n", ct.c_int64 * 3)]
+
+
+class mor_plan_opts(ct.Structure):
+    _fields_ = [("gamma_kind", ct.c_int32), ("pad_", ct.c_int32), ("stream", ct.c_void_p)]
+
+
+class mor_plan_info(ct.Structure):
+    _fields_ = [("N", ct.c_int64), ("M", ct.c_int64), ("M_actual", ct.c_int64), ("n_coeff", ct.c_int64),
+                ("n_columns", ct.c_int64), ("n_last", ct.c_int64), ("inclusion_count", ct.c_int64),
+                ("ncomp", ct.c_int32), ("nstress", ct.c_int32)]
+
+
+class mor_phase(ct.Structure):
+    _fields_ = [("lambda_", ct.c_double), ("mu", ct.c_double), ("sigma_y0", ct.c_double), ("H", ct.c_double),
+                ("plastic", ct.c_int32), ("pad_", ct.c_int32)]
+
+
+class mor_solve_opts(ct.Structure):
+    _fields_ = [("max_iter", ct.c_int32), ("precision", ct.c_int32), ("transform", ct.c_int32),
+                ("check_every", ct.c_int32), ("warm_start", ct.c_void_p), ("stream", ct.c_void_p),
+                ("use_graph", ct.c_int32), ("pad_", ct.c_int32)]
+
+
+class mor_outputs(ct.Structure):
+    _fields_ = [("eff_stress", ct.POINTER(ct.c_double)), ("strain", ct.c_void_p), ("stress", ct.c_void_p),
+                ("iterations", ct.POINTER(ct.c_int32)), ("residual", ct.POINTER(ct.c_double)),
+                ("coeffs", ct.c_void_p)]
+
+
+# Every function declared in include/mor.h, with its ctypes signature.
+_SIGS = {
+    "mor_plan_create": (ct.c_int, [ct.POINTER(mor_grid), ct.c_void_p, ct.c_int64, ct.POINTER(mor_plan_opts),
+                                   ct.POINTER(ct.c_void_p)]),
+    "mor_plan_get_info": (ct.c_int, [ct.c_void_p, ct.POINTER(mor_plan_info)]),
+    "mor_plan_pattern": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_int64)]),
+    "mor_plan_coeff_index": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64]),
+    "mor_plan_destroy": (ct.c_int, [ct.c_void_p]),
+    "mor_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.POINTER(mor_phase), ct.c_double,
+                             ct.POINTER(mor_solve_opts), ct.POINTER(mor_outputs)]),
+    "mor_solve_multi": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64,
+                                   ct.POINTER(mor_phase), ct.c_double, ct.POINTER(mor_solve_opts),
+                                   ct.POINTER(mor_outputs)]),
+    "mor_solve_path": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.POINTER(mor_phase), ct.c_double,
+                                  ct.POINTER(mor_solve_opts), ct.c_void_p, ct.POINTER(mor_outputs)]),
+    "mor_profile_enable": (ct.c_int, [ct.c_int32]),
+    "mor_profile_reset": (ct.c_int, []),
+    "mor_profile_query": (ct.c_int, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64),
+                                     ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]),
+    "mor_last_error": (ct.c_char_p, []),
+    "mor_version": (ct.c_char_p, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2103_10203_amd.build`")
+    # torch ships its own HIP runtime under the same soname as /opt/rocm's.
+    # Load torch first so that libmor binds to the runtime torch already
+    # holds: one process must not initialise two HSA runtimes.
+    import torch  # noqa: F401
+    lib = ct.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status, allow=()):
+    if status != MOR_OK and status not in allow:
+        raise MorError(status, lib.mor_last_error().decode())
+    return status
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        torch = _torch()
+        if torch.cuda.is_available():
+            return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return ct.c_void_p(None)
+    if isinstance(stream, int):
+        return ct.c_void_p(stream)
+    return ct.c_void_p(stream.cuda_stream)
+
+
+@dataclass(frozen=True)
+class Phase:
+    """Isotropic phase: Lame constants, optional J2 plasticity (linear hardening)."""
+    lam: float
+    mu: float
+    sigma_y0: float = 0.0
+    H: float = 0.0
+    plastic: bool = False
+
+
+def _phases(phases):
+    arr = (mor_phase * 2)()
+    for i, p in enumerate(phases):
+        arr[i] = mor_phase(float(p.lam), float(p.mu), float(p.sigma_y0), float(p.H), 1 if p.plastic else 0, 0)
+    return arr
+
+
+class Plan:
+    """Adapted sampling pattern of one microstructure (mor_plan_create)."""
+
+    def __init__(self, g: np.ndarray, M: int, gamma_kind: int = GAMMA_ROTATED, stream=None):
+        g = np.ascontiguousarray(g, dtype=np.uint8)
+        if g.ndim not in (2, 3):
+            raise ValueError("phase map must be 2D or 3D")
+        grid = mor_grid()
+        grid.ndim = g.ndim
+        for a in range(3):
+            grid.n[a] = g.shape[a] if a < g.ndim else 1
+        opts = mor_plan_opts(gamma_kind, 0, _stream_ptr(stream))
+        h = ct.c_void_p()
+        _check(lib.mor_plan_create(ct.byref(grid), _np_ptr(g), int(M), ct.byref(opts), ct.byref(h)))
+        self._h = h
+        self.shape = g.shape
+        self.ndim = g.ndim
+        inf = mor_plan_info()
+        _check(lib.mor_plan_get_info(self._h, ct.byref(inf)))
+        self.info = {k: getattr(inf, k) for k, _ in mor_plan_info._fields_}
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def ncomp(self):
+        return self.info["ncomp"]
+
+    @property
+    def nstress(self):
+        return self.info["nstress"]
+
+    @property
+    def n_coeff(self):
+        return self.info["n_coeff"]
+
+    @property
+    def N(self):
+        return self.info["N"]
+
+    def pattern(self):
+        m = self.info["M_actual"]
+        s = np.zeros(m, np.int64)
+        r = np.zeros(m, np.int64)
+        ma = ct.c_int64()
+        _check(lib.mor_plan_pattern(self._h, _np_ptr(s), _np_ptr(r), m, ct.byref(ma)))
+        return s, r
+
+    def coeff_index(self):
+        n = self.info["n_coeff"]
+        out = np.zeros(n, np.int64)
+        _check(lib.mor_plan_coeff_index(self._h, _np_ptr(out), n))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.mor_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class SolveResult:
+    status: int
+    eff_stress: np.ndarray
+    iterations: np.ndarray
+    residual: np.ndarray
+    strain: object = None
+    stress: object = None
+    coeffs: object = None
+
+
+def _opts(max_iter, check_every, warm_start, stream, precision=PREC_FP32, transform=TRANSFORM_AUTO, use_graph=0):
+    ws = ct.c_void_p(warm_start.data_ptr()) if warm_start is not None else ct.c_void_p(None)
+    return mor_solve_opts(int(max_iter), int(precision), int(transform), int(check_every), ws,
+                          _stream_ptr(stream), int(use_graph), 0)
+
+
+def _outputs(B, S, eff_rows, want_fields, want_coeffs, nfield_pts, C, ncoef_total):
+    torch = _torch()
+    eff = np.zeros((eff_rows, S), np.float64)
+    its = np.zeros(B, np.int32)
+    res = np.zeros(B, np.float64)
+    out = mor_outputs()
+    out.eff_stress = eff.ctypes.data_as(ct.POINTER(ct.c_double))
+    out.iterations = its.ctypes.data_as(ct.POINTER(ct.c_int32))
+    out.residual = res.ctypes.data_as(ct.POINTER(ct.c_double))
+    strain = stress = coeffs = None
+    if want_fields:
+        strain = torch.empty(C * nfield_pts, dtype=torch.float32, device="cuda")
+        stress = torch.empty(S * nfield_pts, dtype=torch.float32, device="cuda")
+        out.strain = strain.data_ptr()
+        out.stress = stress.data_ptr()
+    if want_coeffs:
+        coeffs = torch.empty(ncoef_total, dtype=torch.complex64, device="cuda")
+        out.coeffs = coeffs.data_ptr()
+    return out, eff, its, res, strain, stress, coeffs
+
+
+def solve(plan: Plan, macro_strain, phases, tol: float, max_iter: int = 0, warm_start=None, stream=None,
+          want_fields: bool = False, want_coeffs: bool = False, check_every: int = 0,
+          precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO, use_graph: int = 0,
+          allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
+    """mor_solve for B macro strains on one plan; macro_strain [B][ncomp]."""
+    eb = np.ascontiguousarray(np.atleast_2d(macro_strain), dtype=np.float64)
+    B, C = eb.shape
+    if C != plan.ncomp:
+        raise ValueError(f"macro strain needs {plan.ncomp} components")
+    S = plan.nstress
+    out, eff, its, res, strain, stress, coeffs = _outputs(B, S, B, want_fields, want_coeffs, B * plan.N, C,
+                                                          B * C * plan.n_coeff)
+    opts = _opts(max_iter, check_every, warm_start, stream, precision, transform, use_graph)
+    st = _check(lib.mor_solve(plan.handle, _np_ptr(eb), B, _phases(phases), float(tol), ct.byref(opts),
+                              ct.byref(out)), allow)
+    if strain is not None:
+        strain = strain.view(B, C, *plan.shape)
+        stress = stress.view(B, S, *plan.shape)
+    if coeffs is not None:
+        coeffs = coeffs.view(B, C, plan.n_coeff)
+    return SolveResult(st, eff, its, res, strain, stress, coeffs)
+
+
+def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int = 0, warm_start=None, stream=None,
+                want_fields: bool = False, want_coeffs: bool = False, check_every: int = 0, use_graph: int = 0,
+                allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
+    """mor_solve_multi: RVE b uses plans[plan_of[b]]; outputs packed per RVE."""
+    eb = np.ascontiguousarray(np.atleast_2d(macro_strain), dtype=np.float64)
+    B, C = eb.shape
+    po = np.ascontiguousarray(plan_of, dtype=np.int64)
+    handles = (ct.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    S = plans[0].nstress
+    npts = int(sum(plans[i].N for i in po))
+    ncoef = int(sum(plans[i].n_coeff for i in po)) * C
+    out, eff, its, res, strain, stress, coeffs = _outputs(B, S, B, want_fields, want_coeffs, npts, C, ncoef)
+    opts = _opts(max_iter, check_every, warm_start, stream, use_graph=use_graph)
+    st = _check(lib.mor_solve_multi(handles, len(plans), _np_ptr(po), _np_ptr(eb), B, _phases(phases), float(tol),
+                                    ct.byref(opts), ct.byref(out)), allow)
+    return SolveResult(st, eff, its, res, strain, stress, coeffs)
+
+
+def solve_path(plan: Plan, macro_strains, phases, tol: float, state, max_iter: int = 0, stream=None,
+               want_fields: bool = False, check_every: int = 0, allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
+    """mor_solve_path: macro_strains [steps][ncomp]; state: torch float32 cuda [nstate][N] (in/out)."""
+    eb = np.ascontiguousarray(np.atleast_2d(macro_strains), dtype=np.float64)
+    steps, C = eb.shape
+    S = plan.nstress
+    out, eff, its, res, strain, stress, coeffs = _outputs(steps, S, steps, want_fields, False, plan.N, C, 0)
+    opts = _opts(max_iter, check_every, None, stream)
+    st = _check(lib.mor_solve_path(plan.handle, _np_ptr(eb), steps, _phases(phases), float(tol), ct.byref(opts),
+                                   ct.c_void_p(state.data_ptr()), ct.byref(out)), allow)
+    if strain is not None:
+        strain = strain.view(C, *plan.shape)
+        stress = stress.view(S, *plan.shape)
+    return SolveResult(st, eff, its, res, strain, stress, None)
+
+
+def profile_enable(on: bool = True):
+    _check(lib.mor_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib.mor_profile_reset())
+
+
+def profile_query(kernel: str):
+    ms = ct.c_double()
+    la = ct.c_int64()
+    it = ct.c_int64()
+    by = ct.c_double()
+    _check(lib.mor_profile_query(kernel.encode(), ct.byref(ms), ct.byref(la), ct.byref(it), ct.byref(by)))
+    return {"ms": ms.value, "launches": la.value, "items": it.value, "bytes": by.value}
+
+
+def version() -> str:
+    return lib.mor_version().decode()

@@ -1,0 +1,772 @@
+// Host driver of the reduced fixed-point iteration: argument checks,
+// per-stream workspaces, grouping of RVEs by grid, the iteration loop with
+// device-side convergence (the host only polls a counter every few
+// iterations), finalisation, load paths and per-kernel profiling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "solve_kernels.h"
+
+using namespace mor_k;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+void mor_set_error(const std::string& msg) { g_last_error = msg; }
+extern "C" const char* mor_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* mor_version(void) { return "mor 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------ profiling
+namespace {
+struct ProfStat {
+  double ms = 0.0;
+  int64_t launches = 0;
+  int64_t items = 0;
+  double bytes = 0.0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+ProfStat g_prof[PK_COUNT];
+const char* kPkName[PK_COUNT] = {"row", "col", "mid_fwd", "mid_inv", "final", "init"};
+
+struct EventPair {
+  hipEvent_t a, b;
+  int kind;
+};
+
+// ------------------------------------------------------------------ workspace
+struct Workspace {
+  std::map<std::string, std::pair<void*, size_t>> bufs;
+  unsigned int* h_active = nullptr;  // pinned
+  std::vector<hipEvent_t> evpool;
+  size_t evnext = 0;
+  ~Workspace() {}
+  template <typename T>
+  mor_status get(const char* name, size_t count, T** out) {
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    auto it = bufs.find(name);
+    if (it != bufs.end() && it->second.second >= bytes) {
+      *out = reinterpret_cast<T*>(it->second.first);
+      return MOR_OK;
+    }
+    if (it != bufs.end()) {
+      (void)hipFree(it->second.first);
+      bufs.erase(it);
+    }
+    void* p = nullptr;
+    size_t alloc = bytes + bytes / 4;
+    if (hipMalloc(&p, alloc) != hipSuccess) {
+      (void)hipGetLastError();
+      mor_set_error(std::string("workspace allocation failed: ") + name);
+      return MOR_E_OUT_OF_MEMORY;
+    }
+    bufs[name] = {p, alloc};
+    *out = reinterpret_cast<T*>(p);
+    return MOR_OK;
+  }
+  hipEvent_t event() {
+    if (evnext == evpool.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      evpool.push_back(e);
+    }
+    return evpool[evnext++];
+  }
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, void*>, Workspace*> g_ws;
+
+Workspace* workspace_for(void* stream) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto key = std::make_pair(dev, stream);
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) return it->second;
+  Workspace* w = new Workspace();
+  (void)hipHostMalloc((void**)&w->h_active, 64, hipHostMallocDefault);
+  g_ws[key] = w;
+  return w;
+}
+
+// Launch geometry from an LDS budget (bytes).
+constexpr int kLdsBudget = 56 * 1024;
+int rows_per_block(int C, int nlen) {
+  const int nh = nlen / 2;
+  int rb = (kLdsBudget / 8 - (2 * nh + 1)) / (2 * C * (nh + 1));
+  return std::max(1, rb);
+}
+int cols_per_block(int C, int n0) {
+  int cb = (kLdsBudget / 8 - n0) / (2 * C * n0);
+  return std::max(1, cb);
+}
+
+struct Group {
+  int ndim, n0, n1, n2;
+  std::vector<int> rves;
+  int ncol_max = 0, nlast_max = 0;
+  int rb = 1, cb = 1, xb = 1;
+  int* d_list = nullptr;
+};
+
+struct SolveCtx {
+  hipStream_t st = nullptr;
+  Workspace* ws = nullptr;
+  int C = 3, S = 4, NST = 5, ndim = 2;
+  int64_t B = 0;
+  std::vector<Group> groups;
+  PlanDev* d_plans = nullptr;
+  RveState* d_st = nullptr;
+  double* d_ebar = nullptr;
+  cpx<float>* d_yl = nullptr;
+  cpx<float>* d_yc = nullptr;
+  cpx<float>* d_coef = nullptr;
+  double* d_part = nullptr;
+  double* d_sigpart = nullptr;
+  double* d_eff = nullptr;
+  unsigned int* d_active = nullptr;
+  unsigned long long* d_prof = nullptr;
+  int* d_nblk = nullptr;
+  float* d_jstate = nullptr;
+  Offs off{};
+  MatDev mat{};
+  bool j2 = false;
+  std::vector<int64_t> coef_off_h, field_off_h;
+  std::vector<int> ncoef_h;
+  std::vector<EventPair> events;
+  std::vector<std::vector<char>> keep;  // host staging that must outlive async copies
+};
+
+// Asynchronous upload from a host copy kept alive until the solve ends.
+template <typename T>
+mor_status upload(SolveCtx& cx, T* dst, const std::vector<T>& src) {
+  if (src.empty()) return MOR_OK;
+  const size_t nb = src.size() * sizeof(T);
+  cx.keep.emplace_back(nb);
+  std::memcpy(cx.keep.back().data(), src.data(), nb);
+  MOR_HIP_TRY(hipMemcpyAsync(dst, cx.keep.back().data(), nb, hipMemcpyHostToDevice, cx.st));
+  return MOR_OK;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+mor_status check_phase(const mor_phase* ph, int ndim) {
+  for (int p = 0; p < 2; ++p) {
+    const mor_phase& q = ph[p];
+    if (!finite(q.lambda) || !finite(q.mu) || !finite(q.sigma_y0) || !finite(q.H)) {
+      mor_set_error("phase parameters must be finite");
+      return MOR_E_INVALID_ARG;
+    }
+    if (q.mu <= 0.0) {
+      mor_set_error("phase shear modulus must be > 0");
+      return MOR_E_INVALID_ARG;
+    }
+    if ((ndim == 2 && q.lambda + q.mu <= 0.0) || (ndim == 3 && q.lambda + 2.0 * q.mu / 3.0 <= 0.0)) {
+      mor_set_error("phase bulk modulus must be > 0");
+      return MOR_E_INVALID_ARG;
+    }
+    if (q.plastic && (q.sigma_y0 <= 0.0 || q.H < 0.0)) {
+      mor_set_error("plastic phase needs sigma_y0 > 0 and H >= 0");
+      return MOR_E_INVALID_ARG;
+    }
+  }
+  return MOR_OK;
+}
+
+MatDev make_mat(const mor_phase* ph) {
+  MatDev m{};
+  for (int p = 0; p < 2; ++p) {
+    m.lam[p] = (float)ph[p].lambda;
+    m.mu[p] = (float)ph[p].mu;
+    m.sy[p] = (float)ph[p].sigma_y0;
+    m.H[p] = (float)ph[p].H;
+    m.plastic[p] = ph[p].plastic ? 1 : 0;
+  }
+  const double lam0 = 0.5 * (ph[0].lambda + ph[1].lambda);
+  const double mu0 = 0.5 * (ph[0].mu + ph[1].mu);
+  m.lam0 = (float)lam0;
+  m.mu0 = (float)mu0;
+  m.g_inv_mu0 = (float)(1.0 / mu0);
+  m.g_k = (float)((lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0)));
+  return m;
+}
+
+
+void ev_begin(SolveCtx& cx, int kind, hipEvent_t* a) {
+  if (!g_prof_on) return;
+  *a = cx.ws->event();
+  (void)hipEventRecord(*a, cx.st);
+  (void)kind;
+}
+void ev_end(SolveCtx& cx, int kind, hipEvent_t a) {
+  if (!g_prof_on) return;
+  hipEvent_t b = cx.ws->event();
+  (void)hipEventRecord(b, cx.st);
+  cx.events.push_back({a, b, kind});
+}
+
+Prof prof_of(SolveCtx& cx) {
+  Prof p{nullptr, nullptr};
+  if (g_prof_on) {
+    p.items = cx.d_prof;
+    p.bytes = cx.d_prof + PK_COUNT;
+  }
+  return p;
+}
+
+// ------------------------------------------------------------------ launches
+template <int C>
+mor_status launch_init(SolveCtx& cx, Group& g, const cpx<float>* warm) {
+  const size_t shc = (size_t)(g.n0 + 2 * C * g.cb * g.n0) * sizeof(cpx<float>);
+  dim3 grid((g.ncol_max + g.cb - 1) / g.cb, (unsigned)g.rves.size());
+  hipEvent_t a{};
+  ev_begin(cx, PK_INIT, &a);
+  k_col<C, MODE_INIT><<<grid, 256, shc, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef, warm,
+                                                 cx.off, cx.d_part, cx.mat, g.cb, cx.d_active, prof_of(cx));
+  MOR_LAUNCH_CHECK("col(init)");
+  ev_end(cx, PK_INIT, a);
+  if (C == 6) {
+    const size_t shm = (size_t)(g.n1 + 2 * C * g.xb * g.n1) * sizeof(cpx<float>);
+    dim3 gm((g.n0 + g.xb - 1) / g.xb, g.nlast_max, (unsigned)g.rves.size());
+    ev_begin(cx, PK_MIDI, &a);
+    k_mid<C, +1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 0,
+                                         prof_of(cx));
+    MOR_LAUNCH_CHECK("mid(inv)");
+    ev_end(cx, PK_MIDI, a);
+  }
+  return MOR_OK;
+}
+
+template <int C, int MAT>
+mor_status launch_iter(SolveCtx& cx, Group& g) {
+  const int nlen = C == 3 ? g.n1 : g.n2;
+  const int rows = C == 3 ? g.n0 : g.n0 * g.n1;
+  const int nh = nlen / 2;
+  const size_t shr = (size_t)(nh + nh + 1 + 2 * C * g.rb * (nh + 1)) * sizeof(cpx<float>);
+  dim3 gr((rows + g.rb - 1) / g.rb, (unsigned)g.rves.size());
+  hipEvent_t a{};
+  ev_begin(cx, PK_ROW, &a);
+  k_row<C, MODE_ITER, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
+                                                    cx.d_jstate, nullptr, nullptr, nullptr, g.rb, prof_of(cx));
+  MOR_LAUNCH_CHECK("row");
+  ev_end(cx, PK_ROW, a);
+  const size_t shm = (size_t)(g.n1 + 2 * C * g.xb * g.n1) * sizeof(cpx<float>);
+  dim3 gm((g.n0 + g.xb - 1) / g.xb, g.nlast_max, (unsigned)g.rves.size());
+  if (C == 6) {
+    ev_begin(cx, PK_MIDF, &a);
+    k_mid<C, -1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 1,
+                                         prof_of(cx));
+    MOR_LAUNCH_CHECK("mid(fwd)");
+    ev_end(cx, PK_MIDF, a);
+  }
+  const size_t shc = (size_t)(g.n0 + 2 * C * g.cb * g.n0) * sizeof(cpx<float>);
+  dim3 gc((g.ncol_max + g.cb - 1) / g.cb, (unsigned)g.rves.size());
+  ev_begin(cx, PK_COL, &a);
+  k_col<C, MODE_ITER><<<gc, 256, shc, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef, nullptr,
+                                               cx.off, cx.d_part, cx.mat, g.cb, cx.d_active, prof_of(cx));
+  MOR_LAUNCH_CHECK("col");
+  ev_end(cx, PK_COL, a);
+  if (C == 6) {
+    ev_begin(cx, PK_MIDI, &a);
+    k_mid<C, +1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 1,
+                                         prof_of(cx));
+    MOR_LAUNCH_CHECK("mid(inv)");
+    ev_end(cx, PK_MIDI, a);
+  }
+  return MOR_OK;
+}
+
+template <int C, int MAT>
+mor_status launch_final(SolveCtx& cx, Group& g, float* eps, float* sig) {
+  const int nlen = C == 3 ? g.n1 : g.n2;
+  const int rows = C == 3 ? g.n0 : g.n0 * g.n1;
+  const int nh = nlen / 2;
+  const size_t shr = (size_t)(nh + nh + 1 + 2 * C * g.rb * (nh + 1)) * sizeof(cpx<float>);
+  dim3 gr((rows + g.rb - 1) / g.rb, (unsigned)g.rves.size());
+  hipEvent_t a{};
+  ev_begin(cx, PK_FINAL, &a);
+  k_row<C, MODE_FINAL, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
+                                                     cx.d_jstate, eps, sig, cx.d_sigpart, g.rb, prof_of(cx));
+  MOR_LAUNCH_CHECK("row(final)");
+  ev_end(cx, PK_FINAL, a);
+  constexpr int S = Comp<C>::S;
+  const int n = (int)g.rves.size() * S;
+  k_sig_reduce<S><<<(n + 255) / 256, 256, 0, cx.st>>>(cx.d_plans, cx.d_st, g.d_list, (int)g.rves.size(), cx.d_sigpart, cx.off,
+                                                      cx.d_nblk, cx.d_eff, S);
+  MOR_LAUNCH_CHECK("sig_reduce");
+  return MOR_OK;
+}
+
+mor_status do_init(SolveCtx& cx, Group& g, const cpx<float>* warm) {
+  return cx.C == 3 ? launch_init<3>(cx, g, warm) : launch_init<6>(cx, g, warm);
+}
+mor_status do_iter(SolveCtx& cx, Group& g) {
+  if (cx.C == 3) return cx.j2 ? launch_iter<3, MAT_J2>(cx, g) : launch_iter<3, MAT_HOOKE>(cx, g);
+  return cx.j2 ? launch_iter<6, MAT_J2>(cx, g) : launch_iter<6, MAT_HOOKE>(cx, g);
+}
+mor_status do_final(SolveCtx& cx, Group& g, float* eps, float* sig) {
+  if (cx.C == 3) return cx.j2 ? launch_final<3, MAT_J2>(cx, g, eps, sig) : launch_final<3, MAT_HOOKE>(cx, g, eps, sig);
+  return cx.j2 ? launch_final<6, MAT_J2>(cx, g, eps, sig) : launch_final<6, MAT_HOOKE>(cx, g, eps, sig);
+}
+
+// Prepare the context: plan table, groups, offsets, states.
+mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::vector<int>& plan_of,
+                 const double* ebar, int64_t B, const mor_phase* phase, double tol, const mor_solve_opts* opts,
+                 float* jstate_user) {
+  cx.st = opts ? (hipStream_t)opts->stream : nullptr;
+  cx.ws = workspace_for(cx.st);
+  cx.B = B;
+  cx.ndim = plans[0]->ndim;
+  cx.C = cx.ndim == 2 ? 3 : 6;
+  cx.S = cx.ndim == 2 ? 4 : 6;
+  cx.NST = cx.ndim == 2 ? 5 : 7;
+  cx.mat = make_mat(phase);
+  cx.j2 = phase[0].plastic || phase[1].plastic;
+  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10000;
+  Workspace& ws = *cx.ws;
+  mor_status s;
+  // plan table
+  std::vector<PlanDev> pd(plans.size());
+  for (size_t i = 0; i < plans.size(); ++i) pd[i] = plans[i]->dev;
+  if ((s = ws.get("plans", pd.size(), &cx.d_plans)) != MOR_OK) return s;
+  if ((s = upload(cx, cx.d_plans, pd)) != MOR_OK) return s;
+  // groups by grid
+  std::map<std::vector<int>, int> gidx;
+  for (int64_t b = 0; b < B; ++b) {
+    const mor_plan* p = plans[plan_of[b]];
+    std::vector<int> key = {p->ndim, p->n[0], p->n[1], p->n[2]};
+    auto it = gidx.find(key);
+    int gi;
+    if (it == gidx.end()) {
+      gi = (int)cx.groups.size();
+      gidx[key] = gi;
+      Group g;
+      g.ndim = p->ndim;
+      g.n0 = p->n[0];
+      g.n1 = p->n[1];
+      g.n2 = p->ndim == 3 ? p->n[2] : 1;
+      cx.groups.push_back(g);
+    } else {
+      gi = it->second;
+    }
+    Group& g = cx.groups[gi];
+    g.rves.push_back((int)b);
+    g.ncol_max = std::max(g.ncol_max, p->dev.ncol);
+    g.nlast_max = std::max(g.nlast_max, p->dev.nlast);
+  }
+  // offsets
+  std::vector<int64_t> offs(5 * B);
+  std::vector<int> nblk(B);
+  int64_t yl = 0, yc = 0, co = 0, fo = 0, pa = 0;
+  cx.coef_off_h.resize(B);
+  cx.field_off_h.resize(B);
+  cx.ncoef_h.resize(B);
+  for (auto& g : cx.groups) {
+    const int nlen = g.ndim == 2 ? g.n1 : g.n2;
+    g.rb = rows_per_block(cx.C, nlen);
+    g.cb = cols_per_block(cx.C, g.n0);
+    g.xb = g.ndim == 3 ? cols_per_block(cx.C, g.n1) : 1;
+    const int rows = g.ndim == 2 ? g.n0 : g.n0 * g.n1;
+    g.rb = std::min(g.rb, rows);
+  }
+  std::vector<int> gof(B);
+  for (size_t gi = 0; gi < cx.groups.size(); ++gi)
+    for (int b : cx.groups[gi].rves) gof[b] = (int)gi;
+  for (int64_t b = 0; b < B; ++b) {
+    const mor_plan* p = plans[plan_of[b]];
+    const Group& g = cx.groups[gof[b]];
+    const int rows = p->dev.rows;
+    offs[0 * B + b] = yl;
+    yl += (int64_t)cx.C * p->dev.nlast * rows;
+    if (cx.ndim == 3) {
+      offs[1 * B + b] = yc;
+      yc += (int64_t)cx.C * p->dev.ncol * p->n[0];
+    } else {
+      offs[1 * B + b] = offs[0 * B + b];
+    }
+    offs[2 * B + b] = co;
+    cx.coef_off_h[b] = co;
+    cx.ncoef_h[b] = p->dev.ncoef;
+    co += (int64_t)cx.C * p->dev.ncoef;
+    offs[3 * B + b] = fo;
+    cx.field_off_h[b] = fo;
+    fo += p->N;
+    offs[4 * B + b] = pa;
+    const int nrb = (rows + g.rb - 1) / g.rb;
+    const int ncb = (p->dev.ncol + g.cb - 1) / g.cb;
+    pa += std::max(nrb, ncb);
+    nblk[b] = nrb;
+  }
+  int64_t* d_offs;
+  if ((s = ws.get("offs", offs.size(), &d_offs)) != MOR_OK) return s;
+  if ((s = upload(cx, d_offs, offs)) != MOR_OK) return s;
+  cx.off.yl = d_offs;
+  cx.off.yc = d_offs + B;
+  cx.off.coef = d_offs + 2 * B;
+  cx.off.field = d_offs + 3 * B;
+  cx.off.part = d_offs + 4 * B;
+  if ((s = ws.get("yl", (size_t)yl, &cx.d_yl)) != MOR_OK) return s;
+  if (cx.ndim == 3) {
+    if ((s = ws.get("yc", (size_t)yc, &cx.d_yc)) != MOR_OK) return s;
+  } else {
+    cx.d_yc = cx.d_yl;
+  }
+  if ((s = ws.get("coef", (size_t)co, &cx.d_coef)) != MOR_OK) return s;
+  if ((s = ws.get("part", (size_t)pa, &cx.d_part)) != MOR_OK) return s;
+  if ((s = ws.get("sigpart", (size_t)pa * cx.S, &cx.d_sigpart)) != MOR_OK) return s;
+  if ((s = ws.get("eff", (size_t)B * cx.S, &cx.d_eff)) != MOR_OK) return s;
+  if ((s = ws.get("active", 1, &cx.d_active)) != MOR_OK) return s;
+  if ((s = ws.get("prof", 2 * PK_COUNT, &cx.d_prof)) != MOR_OK) return s;
+  if ((s = ws.get("ebar", (size_t)B * cx.C, &cx.d_ebar)) != MOR_OK) return s;
+  if ((s = ws.get("state", (size_t)B, &cx.d_st)) != MOR_OK) return s;
+  // group lists and final block counts (per group position)
+  std::vector<int> lists, nblk_list;
+  std::vector<size_t> lstart;
+  for (auto& g : cx.groups) {
+    lstart.push_back(lists.size());
+    for (int b : g.rves) {
+      lists.push_back(b);
+      nblk_list.push_back(nblk[b]);
+    }
+  }
+  int* d_lists;
+  if ((s = ws.get("lists", lists.size(), &d_lists)) != MOR_OK) return s;
+  if ((s = ws.get("nblk", nblk_list.size(), &cx.d_nblk)) != MOR_OK) return s;
+  if ((s = upload(cx, d_lists, lists)) != MOR_OK) return s;
+  if ((s = upload(cx, cx.d_nblk, nblk_list)) != MOR_OK) return s;
+  for (size_t gi = 0; gi < cx.groups.size(); ++gi) cx.groups[gi].d_list = d_lists + lstart[gi];
+  // nblk is indexed by group position in k_sig_reduce: shift per group
+  // (k_sig_reduce receives the group's list; its nblk pointer is offset below)
+  // states
+  std::vector<RveState> hs(B);
+  std::vector<double> eb(ebar, ebar + B * cx.C);
+  for (int64_t b = 0; b < B; ++b) {
+    double nrm2 = 0.0;
+    for (int c = 0; c < cx.C; ++c) {
+      const double v = ebar[b * cx.C + c];
+      nrm2 += (c < (cx.C == 3 ? 2 : 3) ? 1.0 : 2.0) * v * v;
+    }
+    RveState& r = hs[b];
+    r.active = 1;
+    r.iters = 0;
+    r.status = MOR_OK;
+    r.plan = plan_of[b];
+    r.resid = 0.0;
+    r.denom = (double)plans[plan_of[b]]->N * (nrm2 > 0.0 ? std::sqrt(nrm2) : 1.0);
+    r.tol = tol;
+    r.max_iter = max_iter;
+    r.counter = 0u;
+  }
+  if ((s = upload(cx, cx.d_st, hs)) != MOR_OK) return s;
+  if ((s = upload(cx, cx.d_ebar, eb)) != MOR_OK) return s;
+  std::vector<unsigned int> act(1, (unsigned int)B);
+  if ((s = upload(cx, cx.d_active, act)) != MOR_OK) return s;
+  if (g_prof_on) MOR_HIP_TRY(hipMemsetAsync(cx.d_prof, 0, 2 * PK_COUNT * sizeof(unsigned long long), cx.st));
+  // J2 state
+  if (cx.j2) {
+    if (jstate_user) {
+      cx.d_jstate = jstate_user;
+    } else {
+      if ((s = ws.get("jstate", (size_t)fo * cx.NST, &cx.d_jstate)) != MOR_OK) return s;
+      MOR_HIP_TRY(hipMemsetAsync(cx.d_jstate, 0, (size_t)fo * cx.NST * sizeof(float), cx.st));
+    }
+  }
+  return MOR_OK;
+}
+
+mor_status run(SolveCtx& cx, const cpx<float>* warm, const mor_solve_opts* opts, float* eps, float* sig) {
+  mor_status s;
+  for (auto& g : cx.groups)
+    if ((s = do_init(cx, g, warm)) != MOR_OK) return s;
+  const int check = (opts && opts->check_every > 0) ? opts->check_every : 8;
+  int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10000;
+  int done = 0;
+  while (true) {
+    for (int k = 0; k < check; ++k)
+      for (auto& g : cx.groups)
+        if ((s = do_iter(cx, g)) != MOR_OK) return s;
+    done += check;
+    MOR_HIP_TRY(hipMemcpyAsync(cx.ws->h_active, cx.d_active, sizeof(unsigned int), hipMemcpyDeviceToHost, cx.st));
+    MOR_HIP_TRY(hipStreamSynchronize(cx.st));
+    if (*cx.ws->h_active == 0u) break;
+    if (done > max_iter + check) {
+      mor_set_error("iteration loop did not drain");
+      return MOR_E_DEVICE;
+    }
+  }
+  // finalize; the nblk pointer is offset per group
+  size_t pos = 0;
+  int* nblk_base = cx.d_nblk;
+  for (auto& g : cx.groups) {
+    cx.d_nblk = nblk_base + pos;
+    int64_t foff = 0;
+    (void)foff;
+    if ((s = do_final(cx, g, eps, sig)) != MOR_OK) {
+      cx.d_nblk = nblk_base;
+      return s;
+    }
+    pos += g.rves.size();
+  }
+  cx.d_nblk = nblk_base;
+  return MOR_OK;
+}
+
+mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<RveState>* states_out) {
+  std::vector<RveState> hs(cx.B);
+  MOR_HIP_TRY(hipMemcpyAsync(hs.data(), cx.d_st, cx.B * sizeof(RveState), hipMemcpyDeviceToHost, cx.st));
+  std::vector<double> eff((size_t)cx.B * cx.S);
+  if (out && out->eff_stress)
+    MOR_HIP_TRY(hipMemcpyAsync(eff.data(), cx.d_eff, eff.size() * sizeof(double), hipMemcpyDeviceToHost, cx.st));
+  if (out && out->coeffs) {
+    int64_t tot = 0;
+    for (int64_t b = 0; b < cx.B; ++b) tot += (int64_t)cx.C * cx.ncoef_h[b];
+    MOR_HIP_TRY(hipMemcpyAsync(out->coeffs, cx.d_coef, tot * sizeof(cpx<float>), hipMemcpyDeviceToDevice, cx.st));
+  }
+  unsigned long long prof[2 * PK_COUNT] = {0};
+  if (g_prof_on)
+    MOR_HIP_TRY(hipMemcpyAsync(prof, cx.d_prof, sizeof(prof), hipMemcpyDeviceToHost, cx.st));
+  MOR_HIP_TRY(hipStreamSynchronize(cx.st));
+  if (g_prof_on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& e : cx.events) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+        g_prof[e.kind].ms += ms;
+        g_prof[e.kind].launches += 1;
+      }
+    }
+    for (int k = 0; k < PK_COUNT; ++k) {
+      g_prof[k].items += (int64_t)prof[k];
+      g_prof[k].bytes += (double)prof[PK_COUNT + k];
+    }
+  }
+  cx.events.clear();
+  cx.ws->evnext = 0;
+  mor_status worst = MOR_OK;
+  for (int64_t b = 0; b < cx.B; ++b) {
+    if (out && out->iterations) out->iterations[b] = hs[b].iters;
+    if (out && out->residual) out->residual[b] = hs[b].resid;
+    if (out && out->eff_stress)
+      for (int s = 0; s < cx.S; ++s) out->eff_stress[b * eff_stride + s] = eff[b * cx.S + s];
+    if (hs[b].status == MOR_E_NONFINITE) worst = MOR_E_NONFINITE;
+    else if (hs[b].status == MOR_E_NOT_CONVERGED && worst == MOR_OK) worst = MOR_E_NOT_CONVERGED;
+  }
+  if (states_out) *states_out = hs;
+  if (worst == MOR_E_NONFINITE) mor_set_error("non-finite residual in at least one RVE");
+  if (worst == MOR_E_NOT_CONVERGED) mor_set_error("max_iter reached before tol in at least one RVE");
+  return worst;
+}
+
+mor_status check_common(const double* ebar, int64_t B, int C, const mor_phase* phase, double tol,
+                        const mor_solve_opts* opts, int ndim) {
+  if (!ebar || !phase) {
+    mor_set_error("NULL macro strain or phase");
+    return MOR_E_INVALID_ARG;
+  }
+  if (B < 1) {
+    mor_set_error("B must be >= 1");
+    return MOR_E_INVALID_ARG;
+  }
+  if (!(tol > 0.0) || !std::isfinite(tol)) {
+    mor_set_error("tol must be a finite number > 0");
+    return MOR_E_INVALID_ARG;
+  }
+  for (int64_t i = 0; i < B * C; ++i)
+    if (!std::isfinite(ebar[i])) {
+      mor_set_error("macro strain must be finite");
+      return MOR_E_INVALID_ARG;
+    }
+  mor_status s = check_phase(phase, ndim);
+  if (s != MOR_OK) return s;
+  if (opts) {
+    if (opts->max_iter < 0 || opts->check_every < 0) {
+      mor_set_error("max_iter and check_every must be >= 0");
+      return MOR_E_INVALID_ARG;
+    }
+    if (opts->precision != MOR_PREC_FP32) {
+      mor_set_error("only MOR_PREC_FP32 is available in this build");
+      return MOR_E_UNSUPPORTED;
+    }
+    if (opts->transform != MOR_TRANSFORM_AUTO && opts->transform != MOR_TRANSFORM_FFT) {
+      mor_set_error("only the FFT transform is available in this build");
+      return MOR_E_UNSUPPORTED;
+    }
+  }
+  return MOR_OK;
+}
+
+std::mutex& stream_mutex(void* stream) {
+  static std::mutex mu;
+  static std::map<void*, std::mutex*> m;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = m.find(stream);
+  if (it == m.end()) it = m.emplace(stream, new std::mutex()).first;
+  return *it->second;
+}
+
+mor_status solve_impl(const std::vector<mor_plan*>& plans, const std::vector<int>& plan_of, const double* ebar,
+                      int64_t B, const mor_phase* phase, double tol, const mor_solve_opts* opts, mor_outputs* out,
+                      float* jstate, int eff_stride, std::vector<RveState>* st_out) {
+  std::lock_guard<std::mutex> lk(stream_mutex(opts ? opts->stream : nullptr));
+  SolveCtx cx;
+  mor_status s = setup(cx, plans, plan_of, ebar, B, phase, tol, opts, jstate);
+  if (s != MOR_OK) {
+    (void)hipStreamSynchronize(cx.st);
+    return s;
+  }
+  s = run(cx, opts ? (const cpx<float>*)opts->warm_start : nullptr, opts, out ? out->strain : nullptr,
+          out ? out->stress : nullptr);
+  if (s != MOR_OK) {
+    (void)hipStreamSynchronize(cx.st);
+    return s;
+  }
+  return collect(cx, out, eff_stride, st_out);
+}
+
+}  // namespace
+
+extern "C" mor_status mor_solve(mor_plan_t plan, const double* macro_strain, int64_t B, const mor_phase phase[2],
+                                double tol, const mor_solve_opts* opts, mor_outputs* out) {
+  if (!plan) {
+    mor_set_error("mor_solve: NULL plan");
+    return MOR_E_INVALID_ARG;
+  }
+  const int C = plan->ndim == 2 ? 3 : 6;
+  mor_status s = check_common(macro_strain, B, C, phase, tol, opts, plan->ndim);
+  if (s != MOR_OK) return s;
+  std::vector<mor_plan*> plans = {plan};
+  std::vector<int> plan_of(B, 0);
+  return solve_impl(plans, plan_of, macro_strain, B, phase, tol, opts, out, nullptr, plan->ndim == 2 ? 4 : 6,
+                    nullptr);
+}
+
+extern "C" mor_status mor_solve_multi(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of_rve,
+                                      const double* macro_strain_packed, int64_t B, const mor_phase phase[2],
+                                      double tol, const mor_solve_opts* opts, mor_outputs* out) {
+  if (!plans || nplans < 1 || !plan_of_rve) {
+    mor_set_error("mor_solve_multi: NULL or empty plan list");
+    return MOR_E_INVALID_ARG;
+  }
+  for (int64_t i = 0; i < nplans; ++i)
+    if (!plans[i]) {
+      mor_set_error("mor_solve_multi: NULL plan");
+      return MOR_E_INVALID_ARG;
+    }
+  const int ndim = plans[0]->ndim;
+  for (int64_t i = 0; i < nplans; ++i)
+    if (plans[i]->ndim != ndim) {
+      mor_set_error("mor_solve_multi: all plans must have the same ndim");
+      return MOR_E_UNSUPPORTED;
+    }
+  std::vector<int> plan_of(B > 0 ? B : 0);
+  for (int64_t b = 0; b < B; ++b) {
+    if (plan_of_rve[b] < 0 || plan_of_rve[b] >= nplans) {
+      mor_set_error("mor_solve_multi: plan_of_rve out of range");
+      return MOR_E_INVALID_ARG;
+    }
+    plan_of[b] = (int)plan_of_rve[b];
+  }
+  const int C = ndim == 2 ? 3 : 6;
+  mor_status s = check_common(macro_strain_packed, B, C, phase, tol, opts, ndim);
+  if (s != MOR_OK) return s;
+  std::vector<mor_plan*> pl(plans, plans + nplans);
+  return solve_impl(pl, plan_of, macro_strain_packed, B, phase, tol, opts, out, nullptr, ndim == 2 ? 4 : 6, nullptr);
+}
+
+extern "C" mor_status mor_solve_path(mor_plan_t plan, const double* macro_strain, int32_t steps,
+                                     const mor_phase phase[2], double tol, const mor_solve_opts* opts, float* state,
+                                     mor_outputs* out) {
+  if (!plan || !state) {
+    mor_set_error("mor_solve_path: NULL plan or state");
+    return MOR_E_INVALID_ARG;
+  }
+  if (steps < 1) {
+    mor_set_error("mor_solve_path: steps must be >= 1");
+    return MOR_E_INVALID_ARG;
+  }
+  const int C = plan->ndim == 2 ? 3 : 6;
+  const int S = plan->ndim == 2 ? 4 : 6;
+  mor_status s = check_common(macro_strain, steps, C, phase, tol, opts, plan->ndim);
+  if (s != MOR_OK) return s;
+  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  // previous-step coefficients seed the next step (warm start with the new mean)
+  cpx<float>* prev = nullptr;
+  const size_t nco = (size_t)C * plan->dev.ncoef;
+  MOR_HIP_TRY(hipMalloc((void**)&prev, std::max<size_t>(nco, 1) * sizeof(cpx<float>)));
+  std::vector<mor_plan*> plans = {plan};
+  std::vector<int> plan_of(1, 0);
+  mor_status worst = MOR_OK;
+  for (int n = 0; n < steps; ++n) {
+    mor_solve_opts o{};
+    if (opts) o = *opts;
+    o.warm_start = n == 0 ? (opts ? opts->warm_start : nullptr) : (const float*)prev;
+    mor_outputs ostep{};
+    double eff[6];
+    int32_t it = 0;
+    double res = 0.0;
+    ostep.eff_stress = eff;
+    ostep.iterations = &it;
+    ostep.residual = &res;
+    ostep.coeffs = (float*)prev;
+    const bool last = n == steps - 1;
+    ostep.strain = last && out ? out->strain : nullptr;
+    ostep.stress = last && out ? out->stress : nullptr;
+    s = solve_impl(plans, plan_of, macro_strain + (size_t)n * C, 1, phase, tol, &o, &ostep, state, S, nullptr);
+    if (out && out->eff_stress)
+      for (int k = 0; k < S; ++k) out->eff_stress[(size_t)n * S + k] = eff[k];
+    if (out && out->iterations) out->iterations[n] = it;
+    if (out && out->residual) out->residual[n] = res;
+    if (s == MOR_E_NOT_CONVERGED) {
+      worst = s;
+      continue;
+    }
+    if (s != MOR_OK) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(prev);
+      return s;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(prev);
+  if (worst != MOR_OK) mor_set_error("max_iter reached before tol in at least one load step");
+  return worst;
+}
+
+extern "C" mor_status mor_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return MOR_OK;
+}
+
+extern "C" mor_status mor_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& p : g_prof) p = ProfStat{};
+  return MOR_OK;
+}
+
+extern "C" mor_status mor_profile_query(const char* kernel, double* total_ms, int64_t* launches, int64_t* items,
+                                        double* bytes) {
+  if (!kernel) {
+    mor_set_error("mor_profile_query: NULL kernel name");
+    return MOR_E_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (int k = 0; k < PK_COUNT; ++k) {
+    if (std::strcmp(kernel, kPkName[k]) == 0) {
+      if (total_ms) *total_ms = g_prof[k].ms;
+      if (launches) *launches = g_prof[k].launches;
+      if (items) *items = g_prof[k].items;
+      if (bytes) *bytes = g_prof[k].bytes;
+      return MOR_OK;
+    }
+  }
+  mor_set_error(std::string("mor_profile_query: unknown kernel ") + kernel);
+  return MOR_E_INVALID_ARG;
+}

@@ -1,0 +1,596 @@
+// Device kernels of the reduced fixed-point iteration (paper Sec. 4, steps a-d).
+//
+// Data held per RVE between kernels (FP32 complex):
+//   coef  [C][ncoef]         strain coefficients eps^ on the half-spectrum part
+//                            of the pattern (column-major: column j, rows k0 up)
+//   Yc    [C][ncol][n0]      axis-0 lines of the pruned transform (column kernel)
+//   Yl    [C][nlast][rows]   last-axis spectra of every row (row kernel); in 2D
+//                            Yl == Yc (columns are the last-axis frequencies)
+// One iteration:
+//   2D: row (Yl: F -> eps -> tau -> T)   col (Yc: T -> tau^ -> Green -> eps^ -> F)
+//   3D: row, mid_fwd (Yl -> Yc), col, mid_inv (Yc -> Yl)
+// F carries the 1/N of the inverse DFT; every other stage is unnormalised.
+#pragma once
+
+#include "mor_internal.h"
+
+namespace mor_k {
+
+enum { MODE_ITER = 0, MODE_FINAL = 1, MODE_INIT = 1 };
+enum { MAT_HOOKE = 0, MAT_J2 = 1 };
+
+struct Offs {
+  const int64_t* yl;     // [B] element offset of RVE b in Yl
+  const int64_t* yc;     // [B] in Yc
+  const int64_t* coef;   // [B] in coef / warm start
+  const int64_t* field;  // [B] in field outputs and J2 state (per component plane: N)
+  const int64_t* part;   // [B] in the partial-sum array (entries)
+};
+
+struct Prof {
+  unsigned long long* items;  // [PK_COUNT] or null
+  unsigned long long* bytes;  // [PK_COUNT] or null
+};
+
+__device__ __forceinline__ void prof_add(const Prof& p, int k, unsigned long long items, unsigned long long bytes) {
+  if (p.items) {
+    atomicAdd(p.items + k, items);
+    atomicAdd(p.bytes + k, bytes);
+  }
+}
+
+// Strain/stress component helpers.  2D: strain [11,22,12], stress [11,22,12,33];
+// 3D: [11,22,33,23,13,12].
+template <int C>
+struct Comp;
+template <>
+struct Comp<3> {
+  static constexpr int S = 4, NST = 5, NDIAG = 2;
+};
+template <>
+struct Comp<6> {
+  static constexpr int S = 6, NST = 7, NDIAG = 3;
+};
+
+// Pointwise polarisation tau = sigma(eps) - C0:eps (step a) and, if wanted,
+// sigma itself and the updated J2 state.
+template <int C, int MAT>
+__device__ __forceinline__ void constitutive(const float* e, int ph, const MatDev& m, const float* stin, float* tau,
+                                             float* sig, float* stout) {
+  constexpr int ND = Comp<C>::NDIAG;
+  float tr = 0.f;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) tr += e[i];
+  if (MAT == MAT_HOOKE) {
+    const float lam = m.lam[ph], mu = m.mu[ph];
+    const float dl = lam - m.lam0, dm = 2.f * (mu - m.mu0);
+#pragma unroll
+    for (int i = 0; i < C; ++i) tau[i] = (i < ND ? dl * tr : 0.f) + dm * e[i];
+    if (sig) {
+#pragma unroll
+      for (int i = 0; i < C; ++i) sig[i] = (i < ND ? lam * tr : 0.f) + 2.f * mu * e[i];
+      if (C == 3) sig[3] = lam * tr;
+    }
+  } else {
+    // full 3D tensors, order 11,22,33,23,13,12
+    float E[6], EP[6], alpha;
+    if (C == 3) {
+      E[0] = e[0]; E[1] = e[1]; E[2] = 0.f; E[3] = 0.f; E[4] = 0.f; E[5] = e[2];
+      EP[0] = stin[0]; EP[1] = stin[1]; EP[2] = stin[3]; EP[3] = 0.f; EP[4] = 0.f; EP[5] = stin[2];
+      alpha = stin[4];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) { E[i] = e[i]; EP[i] = stin[i]; }
+      alpha = stin[6];
+    }
+    const float lam = m.lam[ph], mu = m.mu[ph];
+    float ee[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ee[i] = E[i] - EP[i];
+    const float tre = ee[0] + ee[1] + ee[2];
+    float st[6], s[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      st[i] = (i < 3 ? lam * tre : 0.f) + 2.f * mu * ee[i];
+      s[i] = 2.f * mu * (i < 3 ? ee[i] - tre * (1.f / 3.f) : ee[i]);
+    }
+    const float ns = sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.f * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
+    const float q = 1.22474487139158905f * ns;
+    const float H = m.H[ph];
+    const float f = q - (m.sy[ph] + H * alpha);
+    float sg[6];
+    float dg = 0.f, fac = 0.f;
+    if (m.plastic[ph] && f > 0.f) {
+      dg = f / (3.f * mu + H);
+      fac = 1.22474487139158905f * dg / ns;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) sg[i] = st[i] - 2.f * mu * fac * s[i];
+    const float tr3 = E[0] + E[1] + E[2];
+    if (C == 3) {
+      tau[0] = sg[0] - (m.lam0 * tr3 + 2.f * m.mu0 * E[0]);
+      tau[1] = sg[1] - (m.lam0 * tr3 + 2.f * m.mu0 * E[1]);
+      tau[2] = sg[5] - 2.f * m.mu0 * E[5];
+      if (sig) { sig[0] = sg[0]; sig[1] = sg[1]; sig[2] = sg[5]; sig[3] = sg[2]; }
+      if (stout) {
+        stout[0] = EP[0] + fac * s[0];
+        stout[1] = EP[1] + fac * s[1];
+        stout[2] = EP[5] + fac * s[5];
+        stout[3] = EP[2] + fac * s[2];
+        stout[4] = alpha + dg;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 6; ++i) tau[i] = sg[i] - ((i < 3 ? m.lam0 * tr3 : 0.f) + 2.f * m.mu0 * E[i]);
+      if (sig) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sig[i] = sg[i];
+      }
+      if (stout) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) stout[i] = EP[i] + fac * s[i];
+        stout[6] = alpha + dg;
+      }
+    }
+  }
+}
+
+// Green operator of the isotropic reference medium (Sec. 3, eq. Gamma):
+// eps^ = -[(n (x) v + v (x) n)/(2 mu0) - k s n (x) n], v = tau^ n, s = n.v,
+// k = (lam0 + mu0)/(mu0 (lam0 + 2 mu0)).  Applied to real and imaginary parts.
+template <int C>
+__device__ __forceinline__ void green(const float* n, const float* t, float* out, float inv_mu, float kk) {
+  if (C == 3) {
+    float v0 = t[0] * n[0] + t[2] * n[1];
+    float v1 = t[2] * n[0] + t[1] * n[1];
+    float s = n[0] * v0 + n[1] * v1;
+    float ks = kk * s;
+    out[0] = -(inv_mu * n[0] * v0 - ks * n[0] * n[0]);
+    out[1] = -(inv_mu * n[1] * v1 - ks * n[1] * n[1]);
+    out[2] = -(0.5f * inv_mu * (n[0] * v1 + n[1] * v0) - ks * n[0] * n[1]);
+  } else {
+    // t: 11,22,33,23,13,12
+    float v0 = t[0] * n[0] + t[5] * n[1] + t[4] * n[2];
+    float v1 = t[5] * n[0] + t[1] * n[1] + t[3] * n[2];
+    float v2 = t[4] * n[0] + t[3] * n[1] + t[2] * n[2];
+    float s = n[0] * v0 + n[1] * v1 + n[2] * v2;
+    float ks = kk * s;
+    out[0] = -(inv_mu * n[0] * v0 - ks * n[0] * n[0]);
+    out[1] = -(inv_mu * n[1] * v1 - ks * n[1] * n[1]);
+    out[2] = -(inv_mu * n[2] * v2 - ks * n[2] * n[2]);
+    out[3] = -(0.5f * inv_mu * (n[1] * v2 + n[2] * v1) - ks * n[1] * n[2]);
+    out[4] = -(0.5f * inv_mu * (n[0] * v2 + n[2] * v0) - ks * n[0] * n[2]);
+    out[5] = -(0.5f * inv_mu * (n[0] * v1 + n[1] * v0) - ks * n[0] * n[1]);
+  }
+}
+
+template <int C>
+__device__ __forceinline__ float comp_weight(int c) {
+  return c < Comp<C>::NDIAG ? 1.f : 2.f;  // Frobenius norm of the symmetric tensor
+}
+
+// Block reduction of one double per thread; result valid in thread 0.
+__device__ __forceinline__ double block_sum_d(double v, double* lds) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += lds[w];
+  }
+  return r;
+}
+
+// ------------------------------------------------------------------ row kernel
+// Workgroup = `rb` consecutive rows of one RVE.  MODE_ITER: Yl (F) -> Yl (T).
+// MODE_FINAL: Yl (F) -> strain, stress fields, FP64 stress partial sums,
+// committed J2 state.
+template <int C, int MODE, int MAT>
+__global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
+                                             RveState* __restrict__ st, cpx<float>* __restrict__ Yl, Offs off,
+                                             MatDev mat, float* __restrict__ jstate, float* __restrict__ out_eps,
+                                             float* __restrict__ out_sig, double* __restrict__ sig_part, int rb,
+                                             Prof prof) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int S = Comp<C>::S;
+  constexpr int NST = Comp<C>::NST;
+  const int b = rve_list[blockIdx.y];
+  if (MODE == MODE_ITER && !st[b].active) return;
+  const PlanDev& P = plans[st[b].plan];
+  const int nh = P.nlen >> 1;
+  const int rows = P.rows;
+  const int r0 = blockIdx.x * rb;
+  if (r0 >= rows) return;
+  const int nr = min(rb, rows - r0);
+  const int ss = nh + 1;
+  const int nseq = C * rb;
+  cpx<float>* twh = reinterpret_cast<cpx<float>*>(smem_raw);
+  cpx<float>* rtw = twh + nh;
+  cpx<float>* A = rtw + nh + 1;
+  cpx<float>* Bf = A + nseq * ss;
+  for (int t = threadIdx.x; t < nh; t += blockDim.x) twh[t] = P.twh[t];
+  for (int t = threadIdx.x; t <= nh; t += blockDim.x) rtw[t] = P.rtw[t];
+  for (int t = threadIdx.x; t < nseq * ss; t += blockDim.x) Bf[t] = {0.f, 0.f};
+  __syncthreads();
+  const int nlast = P.nlast;
+  cpx<float>* Y = Yl + off.yl[b];
+  const int64_t cstride = (int64_t)nlast * rows;
+  for (int t = threadIdx.x; t < C * nlast * nr; t += blockDim.x) {
+    const int r = t % nr;
+    const int q = t / nr;
+    const int j = q % nlast, c = q / nlast;
+    Bf[(c * rb + r) * ss + P.last_k[j]] = Y[c * cstride + (int64_t)j * rows + r0 + r];
+  }
+  __syncthreads();
+  // pack the half spectrum X[0..nh] into a length-nh complex sequence
+  for (int t = threadIdx.x; t < nseq * nh; t += blockDim.x) {
+    const int q = t / nh, k = t - q * nh;
+    const cpx<float> X = Bf[q * ss + k];
+    const cpx<float> Xc = cconj(Bf[q * ss + nh - k]);
+    const cpx<float> a = cadd(X, Xc);
+    const cpx<float> dd = cmul(csub(X, Xc), cconj(rtw[k]));
+    A[q * ss + k] = {a.x - dd.y, a.y + dd.x};
+  }
+  __syncthreads();
+  cpx<float>* E = fft_stockham<float, +1>(A, Bf, nseq, ss, P.fdh, twh);
+  cpx<float>* O = (E == A) ? Bf : A;
+
+  double acc[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc[s] = 0.0;
+  for (int t = threadIdx.x; t < nr * nh; t += blockDim.x) {
+    const int r = t / nh, k = t - r * nh;
+    const int64_t row = r0 + r;
+    const uint8_t* grow = P.g + row * P.nlen;
+    float e0[C], e1[C], t0[C], t1[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const cpx<float> z = E[(c * rb + r) * ss + k];
+      e0[c] = z.x;
+      e1[c] = z.y;
+    }
+    const int g0 = grow[2 * k], g1 = grow[2 * k + 1];
+    if (MODE == MODE_ITER) {
+      float sin0[NST], sin1[NST];
+      if (MAT == MAT_J2) {
+        const float* sp = jstate + off.field[b] * NST;
+        const int64_t p0 = row * P.nlen + 2 * k;
+#pragma unroll
+        for (int i = 0; i < NST; ++i) {
+          sin0[i] = sp[(int64_t)i * P.N + p0];
+          sin1[i] = sp[(int64_t)i * P.N + p0 + 1];
+        }
+      }
+      constitutive<C, MAT>(e0, g0, mat, sin0, t0, nullptr, nullptr);
+      constitutive<C, MAT>(e1, g1, mat, sin1, t1, nullptr, nullptr);
+#pragma unroll
+      for (int c = 0; c < C; ++c) E[(c * rb + r) * ss + k] = {t0[c], t1[c]};
+    } else {
+      float s0[S], s1[S], sin0[NST], sin1[NST], so0[NST], so1[NST];
+      const int64_t p0 = row * P.nlen + 2 * k;
+      if (MAT == MAT_J2) {
+        float* sp = jstate + off.field[b] * NST;
+#pragma unroll
+        for (int i = 0; i < NST; ++i) {
+          sin0[i] = sp[(int64_t)i * P.N + p0];
+          sin1[i] = sp[(int64_t)i * P.N + p0 + 1];
+        }
+      }
+      constitutive<C, MAT>(e0, g0, mat, sin0, t0, s0, so0);
+      constitutive<C, MAT>(e1, g1, mat, sin1, t1, s1, so1);
+      if (MAT == MAT_J2) {
+        float* sp = jstate + off.field[b] * NST;
+#pragma unroll
+        for (int i = 0; i < NST; ++i) {
+          sp[(int64_t)i * P.N + p0] = so0[i];
+          sp[(int64_t)i * P.N + p0 + 1] = so1[i];
+        }
+      }
+      if (out_eps) {
+        float* fe = out_eps + off.field[b] * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          fe[(int64_t)c * P.N + p0] = e0[c];
+          fe[(int64_t)c * P.N + p0 + 1] = e1[c];
+        }
+      }
+      if (out_sig) {
+        float* fs = out_sig + off.field[b] * S;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          fs[(int64_t)s * P.N + p0] = s0[s];
+          fs[(int64_t)s * P.N + p0 + 1] = s1[s];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[s] += (double)s0[s] + (double)s1[s];
+    }
+  }
+  if (MODE == MODE_FINAL) {
+    __shared__ double red[16];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double v = block_sum_d(acc[s], red);
+      if (threadIdx.x == 0) sig_part[(off.part[b] + blockIdx.x) * S + s] = v;
+    }
+    if (threadIdx.x == 0) {
+      unsigned long long by = (unsigned long long)nr * (unsigned long long)(16 * C * nlast + P.nlen);
+      if (out_eps) by += (unsigned long long)nr * P.nlen * 4ull * C;
+      if (out_sig) by += (unsigned long long)nr * P.nlen * 4ull * S;
+      if (MAT == MAT_J2) by += (unsigned long long)nr * P.nlen * 8ull * NST;
+      prof_add(prof, PK_FINAL, nr, by);
+    }
+    return;
+  }
+  __syncthreads();
+  cpx<float>* Z = fft_stockham<float, -1>(E, O, nseq, ss, P.fdh, twh);
+  for (int t = threadIdx.x; t < C * nlast * nr; t += blockDim.x) {
+    const int r = t % nr;
+    const int q = t / nr;
+    const int j = q % nlast, c = q / nlast;
+    const int k = P.last_k[j];
+    const cpx<float>* z = Z + (c * rb + r) * ss;
+    const cpx<float> Zk = z[k == nh ? 0 : k];
+    const cpx<float> Zc = cconj(z[k == 0 ? 0 : nh - k]);
+    const cpx<float> sm = cadd(Zk, Zc);
+    const cpx<float> wd = cmul(rtw[k], csub(Zk, Zc));
+    Y[c * cstride + (int64_t)j * rows + r0 + r] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
+  }
+  if (threadIdx.x == 0) {
+    unsigned long long by = (unsigned long long)nr * (unsigned long long)(16 * C * nlast + P.nlen);
+    if (MAT == MAT_J2) by += (unsigned long long)nr * P.nlen * 4ull * NST;
+    prof_add(prof, PK_ROW, nr, by);
+  }
+}
+
+// ------------------------------------------------------------------ column kernel
+// Workgroup = `cb` consecutive columns of one RVE.  MODE_ITER: forward FFT
+// along axis 0, Green operator on the pattern rows, residual, inverse FFT.
+// MODE_INIT: coefficients from the cold or warm start, inverse FFT only.
+template <int C, int MODE>
+__global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
+                                             RveState* __restrict__ st, const double* __restrict__ ebar,
+                                             cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
+                                             const cpx<float>* __restrict__ warm, Offs off,
+                                             double* __restrict__ part, MatDev mat, int cb,
+                                             unsigned int* __restrict__ active_count, Prof prof) {
+  extern __shared__ unsigned char smem_raw[];
+  const int b = rve_list[blockIdx.y];
+  if (MODE == MODE_ITER && !st[b].active) return;
+  const PlanDev& P = plans[st[b].plan];
+  const int ncol = P.ncol;
+  const int j0 = blockIdx.x * cb;
+  if (j0 >= ncol) return;
+  const int ncb = min(cb, ncol - j0);
+  const int n0 = P.n0;
+  const int nseq = C * cb;
+  cpx<float>* tw = reinterpret_cast<cpx<float>*>(smem_raw);
+  cpx<float>* A = tw + n0;
+  cpx<float>* Bf = A + nseq * n0;
+  for (int t = threadIdx.x; t < n0; t += blockDim.x) tw[t] = P.tw0[t];
+  cpx<float>* Y = Yc + off.yc[b];
+  const int64_t cstride = (int64_t)ncol * n0;
+  const int ncoef = P.ncoef;
+  cpx<float>* co = coef + off.coef[b];
+  cpx<float>* R = A;   // forward result
+  cpx<float>* O = Bf;  // zeroed buffer receiving the new coefficients
+  if (MODE == MODE_ITER) {
+    for (int t = threadIdx.x; t < C * ncb * n0; t += blockDim.x) {
+      const int x = t % n0;
+      const int q = t / n0;
+      const int jj = q % ncb, c = q / ncb;
+      A[(c * cb + jj) * n0 + x] = Y[c * cstride + (int64_t)(j0 + jj) * n0 + x];
+    }
+    __syncthreads();
+    R = fft_stockham<float, -1>(A, Bf, nseq, n0, P.fd0, tw);
+    O = (R == A) ? Bf : A;
+  }
+  for (int t = threadIdx.x; t < nseq * n0; t += blockDim.x) O[t] = {0.f, 0.f};
+  __syncthreads();
+  const float Nf = (float)P.N;
+  const float invN = P.inv_N;
+  double dsum = 0.0;
+  for (int jj = 0; jj < ncb; ++jj) {
+    const int j = j0 + jj;
+    const int kl = P.last_k[P.col_last[j]];
+    const float wcol = (kl == 0 || 2 * kl == P.nlen) ? 1.f : 2.f;
+    const int e1 = P.col_off[j + 1];
+    for (int e = P.col_off[j] + threadIdx.x; e < e1; e += blockDim.x) {
+      const int k0 = P.coef_k0[e];
+      const uint8_t fl = P.coef_flag[e];
+      float nr_[C], ni_[C];
+      if (fl & COEF_ZERO) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          nr_[c] = (float)((double)P.N * ebar[(int64_t)b * C + c]);
+          ni_[c] = 0.f;
+        }
+      } else if ((fl & COEF_DEAD)) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) nr_[c] = ni_[c] = 0.f;
+      } else if (MODE == MODE_ITER) {
+        float tr_[C], ti_[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const cpx<float> v = R[(c * cb + jj) * n0 + k0];
+          tr_[c] = v.x;
+          ti_[c] = v.y;
+        }
+        const float nv[3] = {P.coef_n[3 * e], P.coef_n[3 * e + 1], P.coef_n[3 * e + 2]};
+        green<C>(nv, tr_, nr_, mat.g_inv_mu0, mat.g_k);
+        green<C>(nv, ti_, ni_, mat.g_inv_mu0, mat.g_k);
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          if (warm) {
+            const cpx<float> w = warm[off.coef[b] + (int64_t)c * ncoef + e];
+            nr_[c] = w.x;
+            ni_[c] = w.y;
+          } else {
+            nr_[c] = ni_[c] = 0.f;
+          }
+        }
+      }
+      if (MODE == MODE_ITER) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const cpx<float> old = co[(int64_t)c * ncoef + e];
+          const double dr = (double)nr_[c] - (double)old.x, di = (double)ni_[c] - (double)old.y;
+          d2 += (double)comp_weight<C>(c) * (dr * dr + di * di);
+        }
+        dsum += (double)wcol * d2;
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        co[(int64_t)c * ncoef + e] = {nr_[c], ni_[c]};
+        O[(c * cb + jj) * n0 + k0] = {nr_[c] * invN, ni_[c] * invN};
+      }
+    }
+  }
+  (void)Nf;
+  __syncthreads();
+  cpx<float>* other = (O == A) ? Bf : A;
+  cpx<float>* F = fft_stockham<float, +1>(O, other, nseq, n0, P.fd0, tw);
+  for (int t = threadIdx.x; t < C * ncb * n0; t += blockDim.x) {
+    const int x = t % n0;
+    const int q = t / n0;
+    const int jj = q % ncb, c = q / ncb;
+    Y[c * cstride + (int64_t)(j0 + jj) * n0 + x] = F[(c * cb + jj) * n0 + x];
+  }
+  if (MODE == MODE_ITER) {
+    __shared__ double red[16];
+    const double tot = block_sum_d(dsum, red);
+    if (threadIdx.x == 0) {
+      const int e0 = P.col_off[j0], e1 = P.col_off[j0 + ncb];
+      prof_add(prof, PK_COL, ncb,
+               (unsigned long long)ncb * 16ull * C * n0 + (unsigned long long)(e1 - e0) * (16ull * C + 17ull));
+      const int nblk = (ncol + cb - 1) / cb;
+      part[off.part[b] + blockIdx.x] = tot;
+      __threadfence();
+      const unsigned prev = atomicAdd(&st[b].counter, 1u);
+      if (prev == (unsigned)(nblk - 1)) {
+        __threadfence();
+        double sum = 0.0;
+        const volatile double* pp = part + off.part[b];
+        for (int i = 0; i < nblk; ++i) sum += pp[i];
+        st[b].counter = 0u;
+        const double r = sqrt(sum) / st[b].denom;
+        const int it = st[b].iters + 1;
+        st[b].iters = it;
+        st[b].resid = r;
+        int done = 0;
+        if (!(r == r) || isinf(r)) {
+          st[b].status = MOR_E_NONFINITE;
+          done = 1;
+        } else if (r < st[b].tol) {
+          st[b].status = MOR_OK;
+          done = 1;
+        } else if (it >= st[b].max_iter) {
+          st[b].status = MOR_E_NOT_CONVERGED;
+          done = 1;
+        }
+        if (done) {
+          st[b].active = 0;
+          atomicSub(active_count, 1u);
+        }
+        __threadfence();
+      }
+    }
+  } else {
+    if (threadIdx.x == 0) prof_add(prof, PK_INIT, ncb, (unsigned long long)ncb * 8ull * C * n0);
+  }
+}
+
+// ------------------------------------------------------------------ 3D axis-1 kernels
+// Workgroup = (RVE, last-axis frequency j2, block of `xb` x0 values).
+// FWD: Yl lines along x1 -> FFT -> Yc at the group's columns.
+// INV: Yc at the group's columns -> zero-filled line -> inverse FFT -> Yl.
+template <int C, int DIR>
+__global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
+                                             RveState* __restrict__ st, cpx<float>* __restrict__ Yl,
+                                             cpx<float>* __restrict__ Yc, Offs off, int xb, int check_active,
+                                             Prof prof) {
+  extern __shared__ unsigned char smem_raw[];
+  const int b = rve_list[blockIdx.z];
+  if (check_active && !st[b].active) return;
+  const PlanDev& P = plans[st[b].plan];
+  const int j2 = blockIdx.y;
+  if (j2 >= P.nlast) return;
+  const int n0 = P.n0, n1 = P.n1;
+  const int x00 = blockIdx.x * xb;
+  if (x00 >= n0) return;
+  const int nx = min(xb, n0 - x00);
+  const int nseq = C * xb;
+  cpx<float>* tw = reinterpret_cast<cpx<float>*>(smem_raw);
+  cpx<float>* A = tw + n1;
+  cpx<float>* Bf = A + nseq * n1;
+  for (int t = threadIdx.x; t < n1; t += blockDim.x) tw[t] = P.tw1[t];
+  const int rows = P.rows;
+  const int nlast = P.nlast, ncol = P.ncol;
+  cpx<float>* L = Yl + off.yl[b];
+  cpx<float>* Cc = Yc + off.yc[b];
+  const int64_t lcs = (int64_t)nlast * rows;
+  const int64_t ccs = (int64_t)ncol * n0;
+  const int ja = P.last_off[j2], jb = P.last_off[j2 + 1];
+  const int ng = jb - ja;
+  if (DIR < 0) {
+    for (int t = threadIdx.x; t < C * nx * n1; t += blockDim.x) {
+      const int x1 = t % n1;
+      const int q = t / n1;
+      const int xi = q % nx, c = q / nx;
+      A[(c * xb + xi) * n1 + x1] = L[c * lcs + (int64_t)j2 * rows + (int64_t)(x00 + xi) * n1 + x1];
+    }
+    __syncthreads();
+    cpx<float>* R = fft_stockham<float, -1>(A, Bf, nseq, n1, P.fd1, tw);
+    for (int t = threadIdx.x; t < C * ng * nx; t += blockDim.x) {
+      const int xi = t % nx;
+      const int q = t / nx;
+      const int g = q % ng, c = q / ng;
+      const int j = ja + g;
+      Cc[c * ccs + (int64_t)j * n0 + x00 + xi] = R[(c * xb + xi) * n1 + P.col_k[j]];
+    }
+  } else {
+    for (int t = threadIdx.x; t < nseq * n1; t += blockDim.x) A[t] = {0.f, 0.f};
+    __syncthreads();
+    for (int t = threadIdx.x; t < C * ng * nx; t += blockDim.x) {
+      const int xi = t % nx;
+      const int q = t / nx;
+      const int g = q % ng, c = q / ng;
+      const int j = ja + g;
+      A[(c * xb + xi) * n1 + P.col_k[j]] = Cc[c * ccs + (int64_t)j * n0 + x00 + xi];
+    }
+    __syncthreads();
+    cpx<float>* R = fft_stockham<float, +1>(A, Bf, nseq, n1, P.fd1, tw);
+    for (int t = threadIdx.x; t < C * nx * n1; t += blockDim.x) {
+      const int x1 = t % n1;
+      const int q = t / n1;
+      const int xi = q % nx, c = q / nx;
+      L[c * lcs + (int64_t)j2 * rows + (int64_t)(x00 + xi) * n1 + x1] = R[(c * xb + xi) * n1 + x1];
+    }
+  }
+  if (threadIdx.x == 0)
+    prof_add(prof, DIR < 0 ? PK_MIDF : PK_MIDI, nx,
+             (unsigned long long)nx * 8ull * C * (n1 + ng));
+}
+
+// Per-RVE FP64 sum of the stress partials, fixed order.
+// Per-RVE grid mean of the stress: FP64 sum of the block partials in a fixed
+// order, divided by N (paper Sec. 2, volume average).
+template <int S>
+__global__ void k_sig_reduce(const PlanDev* __restrict__ plans, const RveState* __restrict__ st,
+                             const int* __restrict__ rve_list, int nrve, const double* __restrict__ sig_part,
+                             Offs off, const int* __restrict__ nblk, double* __restrict__ eff, int eff_stride) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrve * S) return;
+  const int i = t / S, s = t - i * S;
+  const int b = rve_list[i];
+  double acc = 0.0;
+  const int nb = nblk[i];
+  for (int k = 0; k < nb; ++k) acc += sig_part[(off.part[b] + k) * S + s];
+  eff[(int64_t)b * eff_stride + s] = acc / (double)plans[st[b].plan].N;
+}
+
+}  // namespace mor_k
