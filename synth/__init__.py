@@ -141,34 +141,62 @@ class RSAResult:
         return len(self.radii)
 
 
+def _stamp(g, centre, r):
+    """Set g = 1 on the voxels of one periodic ball; only its bounding box is
+    visited (voxels outside it are farther than r from the centre)."""
+    shape = g.shape
+    idx, ds = [], []
+    for a, n in enumerate(shape):
+        lo = int(np.floor(centre[a] - r - 1.0))
+        hi = int(np.floor(centre[a] + r + 1.0))
+        if hi - lo + 1 >= n:
+            ii = np.arange(n)
+        else:
+            ii = np.arange(lo, hi + 1) % n
+        x = ii.astype(np.float64) + 0.5
+        d = _min_image(x - centre[a], n)
+        sh = [1] * len(shape)
+        sh[a] = ii.size
+        idx.append(ii)
+        ds.append(d.reshape(sh))
+    d2 = 0.0
+    for d in ds:
+        d2 = d2 + d * d
+    inside = d2 <= r * r
+    sub = g[np.ix_(*idx)]
+    sub |= inside.astype(np.uint8)
+    g[np.ix_(*idx)] = sub
+
+
 def _rsa(shape, r_lo, r_hi, target_vf, seed, max_count, max_attempts, gap):
     rng = np.random.default_rng(seed)
     dim = len(shape)
     ext = np.array(shape, dtype=np.float64)
     g = np.zeros(shape, dtype=np.uint8)
-    centres, radii = [], []
+    centres = np.zeros((0, dim))
+    radii = np.zeros(0)
     attempts = 0
     total = float(np.prod(shape))
+    count = 0
     while attempts < max_attempts:
-        if max_count is not None and len(radii) >= max_count:
+        if max_count is not None and radii.size >= max_count:
             break
-        if target_vf is not None and g.sum() / total >= target_vf:
+        if target_vf is not None and count / total >= target_vf:
             break
         attempts += 1
         r = rng.uniform(r_lo, r_hi)
         c = rng.uniform(0.0, 1.0, size=dim) * ext
-        ok = True
-        for c2, r2 in zip(centres, radii):
-            d = _min_image(c - c2, ext)
-            if float(np.dot(d, d)) < (r + r2 + gap) ** 2:
-                ok = False
-                break
-        if not ok:
-            continue
-        centres.append(c)
-        radii.append(r)
-        g |= (_dist2(shape, c) <= r * r).astype(np.uint8)
-    return RSAResult(g=g, centres=centres, radii=radii, vf=float(g.sum()) / total, attempts=attempts)
+        if radii.size:
+            d = _min_image(c[None, :] - centres, ext)
+            dist2 = np.sum(d * d, axis=1)
+            if np.any(dist2 < (r + radii + gap) ** 2):
+                continue
+        centres = np.vstack([centres, c[None, :]])
+        radii = np.append(radii, r)
+        _stamp(g, c, r)
+        count = int(g.sum())
+    return RSAResult(g=g, centres=[c for c in centres], radii=radii.tolist(), vf=float(g.sum()) / total,
+                     attempts=attempts)
 
 
 def rsa_fibres(n0: int, n1: int, r_lo: float, r_hi: float, seed: int, target_vf=None,
