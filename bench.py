@@ -148,14 +148,16 @@ def main():
 
     # plain path: one RVE per launch
     ns = min(args.single, B)
-    for i in range(2):
-        mor.solve(plans[i], ebs[i:i + 1], ph, TOL)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for i in range(ns):
-        mor.solve(plans[i], ebs[i:i + 1], ph, TOL)
-    torch.cuda.synchronize()
-    single = ns / (time.perf_counter() - t)
+    single = None
+    if ns > 0:
+        for i in range(2):
+            mor.solve(plans[i], ebs[i:i + 1], ph, TOL)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(ns):
+            mor.solve(plans[i], ebs[i:i + 1], ph, TOL)
+        torch.cuda.synchronize()
+        single = ns / (time.perf_counter() - t)
 
     line = {
         "metric": METRIC,

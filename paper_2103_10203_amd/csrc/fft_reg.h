@@ -1,0 +1,253 @@
+// Compile-time specialised FFT building blocks: length-R DFTs in registers
+// and in-place Stockham passes over an LDS buffer.
+//
+// Stockham pass (radix R, span P = product of the radices before it, length
+// N): butterfly i < N/R of a sequence reads x[i + j N/R] (j < R), multiplies
+// input j by w^{j k N/(P R)} with k = i mod P and w = exp(SIGN 2 pi i / N),
+// applies the length-R DFT and stores output j at (i - k) R + k + j P.  A
+// pass reads everything into registers, waits at a barrier, then writes in
+// place, so one LDS buffer suffices.  The last pass of a transform leaves
+// thread i holding outputs i + j N/R; the first pass (P = 1) of the next
+// transform with the same radix reads exactly those indices, so pointwise
+// work between an inverse and a forward transform needs no LDS round trip.
+#pragma once
+
+#include "fft_lds.h"
+
+namespace fftr {
+
+template <int SIGN>
+__device__ __forceinline__ cpx<float> mul_i(cpx<float> a) {
+  return SIGN > 0 ? cpx<float>{-a.y, a.x} : cpx<float>{a.y, -a.x};
+}
+
+// cos and sin of 2 pi k / 16 for k = 0..8
+__host__ __device__ constexpr float c16(int k) {
+  return k == 0 ? 1.0f : k == 1 ? 0.92387953251128674f : k == 2 ? 0.70710678118654752f
+       : k == 3 ? 0.38268343236508977f : k == 4 ? 0.0f : k == 5 ? -0.38268343236508977f
+       : k == 6 ? -0.70710678118654752f : k == 7 ? -0.92387953251128674f : -1.0f;
+}
+__host__ __device__ constexpr float s16(int k) {
+  return k == 0 ? 0.0f : k == 1 ? 0.38268343236508977f : k == 2 ? 0.70710678118654752f
+       : k == 3 ? 0.92387953251128674f : k == 4 ? 1.0f : k == 5 ? 0.92387953251128674f
+       : k == 6 ? 0.70710678118654752f : k == 7 ? 0.38268343236508977f : 0.0f;
+}
+
+template <int SIGN, int K>
+__device__ __forceinline__ cpx<float> rot16(cpx<float> a) {
+  // a * exp(SIGN 2 pi i K / 16), K in [0, 8)
+  if constexpr (K == 0) return a;
+  else if constexpr (K == 4) return mul_i<SIGN>(a);
+  else {
+    constexpr float c = c16(K);
+    constexpr float s = SIGN * s16(K);
+    return {a.x * c - a.y * s, a.x * s + a.y * c};
+  }
+}
+
+template <int R, int SIGN>
+struct Dft;
+
+template <int SIGN>
+struct Dft<2, SIGN> {
+  __device__ __forceinline__ static void run(cpx<float>* v) {
+    cpx<float> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int SIGN>
+struct Dft<3, SIGN> {
+  __device__ __forceinline__ static void run(cpx<float>* v) {
+    const float h = 0.86602540378443864676f;
+    cpx<float> u0 = v[0], u1 = v[1], u2 = v[2];
+    cpx<float> sm = cadd(u1, u2);
+    cpx<float> df = cscale(mul_i<SIGN>(csub(u1, u2)), h);
+    cpx<float> base = {u0.x - 0.5f * sm.x, u0.y - 0.5f * sm.y};
+    v[0] = cadd(u0, sm);
+    v[1] = cadd(base, df);
+    v[2] = csub(base, df);
+  }
+};
+
+template <int SIGN>
+struct Dft<4, SIGN> {
+  __device__ __forceinline__ static void run(cpx<float>* v) {
+    cpx<float> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    cpx<float> s13 = cadd(v[1], v[3]), d13 = mul_i<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[2] = csub(s02, s13);
+    v[3] = csub(d02, d13);
+  }
+};
+
+template <int SIGN>
+struct Dft<6, SIGN> {
+  // two length-3 DFTs of the even and odd samples, combined with w6^k
+  __device__ __forceinline__ static void run(cpx<float>* v) {
+    cpx<float> e[3] = {v[0], v[2], v[4]};
+    cpx<float> o[3] = {v[1], v[3], v[5]};
+    Dft<3, SIGN>::run(e);
+    Dft<3, SIGN>::run(o);
+    const float h = 0.86602540378443864676f;
+    // w6^1 = 1/2 + SIGN i h, w6^2 = -1/2 + SIGN i h
+    const cpx<float> o1 = {0.5f * o[1].x - SIGN * h * o[1].y, 0.5f * o[1].y + SIGN * h * o[1].x};
+    const cpx<float> o2 = {-0.5f * o[2].x - SIGN * h * o[2].y, -0.5f * o[2].y + SIGN * h * o[2].x};
+    v[0] = cadd(e[0], o[0]);
+    v[3] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[4] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[5] = csub(e[2], o2);
+  }
+};
+
+template <int SIGN>
+struct Dft<8, SIGN> {
+  __device__ __forceinline__ static void run(cpx<float>* v) {
+    cpx<float> e[4] = {v[0], v[2], v[4], v[6]};
+    cpx<float> o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4, SIGN>::run(e);
+    Dft<4, SIGN>::run(o);
+    o[1] = rot16<SIGN, 2>(o[1]);
+    o[2] = rot16<SIGN, 4>(o[2]);
+    o[3] = rot16<SIGN, 6>(o[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = cadd(e[k], o[k]);
+      v[k + 4] = csub(e[k], o[k]);
+    }
+  }
+};
+
+template <int SIGN>
+struct Dft<16, SIGN> {
+  __device__ __forceinline__ static void run(cpx<float>* v) {
+    cpx<float> e[8], o[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      e[j] = v[2 * j];
+      o[j] = v[2 * j + 1];
+    }
+    Dft<8, SIGN>::run(e);
+    Dft<8, SIGN>::run(o);
+    o[1] = rot16<SIGN, 1>(o[1]);
+    o[2] = rot16<SIGN, 2>(o[2]);
+    o[3] = rot16<SIGN, 3>(o[3]);
+    o[4] = rot16<SIGN, 4>(o[4]);
+    o[5] = rot16<SIGN, 5>(o[5]);
+    o[6] = rot16<SIGN, 6>(o[6]);
+    o[7] = rot16<SIGN, 7>(o[7]);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      v[k] = cadd(e[k], o[k]);
+      v[k + 8] = csub(e[k], o[k]);
+    }
+  }
+};
+
+// LDS position of element i of a sequence: one pad slot after every 16
+// elements, so that stride-R accesses (R = 2..16, 8-byte elements) of a
+// wavefront spread over all banks.
+__host__ __device__ constexpr int pad16(int i) { return i + (i >> 4); }
+
+// Sequence stride in LDS for `len` logical elements (odd, so that sequences
+// start on different banks).
+__host__ __device__ constexpr int seq_stride(int len) {
+  return (pad16(len - 1) + 1) | 1;
+}
+
+// Twiddle w^{e} from a table tw[t] = exp(-2 pi i t / (N * TWS)), read at
+// stride TWS (conjugated for SIGN > 0).
+template <int SIGN, int TWS>
+__device__ __forceinline__ cpx<float> twid(const cpx<float>* tw, int e) {
+  cpx<float> w = tw[e * TWS];
+  return SIGN > 0 ? cconj(w) : w;
+}
+
+// Apply the pass twiddles to v[1..R-1] for butterfly phase k.
+template <int N, int R, int P, int SIGN, int TWS = 1>
+__device__ __forceinline__ void pass_twiddle(cpx<float>* v, int k, const cpx<float>* tw) {
+  if constexpr (P > 1) {
+    constexpr int ST = N / (P * R);
+#pragma unroll
+    for (int j = 1; j < R; ++j) v[j] = cmul(v[j], twid<SIGN, TWS>(tw, j * k * ST));
+  }
+}
+
+// One in-place Stockham pass over NS sequences (base + s*SS, padded
+// positions) by NT threads.
+template <int N, int R, int P, int SIGN, int NS, int SS, int NT, int TWS>
+__device__ __forceinline__ void lds_pass(cpx<float>* buf, const cpx<float>* tw, int tid) {
+  constexpr int NB = N / R;
+  constexpr int TOTAL = NS * NB;
+  constexpr int PER = (TOTAL + NT - 1) / NT;
+  cpx<float> v[PER][R];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = tid + q * NT;
+    if (TOTAL % NT == 0 || t < TOTAL) {
+      const int s = t / NB, i = t % NB;
+      const int k = i % P;
+      const cpx<float>* src = buf + s * SS;
+#pragma unroll
+      for (int j = 0; j < R; ++j) v[q][j] = src[pad16(i + j * NB)];
+      pass_twiddle<N, R, P, SIGN, TWS>(v[q], k, tw);
+      Dft<R, SIGN>::run(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int t = tid + q * NT;
+    if (TOTAL % NT == 0 || t < TOTAL) {
+      const int s = t / NB, i = t % NB;
+      const int k = i % P;
+      cpx<float>* dst = buf + s * SS;
+      const int o = (i - k) * R + k;
+#pragma unroll
+      for (int j = 0; j < R; ++j) dst[pad16(o + j * P)] = v[q][j];
+    }
+  }
+  __syncthreads();
+}
+
+template <int... Rs>
+struct RList {};
+
+// Runs the passes of RList in order starting with span P.
+template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS>
+__device__ __forceinline__ void lds_passes(cpx<float>*, const cpx<float>*, int, RList<>) {}
+
+template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS, int R, int... Rest>
+__device__ __forceinline__ void lds_passes(cpx<float>* buf, const cpx<float>* tw, int tid, RList<R, Rest...>) {
+  lds_pass<N, R, P, SIGN, NS, SS, NT, TWS>(buf, tw, tid);
+  lds_passes<N, SIGN, P * R, NS, SS, NT, TWS>(buf, tw, tid, RList<Rest...>{});
+}
+
+template <int... Rs>
+struct Prod;
+template <>
+struct Prod<> {
+  static constexpr int v = 1;
+};
+template <int R, int... Rest>
+struct Prod<R, Rest...> {
+  static constexpr int v = R * Prod<Rest...>::v;
+};
+
+// Reverse of a radix list.
+template <typename A, typename B>
+struct Rev;
+template <int... Bs>
+struct Rev<RList<>, RList<Bs...>> {
+  using type = RList<Bs...>;
+};
+template <int A0, int... As, int... Bs>
+struct Rev<RList<A0, As...>, RList<Bs...>> {
+  using type = typename Rev<RList<As...>, RList<A0, Bs...>>::type;
+};
+
+}  // namespace fftr

@@ -65,7 +65,7 @@ struct PlanDev {
   const cpx<float>* tw0;     // [n0]        exp(-2 pi i t/n0)
   const cpx<float>* tw1;     // [n1]        exp(-2 pi i t/n1) (3D)
   const cpx<float>* twh;     // [nlen/2]    exp(-2 pi i t/(nlen/2))
-  const cpx<float>* rtw;     // [nlen/2+1]  exp(-2 pi i t/nlen)
+  const cpx<float>* rtw;     // [nlen]      exp(-2 pi i t/nlen)
   FftDesc fd0, fd1, fdh;
 };
 
@@ -108,7 +108,7 @@ struct RveState {
   double denom;     // N * ||eps_bar||_F (or N when eps_bar = 0)
   double tol;
   int32_t max_iter;
-  uint32_t counter; // column-kernel completion counter of the current pass
+  int32_t pad_;
 };
 
 // Kernel ids of the profiling counters.

@@ -599,7 +599,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
 
   // twiddles for the solver transforms
   const int n0 = P->n[0], n1 = P->n[1];
-  const int ntw = n0 + n1 + nlen / 2 + (nlen / 2 + 1);
+  const int ntw = n0 + n1 + nlen / 2 + nlen;
   MOR_HIP_TRY(hipMalloc((void**)&P->d_tw, ntw * sizeof(cpx<float>)));
   cpx<float>* tw0 = P->d_tw;
   cpx<float>* tw1 = tw0 + n0;
@@ -608,7 +608,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   k_twiddle_f32<<<(n0 + 255) / 256, 256, 0, st>>>(tw0, n0, n0);
   k_twiddle_f32<<<(n1 + 255) / 256, 256, 0, st>>>(tw1, n1, n1);
   k_twiddle_f32<<<(nlen / 2 + 255) / 256, 256, 0, st>>>(twh, nlen / 2, nlen / 2);
-  k_twiddle_f32<<<(nlen / 2 + 1 + 255) / 256, 256, 0, st>>>(rtw, nlen, nlen / 2 + 1);
+  k_twiddle_f32<<<(nlen + 255) / 256, 256, 0, st>>>(rtw, nlen, nlen);
   MOR_LAUNCH_CHECK("twiddle_f32");
 
   PlanDev& v = P->dev;

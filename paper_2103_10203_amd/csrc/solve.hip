@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "solve_kernels.h"
+#include "solve_fast.h"
 
 using namespace mor_k;
 
@@ -113,8 +113,47 @@ struct Group {
   std::vector<int> rves;
   int ncol_max = 0, nlast_max = 0;
   int rb = 1, cb = 1, xb = 1;
+  bool fast_row = false, fast_col = false;
   int* d_list = nullptr;
 };
+
+// Size-specialised kernels available for (C, half row length) and (C, n0).
+bool has_fast_row(int C, int nh) {
+  if (C == 3) return nh == 32 || nh == 64 || nh == 128 || nh == 192 || nh == 256;
+  return nh == 32 || nh == 64 || nh == 128;
+}
+bool has_fast_col(int C, int n0) {
+  if (C == 3) return n0 == 64 || n0 == 128 || n0 == 256 || n0 == 384 || n0 == 512;
+  return n0 == 64 || n0 == 128;
+}
+int fast_rb(int C, int nh) {
+  if (C == 3) {
+    switch (nh) {
+      case 32: return RowCfg<3, 32>::RB;
+      case 64: return RowCfg<3, 64>::RB;
+      case 128: return RowCfg<3, 128>::RB;
+      case 192: return RowCfg<3, 192>::RB;
+      default: return RowCfg<3, 256>::RB;
+    }
+  }
+  switch (nh) {
+    case 32: return RowCfg<6, 32>::RB;
+    case 64: return RowCfg<6, 64>::RB;
+    default: return RowCfg<6, 128>::RB;
+  }
+}
+int fast_cb(int C, int n0) {
+  if (C == 3) {
+    switch (n0) {
+      case 64: return ColCfg<3, 64>::CB;
+      case 128: return ColCfg<3, 128>::CB;
+      case 256: return ColCfg<3, 256>::CB;
+      case 384: return ColCfg<3, 384>::CB;
+      default: return ColCfg<3, 512>::CB;
+    }
+  }
+  return n0 == 64 ? ColCfg<6, 64>::CB : ColCfg<6, 128>::CB;
+}
 
 struct SolveCtx {
   hipStream_t st = nullptr;
@@ -132,7 +171,6 @@ struct SolveCtx {
   double* d_sigpart = nullptr;
   double* d_eff = nullptr;
   unsigned int* d_active = nullptr;
-  unsigned long long* d_prof = nullptr;
   int* d_nblk = nullptr;
   float* d_jstate = nullptr;
   Offs off{};
@@ -142,6 +180,8 @@ struct SolveCtx {
   std::vector<int> ncoef_h;
   std::vector<EventPair> events;
   std::vector<std::vector<char>> keep;  // host staging that must outlive async copies
+  std::vector<PlanDev> plan_dev;         // plan of every RVE (host copy)
+  bool want_eps = false, want_sig = false;
 };
 
 // Asynchronous upload from a host copy kept alive until the solve ends.
@@ -212,32 +252,77 @@ void ev_end(SolveCtx& cx, int kind, hipEvent_t a) {
   cx.events.push_back({a, b, kind});
 }
 
-Prof prof_of(SolveCtx& cx) {
-  Prof p{nullptr, nullptr};
-  if (g_prof_on) {
-    p.items = cx.d_prof;
-    p.bytes = cx.d_prof + PK_COUNT;
-  }
-  return p;
-}
 
 // ------------------------------------------------------------------ launches
+template <int C, int NH, int MODE, int MAT>
+void go_row_fast(SolveCtx& cx, Group& g, float* eps, float* sig, int rows) {
+  dim3 gr((rows + RowCfg<C, NH>::RB - 1) / RowCfg<C, NH>::RB, (unsigned)g.rves.size());
+  k_row_fast<C, NH, MODE, MAT><<<gr, row_threads<C, NH>(), row_lds_bytes<C, NH>(), cx.st>>>(
+      cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat, cx.d_jstate, eps, sig, cx.d_sigpart);
+}
+
+template <int C, int MODE, int MAT>
+void row_fast(SolveCtx& cx, Group& g, float* eps, float* sig) {
+  const int nlen = C == 3 ? g.n1 : g.n2;
+  const int rows = C == 3 ? g.n0 : g.n0 * g.n1;
+  if constexpr (C == 3) {
+    switch (nlen / 2) {
+      case 32: go_row_fast<3, 32, MODE, MAT>(cx, g, eps, sig, rows); break;
+      case 64: go_row_fast<3, 64, MODE, MAT>(cx, g, eps, sig, rows); break;
+      case 128: go_row_fast<3, 128, MODE, MAT>(cx, g, eps, sig, rows); break;
+      case 192: go_row_fast<3, 192, MODE, MAT>(cx, g, eps, sig, rows); break;
+      default: go_row_fast<3, 256, MODE, MAT>(cx, g, eps, sig, rows); break;
+    }
+  } else {
+    switch (nlen / 2) {
+      case 32: go_row_fast<6, 32, MODE, MAT>(cx, g, eps, sig, rows); break;
+      case 64: go_row_fast<6, 64, MODE, MAT>(cx, g, eps, sig, rows); break;
+      default: go_row_fast<6, 128, MODE, MAT>(cx, g, eps, sig, rows); break;
+    }
+  }
+}
+
+template <int C, int N0, int MODE>
+void go_col_fast(SolveCtx& cx, Group& g, const cpx<float>* warm) {
+  dim3 gc((g.ncol_max + ColCfg<C, N0>::CB - 1) / ColCfg<C, N0>::CB, (unsigned)g.rves.size());
+  k_col_fast<C, N0, MODE><<<gc, col_threads<C, N0>(), col_lds_bytes<C, N0>(), cx.st>>>(
+      cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef, warm, cx.off, cx.d_part, cx.mat);
+}
+
+template <int C, int MODE>
+void col_fast(SolveCtx& cx, Group& g, const cpx<float>* warm) {
+  if constexpr (C == 3) {
+    switch (g.n0) {
+      case 64: go_col_fast<3, 64, MODE>(cx, g, warm); break;
+      case 128: go_col_fast<3, 128, MODE>(cx, g, warm); break;
+      case 256: go_col_fast<3, 256, MODE>(cx, g, warm); break;
+      case 384: go_col_fast<3, 384, MODE>(cx, g, warm); break;
+      default: go_col_fast<3, 512, MODE>(cx, g, warm); break;
+    }
+  } else {
+    if (g.n0 == 64) go_col_fast<6, 64, MODE>(cx, g, warm);
+    else go_col_fast<6, 128, MODE>(cx, g, warm);
+  }
+}
+
 template <int C>
 mor_status launch_init(SolveCtx& cx, Group& g, const cpx<float>* warm) {
   const size_t shc = (size_t)(g.n0 + 2 * C * g.cb * g.n0) * sizeof(cpx<float>);
   dim3 grid((g.ncol_max + g.cb - 1) / g.cb, (unsigned)g.rves.size());
   hipEvent_t a{};
   ev_begin(cx, PK_INIT, &a);
-  k_col<C, MODE_INIT><<<grid, 256, shc, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef, warm,
-                                                 cx.off, cx.d_part, cx.mat, g.cb, cx.d_active, prof_of(cx));
+  if (g.fast_col)
+    col_fast<C, MODE_INIT>(cx, g, warm);
+  else
+    k_col<C, MODE_INIT><<<grid, 256, shc, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef,
+                                                   warm, cx.off, cx.d_part, cx.mat, g.cb);
   MOR_LAUNCH_CHECK("col(init)");
   ev_end(cx, PK_INIT, a);
   if (C == 6) {
     const size_t shm = (size_t)(g.n1 + 2 * C * g.xb * g.n1) * sizeof(cpx<float>);
     dim3 gm((g.n0 + g.xb - 1) / g.xb, g.nlast_max, (unsigned)g.rves.size());
     ev_begin(cx, PK_MIDI, &a);
-    k_mid<C, +1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 0,
-                                         prof_of(cx));
+    k_mid<C, +1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 0);
     MOR_LAUNCH_CHECK("mid(inv)");
     ev_end(cx, PK_MIDI, a);
   }
@@ -253,33 +338,42 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
   dim3 gr((rows + g.rb - 1) / g.rb, (unsigned)g.rves.size());
   hipEvent_t a{};
   ev_begin(cx, PK_ROW, &a);
-  k_row<C, MODE_ITER, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
-                                                    cx.d_jstate, nullptr, nullptr, nullptr, g.rb, prof_of(cx));
+  if (g.fast_row)
+    row_fast<C, MODE_ITER, MAT>(cx, g, nullptr, nullptr);
+  else
+    k_row<C, MODE_ITER, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
+                                                      cx.d_jstate, nullptr, nullptr, nullptr, g.rb);
   MOR_LAUNCH_CHECK("row");
   ev_end(cx, PK_ROW, a);
   const size_t shm = (size_t)(g.n1 + 2 * C * g.xb * g.n1) * sizeof(cpx<float>);
   dim3 gm((g.n0 + g.xb - 1) / g.xb, g.nlast_max, (unsigned)g.rves.size());
   if (C == 6) {
     ev_begin(cx, PK_MIDF, &a);
-    k_mid<C, -1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 1,
-                                         prof_of(cx));
+    k_mid<C, -1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 1);
     MOR_LAUNCH_CHECK("mid(fwd)");
     ev_end(cx, PK_MIDF, a);
   }
   const size_t shc = (size_t)(g.n0 + 2 * C * g.cb * g.n0) * sizeof(cpx<float>);
   dim3 gc((g.ncol_max + g.cb - 1) / g.cb, (unsigned)g.rves.size());
   ev_begin(cx, PK_COL, &a);
-  k_col<C, MODE_ITER><<<gc, 256, shc, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef, nullptr,
-                                               cx.off, cx.d_part, cx.mat, g.cb, cx.d_active, prof_of(cx));
+  if (g.fast_col)
+    col_fast<C, MODE_ITER>(cx, g, nullptr);
+  else
+    k_col<C, MODE_ITER><<<gc, 256, shc, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef,
+                                                 nullptr, cx.off, cx.d_part, cx.mat, g.cb);
   MOR_LAUNCH_CHECK("col");
   ev_end(cx, PK_COL, a);
   if (C == 6) {
     ev_begin(cx, PK_MIDI, &a);
-    k_mid<C, +1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 1,
-                                         prof_of(cx));
+    k_mid<C, +1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 1);
     MOR_LAUNCH_CHECK("mid(inv)");
     ev_end(cx, PK_MIDI, a);
   }
+  // the stop decision comes last: every stage of this iteration has run
+  const int nrv = (int)g.rves.size();
+  k_converge<<<(nrv + 255) / 256, 256, 0, cx.st>>>(cx.d_plans, g.d_list, nrv, cx.d_st, cx.d_part, cx.off, g.cb,
+                                                   cx.d_active);
+  MOR_LAUNCH_CHECK("converge");
   return MOR_OK;
 }
 
@@ -292,8 +386,11 @@ mor_status launch_final(SolveCtx& cx, Group& g, float* eps, float* sig) {
   dim3 gr((rows + g.rb - 1) / g.rb, (unsigned)g.rves.size());
   hipEvent_t a{};
   ev_begin(cx, PK_FINAL, &a);
-  k_row<C, MODE_FINAL, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
-                                                     cx.d_jstate, eps, sig, cx.d_sigpart, g.rb, prof_of(cx));
+  if (g.fast_row)
+    row_fast<C, MODE_FINAL, MAT>(cx, g, eps, sig);
+  else
+    k_row<C, MODE_FINAL, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
+                                                       cx.d_jstate, eps, sig, cx.d_sigpart, g.rb);
   MOR_LAUNCH_CHECK("row(final)");
   ev_end(cx, PK_FINAL, a);
   constexpr int S = Comp<C>::S;
@@ -335,6 +432,8 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   // plan table
   std::vector<PlanDev> pd(plans.size());
   for (size_t i = 0; i < plans.size(); ++i) pd[i] = plans[i]->dev;
+  cx.plan_dev.resize(B);
+  for (int64_t b = 0; b < B; ++b) cx.plan_dev[b] = plans[plan_of[b]]->dev;
   if ((s = ws.get("plans", pd.size(), &cx.d_plans)) != MOR_OK) return s;
   if ((s = upload(cx, cx.d_plans, pd)) != MOR_OK) return s;
   // groups by grid
@@ -370,11 +469,13 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   cx.ncoef_h.resize(B);
   for (auto& g : cx.groups) {
     const int nlen = g.ndim == 2 ? g.n1 : g.n2;
-    g.rb = rows_per_block(cx.C, nlen);
-    g.cb = cols_per_block(cx.C, g.n0);
+    g.fast_row = has_fast_row(cx.C, nlen / 2);
+    g.fast_col = has_fast_col(cx.C, g.n0);
+    g.rb = g.fast_row ? fast_rb(cx.C, nlen / 2) : rows_per_block(cx.C, nlen);
+    g.cb = g.fast_col ? fast_cb(cx.C, g.n0) : cols_per_block(cx.C, g.n0);
     g.xb = g.ndim == 3 ? cols_per_block(cx.C, g.n1) : 1;
     const int rows = g.ndim == 2 ? g.n0 : g.n0 * g.n1;
-    g.rb = std::min(g.rb, rows);
+    if (!g.fast_row) g.rb = std::min(g.rb, rows);
   }
   std::vector<int> gof(B);
   for (size_t gi = 0; gi < cx.groups.size(); ++gi)
@@ -423,7 +524,6 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   if ((s = ws.get("sigpart", (size_t)pa * cx.S, &cx.d_sigpart)) != MOR_OK) return s;
   if ((s = ws.get("eff", (size_t)B * cx.S, &cx.d_eff)) != MOR_OK) return s;
   if ((s = ws.get("active", 1, &cx.d_active)) != MOR_OK) return s;
-  if ((s = ws.get("prof", 2 * PK_COUNT, &cx.d_prof)) != MOR_OK) return s;
   if ((s = ws.get("ebar", (size_t)B * cx.C, &cx.d_ebar)) != MOR_OK) return s;
   if ((s = ws.get("state", (size_t)B, &cx.d_st)) != MOR_OK) return s;
   // group lists and final block counts (per group position)
@@ -462,13 +562,12 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     r.denom = (double)plans[plan_of[b]]->N * (nrm2 > 0.0 ? std::sqrt(nrm2) : 1.0);
     r.tol = tol;
     r.max_iter = max_iter;
-    r.counter = 0u;
+    r.pad_ = 0;
   }
   if ((s = upload(cx, cx.d_st, hs)) != MOR_OK) return s;
   if ((s = upload(cx, cx.d_ebar, eb)) != MOR_OK) return s;
   std::vector<unsigned int> act(1, (unsigned int)B);
   if ((s = upload(cx, cx.d_active, act)) != MOR_OK) return s;
-  if (g_prof_on) MOR_HIP_TRY(hipMemsetAsync(cx.d_prof, 0, 2 * PK_COUNT * sizeof(unsigned long long), cx.st));
   // J2 state
   if (cx.j2) {
     if (jstate_user) {
@@ -529,9 +628,6 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
     for (int64_t b = 0; b < cx.B; ++b) tot += (int64_t)cx.C * cx.ncoef_h[b];
     MOR_HIP_TRY(hipMemcpyAsync(out->coeffs, cx.d_coef, tot * sizeof(cpx<float>), hipMemcpyDeviceToDevice, cx.st));
   }
-  unsigned long long prof[2 * PK_COUNT] = {0};
-  if (g_prof_on)
-    MOR_HIP_TRY(hipMemcpyAsync(prof, cx.d_prof, sizeof(prof), hipMemcpyDeviceToHost, cx.st));
   MOR_HIP_TRY(hipStreamSynchronize(cx.st));
   if (g_prof_on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -542,9 +638,34 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
         g_prof[e.kind].launches += 1;
       }
     }
-    for (int k = 0; k < PK_COUNT; ++k) {
-      g_prof[k].items += (int64_t)prof[k];
-      g_prof[k].bytes += (double)prof[PK_COUNT + k];
+    // Algorithmic HBM bytes of the work done: RVE b ran its row/column (and
+    // axis-1) kernels once per iteration, init and final once.
+    for (int64_t b = 0; b < cx.B; ++b) {
+      const PlanDev& d = cx.plan_dev[b];
+      const double it = hs[b].iters;
+      const double C = cx.C, L = d.nlen;
+      double row = d.rows * (16.0 * C * d.nlast + L);
+      if (cx.j2) row += d.rows * L * 4.0 * cx.NST;
+      const double col = d.ncol * 16.0 * C * d.n0 + d.ncoef * (16.0 * C + 17.0);
+      const double mid = cx.ndim == 3 ? d.n0 * 8.0 * C * ((double)d.nlast * d.n1 + d.ncol) : 0.0;
+      double fin = d.rows * (8.0 * C * d.nlast + L);
+      if (cx.want_eps) fin += (double)d.N * 4.0 * C;
+      if (cx.want_sig) fin += (double)d.N * 4.0 * cx.S;
+      if (cx.j2) fin += (double)d.N * 8.0 * cx.NST;
+      g_prof[PK_ROW].items += (int64_t)it;
+      g_prof[PK_ROW].bytes += it * row;
+      g_prof[PK_COL].items += (int64_t)it;
+      g_prof[PK_COL].bytes += it * col;
+      if (cx.ndim == 3) {
+        g_prof[PK_MIDF].items += (int64_t)it;
+        g_prof[PK_MIDF].bytes += it * mid;
+        g_prof[PK_MIDI].items += (int64_t)it + 1;
+        g_prof[PK_MIDI].bytes += (it + 1.0) * mid;
+      }
+      g_prof[PK_FINAL].items += 1;
+      g_prof[PK_FINAL].bytes += fin;
+      g_prof[PK_INIT].items += 1;
+      g_prof[PK_INIT].bytes += d.ncol * 8.0 * C * d.n0 + d.ncoef * 25.0;
     }
   }
   cx.events.clear();
@@ -621,6 +742,8 @@ mor_status solve_impl(const std::vector<mor_plan*>& plans, const std::vector<int
     (void)hipStreamSynchronize(cx.st);
     return s;
   }
+  cx.want_eps = out && out->strain;
+  cx.want_sig = out && out->stress;
   s = run(cx, opts ? (const cpx<float>*)opts->warm_start : nullptr, opts, out ? out->strain : nullptr,
           out ? out->stress : nullptr);
   if (s != MOR_OK) {

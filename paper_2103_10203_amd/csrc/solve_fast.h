@@ -1,0 +1,413 @@
+// Size-specialised row and column kernels of the reduced iteration.  Same
+// data layout and results as the generic kernels in solve_kernels.h; the
+// transforms are compile-time Stockham passes (fft_reg.h) on one in-place,
+// bank-padded LDS buffer, and the pointwise constitutive step runs in
+// registers between the last inverse pass and the first forward pass.
+#pragma once
+
+#include "fft_reg.h"
+#include "solve_kernels.h"
+
+namespace mor_k {
+
+using fftr::Dft;
+using fftr::pad16;
+using fftr::RList;
+
+// Row kernel configuration for a half length NH (row length L = 2 NH):
+// inverse passes RA..., then the register pass RL; forward RL, then RA
+// reversed.  RB rows per workgroup, NH/RL threads per row.
+template <int C, int NH>
+struct RowCfg;
+template <> struct RowCfg<3, 32>  { static constexpr int RL = 8, RB = 48; using RA = RList<4>; };
+template <> struct RowCfg<3, 64>  { static constexpr int RL = 8, RB = 24; using RA = RList<8>; };
+template <> struct RowCfg<3, 128> { static constexpr int RL = 8, RB = 12; using RA = RList<4, 4>; };
+template <> struct RowCfg<3, 192> { static constexpr int RL = 8, RB = 8;  using RA = RList<4, 3, 2>; };
+template <> struct RowCfg<3, 256> { static constexpr int RL = 8, RB = 6;  using RA = RList<4, 8>; };
+template <> struct RowCfg<6, 32>  { static constexpr int RL = 8, RB = 16; using RA = RList<4>; };
+template <> struct RowCfg<6, 64>  { static constexpr int RL = 8, RB = 8;  using RA = RList<8>; };
+template <> struct RowCfg<6, 128> { static constexpr int RL = 8, RB = 4;  using RA = RList<4, 4>; };
+
+template <int C, int NH>
+constexpr int row_threads() {
+  return RowCfg<C, NH>::RB * (NH / RowCfg<C, NH>::RL);
+}
+template <int NH>
+constexpr int row_ss() {
+  return fftr::seq_stride(NH + 1);  // NH + 1 spectrum slots (Nyquist included)
+}
+template <int C, int NH>
+constexpr size_t row_lds_bytes() {
+  return (size_t)(2 * NH + C * RowCfg<C, NH>::RB * row_ss<NH>()) * sizeof(cpx<float>);
+}
+
+template <int C, int NH, int MODE, int MAT>
+__global__ __launch_bounds__((row_threads<C, NH>())) void k_row_fast(
+    const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
+    cpx<float>* __restrict__ Yl, Offs off, MatDev mat, float* __restrict__ jstate, float* __restrict__ out_eps,
+    float* __restrict__ out_sig, double* __restrict__ sig_part) {
+  using Cfg = RowCfg<C, NH>;
+  constexpr int RL = Cfg::RL, RB = Cfg::RB;
+  constexpr int TR = NH / RL;  // threads per row in the register pass
+  constexpr int NT = RB * TR;
+  constexpr int SS = row_ss<NH>();
+  constexpr int NSEQ = C * RB;
+  constexpr int S = Comp<C>::S;
+  constexpr int NST = Comp<C>::NST;
+  constexpr int L = 2 * NH;
+  static_assert(NT % 64 == 0, "workgroups are whole wavefronts");
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ int lk[NH + 1];
+  const int tid = threadIdx.x;
+  const int b = rve_list[blockIdx.y];
+  if (MODE == MODE_ITER && !st[b].active) return;
+  const PlanDev& P = plans[st[b].plan];
+  const int rows = P.rows;
+  const int r0 = blockIdx.x * RB;
+  if (r0 >= rows) return;
+  const int nr = min(RB, rows - r0);
+  // T[t] = exp(-2 pi i t / L): the real-FFT twiddles are T[k], the length-NH
+  // FFT twiddles are T[2 e].
+  cpx<float>* T = reinterpret_cast<cpx<float>*>(smem_raw);
+  cpx<float>* buf = T + L;
+  const int nlast = P.nlast;
+  for (int t = tid; t < L; t += NT) T[t] = P.rtw[t];
+  for (int t = tid; t < nlast; t += NT) lk[t] = P.last_k[t];
+  for (int t = tid; t < NSEQ * SS; t += NT) buf[t] = {0.f, 0.f};
+  __syncthreads();
+  cpx<float>* Y = Yl + off.yl[b];
+  const int64_t cstride = (int64_t)nlast * rows;
+  // gather the row block's last-axis spectra; U independent loads in flight
+  {
+    constexpr int U = 4;
+    const int tot = C * nlast * RB;
+    for (int t0 = tid; t0 < tot; t0 += NT * U) {
+      cpx<float> val[U];
+      int dst[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * NT;
+        const int r = t % RB, q = t / RB;
+        dst[u] = -1;
+        if (t < tot && r < nr) {
+          const int j = q % nlast, c = q / nlast;
+          val[u] = Y[c * cstride + (int64_t)j * rows + r0 + r];
+          dst[u] = (c * RB + r) * SS + pad16(lk[j]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (dst[u] >= 0) buf[dst[u]] = val[u];
+    }
+  }
+  __syncthreads();
+  // pack the half spectrum X[0..NH] into the length-NH sequence
+  //   z[k] = (X[k] + conj X[NH-k]) + i (X[k] - conj X[NH-k]) conj(T[k]);
+  // each thread owns the pair (k, NH-k), so the update is in place.
+  for (int t = tid; t < NSEQ * (NH / 2 + 1); t += NT) {
+    const int q = t / (NH / 2 + 1), k = t % (NH / 2 + 1);
+    cpx<float>* x = buf + q * SS;
+    const cpx<float> Xk = x[pad16(k)], Xm = x[pad16(NH - k)];
+    const cpx<float> a = cadd(Xk, cconj(Xm));
+    const cpx<float> d = cmul(csub(Xk, cconj(Xm)), cconj(T[k]));
+    const cpx<float> zk = {a.x - d.y, a.y + d.x};
+    if (k == 0 || 2 * k == NH) {
+      x[pad16(k)] = zk;
+    } else {
+      const cpx<float> a2 = cadd(Xm, cconj(Xk));
+      const cpx<float> d2 = cmul(csub(Xm, cconj(Xk)), cconj(T[NH - k]));
+      x[pad16(k)] = zk;
+      x[pad16(NH - k)] = {a2.x - d2.y, a2.y + d2.x};
+    }
+  }
+  __syncthreads();
+  fftr::lds_passes<NH, +1, 1, NSEQ, SS, NT, 2>(buf, T, tid, typename Cfg::RA{});
+
+  // register pass: last inverse stage (radix RL, span TR)
+  const int r = tid / TR, i = tid % TR;
+  cpx<float> v[C][RL];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const cpx<float>* src = buf + (c * RB + r) * SS;
+#pragma unroll
+    for (int j = 0; j < RL; ++j) v[c][j] = src[pad16(i + j * TR)];
+    fftr::pass_twiddle<NH, RL, TR, +1, 2>(v[c], i, T);
+    Dft<RL, +1>::run(v[c]);
+  }
+  __syncthreads();
+  // pointwise step a): thread holds points 2t, 2t+1 of row r0+r for t = i + j TR
+  const bool live = r < nr;
+  const int64_t row = r0 + r;
+  double acc[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc[s] = 0.0;
+  if (live) {
+    const uint8_t* grow = P.g + row * L;
+#pragma unroll
+    for (int j = 0; j < RL; ++j) {
+      const int tt = i + j * TR;
+      const int64_t p0 = row * L + 2 * tt;
+      const uchar2 gg = *reinterpret_cast<const uchar2*>(grow + 2 * tt);
+      float e0[C], e1[C], t0[C], t1[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        e0[c] = v[c][j].x;
+        e1[c] = v[c][j].y;
+      }
+      float sin0[NST], sin1[NST];
+      if (MAT == MAT_J2) {
+        const float* sp = jstate + off.field[b] * NST;
+#pragma unroll
+        for (int q = 0; q < NST; ++q) {
+          const float2 w = *reinterpret_cast<const float2*>(sp + (int64_t)q * P.N + p0);
+          sin0[q] = w.x;
+          sin1[q] = w.y;
+        }
+      }
+      if (MODE == MODE_ITER) {
+        constitutive<C, MAT>(e0, gg.x, mat, sin0, t0, nullptr, nullptr);
+        constitutive<C, MAT>(e1, gg.y, mat, sin1, t1, nullptr, nullptr);
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c][j] = {t0[c], t1[c]};
+      } else {
+        float s0[S], s1[S], so0[NST], so1[NST];
+        constitutive<C, MAT>(e0, gg.x, mat, sin0, t0, s0, so0);
+        constitutive<C, MAT>(e1, gg.y, mat, sin1, t1, s1, so1);
+        if (MAT == MAT_J2) {
+          float* sp = jstate + off.field[b] * NST;
+#pragma unroll
+          for (int q = 0; q < NST; ++q)
+            *reinterpret_cast<float2*>(sp + (int64_t)q * P.N + p0) = make_float2(so0[q], so1[q]);
+        }
+        if (out_eps) {
+          float* fe = out_eps + off.field[b] * C;
+#pragma unroll
+          for (int c = 0; c < C; ++c) *reinterpret_cast<float2*>(fe + (int64_t)c * P.N + p0) = make_float2(e0[c], e1[c]);
+        }
+        if (out_sig) {
+          float* fs = out_sig + off.field[b] * S;
+#pragma unroll
+          for (int s = 0; s < S; ++s) *reinterpret_cast<float2*>(fs + (int64_t)s * P.N + p0) = make_float2(s0[s], s1[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[s] += (double)s0[s] + (double)s1[s];
+      }
+    }
+  }
+  if (MODE == MODE_FINAL) {
+    __shared__ double red[16];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      double w = block_sum_d(acc[s], red);
+      if (tid == 0) sig_part[(off.part[b] + blockIdx.x) * S + s] = w;
+    }
+    return;
+  }
+  // register pass: first forward stage (radix RL, span 1), then the rest
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    Dft<RL, -1>::run(v[c]);
+    cpx<float>* dst = buf + (c * RB + r) * SS;
+#pragma unroll
+    for (int j = 0; j < RL; ++j) dst[pad16(i * RL + j)] = v[c][j];
+  }
+  __syncthreads();
+  fftr::lds_passes<NH, -1, RL, NSEQ, SS, NT, 2>(buf, T, tid,
+                                                typename fftr::Rev<typename Cfg::RA, RList<>>::type{});
+  for (int t = tid; t < C * nlast * RB; t += NT) {
+    const int rr = t % RB;
+    if (rr >= nr) continue;
+    const int q = t / RB;
+    const int j = q % nlast, c = q / nlast;
+    const int k = lk[j];
+    const cpx<float>* z = buf + (c * RB + rr) * SS;
+    const cpx<float> Zk = z[pad16(k == NH ? 0 : k)];
+    const cpx<float> Zc = cconj(z[pad16(k == 0 ? 0 : NH - k)]);
+    const cpx<float> sm = cadd(Zk, Zc);
+    const cpx<float> wd = cmul(T[k], csub(Zk, Zc));
+    Y[c * cstride + (int64_t)j * rows + r0 + rr] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
+  }
+}
+
+// Column kernel configuration for axis-0 length N0: forward RF (register,
+// from global), then FA...; inverse FA reversed, then RF (register, to
+// global).  CB columns per workgroup, N0/RF threads per sequence.
+template <int C, int N0>
+struct ColCfg;
+template <> struct ColCfg<3, 64>  { static constexpr int RF = 8, CB = 8; using FA = RList<8>; };
+template <> struct ColCfg<3, 128> { static constexpr int RF = 8, CB = 4; using FA = RList<4, 4>; };
+template <> struct ColCfg<3, 256> { static constexpr int RF = 8, CB = 2; using FA = RList<8, 4>; };
+template <> struct ColCfg<3, 384> { static constexpr int RF = 6, CB = 1; using FA = RList<8, 8>; };
+template <> struct ColCfg<3, 512> { static constexpr int RF = 8, CB = 1; using FA = RList<8, 8>; };
+template <> struct ColCfg<6, 64>  { static constexpr int RF = 8, CB = 4; using FA = RList<8>; };
+template <> struct ColCfg<6, 128> { static constexpr int RF = 8, CB = 2; using FA = RList<4, 4>; };
+
+template <int C, int N0>
+constexpr int col_threads() {
+  return ColCfg<C, N0>::CB * C * (N0 / ColCfg<C, N0>::RF);
+}
+template <int N0>
+constexpr int col_ss() {
+  return fftr::seq_stride(N0);
+}
+template <int C, int N0>
+constexpr size_t col_lds_bytes() {
+  return (size_t)(N0 + 2 * C * ColCfg<C, N0>::CB * col_ss<N0>()) * sizeof(cpx<float>);
+}
+
+template <int C, int N0, int MODE>
+__global__ __launch_bounds__((col_threads<C, N0>())) void k_col_fast(
+    const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
+    const double* __restrict__ ebar, cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
+    const cpx<float>* __restrict__ warm, Offs off, double* __restrict__ part, MatDev mat) {
+  using Cfg = ColCfg<C, N0>;
+  constexpr int RF = Cfg::RF, CB = Cfg::CB;
+  constexpr int TS = N0 / RF;
+  constexpr int NT = CB * C * TS;
+  constexpr int NSEQ = C * CB;
+  constexpr int SS = col_ss<N0>();
+  static_assert(NT % 64 == 0, "workgroups are whole wavefronts");
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ int coff[CB + 1];
+  const int tid = threadIdx.x;
+  const int b = rve_list[blockIdx.y];
+  if (MODE == MODE_ITER && !st[b].active) return;
+  const PlanDev& P = plans[st[b].plan];
+  const int ncol = P.ncol;
+  const int j0 = blockIdx.x * CB;
+  if (j0 >= ncol) return;
+  const int ncb = min(CB, ncol - j0);
+  cpx<float>* tw = reinterpret_cast<cpx<float>*>(smem_raw);
+  cpx<float>* fbuf = tw + N0;          // forward result tau^
+  cpx<float>* ibuf = fbuf + NSEQ * SS;  // new coefficients / inverse transform
+  for (int t = tid; t < N0; t += NT) tw[t] = P.tw0[t];
+  for (int t = tid; t < NSEQ * SS; t += NT) ibuf[t] = {0.f, 0.f};
+  if (tid <= CB) coff[tid] = P.col_off[j0 + min(tid, ncb)];
+  // prefetch this thread's first pattern entry (its loads overlap the FFT)
+  const int ncoef = P.ncoef;
+  cpx<float>* co = coef + off.coef[b];
+  const int ebeg = P.col_off[j0], eend = P.col_off[j0 + ncb];
+  int pk0 = 0;
+  uint8_t pfl = 0;
+  float pn[3] = {0.f, 0.f, 0.f};
+  cpx<float> pold[C];
+  if (ebeg + tid < eend) {
+    const int e = ebeg + tid;
+    pk0 = P.coef_k0[e];
+    pfl = P.coef_flag[e];
+    pn[0] = P.coef_n[3 * e];
+    pn[1] = P.coef_n[3 * e + 1];
+    pn[2] = P.coef_n[3 * e + 2];
+    if (MODE == MODE_ITER) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) pold[c] = co[(int64_t)c * ncoef + e];
+    }
+  }
+  cpx<float>* Y = Yc + off.yc[b];
+  const int64_t cstride = (int64_t)ncol * N0;
+  const int s = tid / TS, i = tid % TS;  // sequence s = c * CB + jj
+  const int c_s = s / CB, jj_s = s % CB;
+  const bool col_live = jj_s < ncb;
+  cpx<float>* yline = Y + c_s * cstride + (int64_t)(j0 + jj_s) * N0;
+  if (MODE == MODE_ITER) {
+    cpx<float> v[RF];
+#pragma unroll
+    for (int j = 0; j < RF; ++j) v[j] = col_live ? yline[i + j * TS] : cpx<float>{0.f, 0.f};
+    Dft<RF, -1>::run(v);
+    cpx<float>* dst = fbuf + s * SS;
+#pragma unroll
+    for (int j = 0; j < RF; ++j) dst[pad16(i * RF + j)] = v[j];
+    __syncthreads();
+    fftr::lds_passes<N0, -1, RF, NSEQ, SS, NT, 1>(fbuf, tw, tid, typename Cfg::FA{});
+  } else {
+    __syncthreads();
+  }
+  // step c): Green operator on the block's pattern entries
+  const float invN = P.inv_N;
+  double dsum = 0.0;
+  for (int e = ebeg + tid; e < eend; e += NT) {
+    int jj = 0;
+    while (jj + 1 < ncb && e >= coff[jj + 1]) ++jj;
+    const int j = j0 + jj;
+    const bool first = e == ebeg + tid;
+    const int k0 = first ? pk0 : P.coef_k0[e];
+    const uint8_t fl = first ? pfl : P.coef_flag[e];
+    float nr_[C], ni_[C];
+    if (fl & COEF_ZERO) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        nr_[c] = (float)((double)P.N * ebar[(int64_t)b * C + c]);
+        ni_[c] = 0.f;
+      }
+    } else if (fl & COEF_DEAD) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) nr_[c] = ni_[c] = 0.f;
+    } else if (MODE == MODE_ITER) {
+      float tr_[C], ti_[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const cpx<float> w = fbuf[(c * CB + jj) * SS + pad16(k0)];
+        tr_[c] = w.x;
+        ti_[c] = w.y;
+      }
+      float nv[3];
+      if (first) {
+        nv[0] = pn[0]; nv[1] = pn[1]; nv[2] = pn[2];
+      } else {
+        nv[0] = P.coef_n[3 * e]; nv[1] = P.coef_n[3 * e + 1]; nv[2] = P.coef_n[3 * e + 2];
+      }
+      green<C>(nv, tr_, nr_, mat.g_inv_mu0, mat.g_k);
+      green<C>(nv, ti_, ni_, mat.g_inv_mu0, mat.g_k);
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (warm) {
+          const cpx<float> w = warm[off.coef[b] + (int64_t)c * ncoef + e];
+          nr_[c] = w.x;
+          ni_[c] = w.y;
+        } else {
+          nr_[c] = ni_[c] = 0.f;
+        }
+      }
+    }
+    if (MODE == MODE_ITER) {
+      const int kl = P.last_k[P.col_last[j]];
+      const double wcol = (kl == 0 || 2 * kl == P.nlen) ? 1.0 : 2.0;
+      double d2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const cpx<float> old = first ? pold[c] : co[(int64_t)c * ncoef + e];
+        const double dr = (double)nr_[c] - (double)old.x, di = (double)ni_[c] - (double)old.y;
+        d2 += (double)comp_weight<C>(c) * (dr * dr + di * di);
+      }
+      dsum += wcol * d2;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      co[(int64_t)c * ncoef + e] = {nr_[c], ni_[c]};
+      ibuf[(c * CB + jj) * SS + pad16(k0)] = {nr_[c] * invN, ni_[c] * invN};
+    }
+  }
+  __syncthreads();
+  // step d), axis 0: inverse passes, the last one straight to global memory
+  fftr::lds_passes<N0, +1, 1, NSEQ, SS, NT, 1>(ibuf, tw, tid, typename fftr::Rev<typename Cfg::FA, RList<>>::type{});
+  {
+    cpx<float> v[RF];
+    const cpx<float>* src = ibuf + s * SS;
+#pragma unroll
+    for (int j = 0; j < RF; ++j) v[j] = src[pad16(i + j * TS)];
+    fftr::pass_twiddle<N0, RF, TS, +1>(v, i, tw);
+    Dft<RF, +1>::run(v);
+    if (col_live) {
+#pragma unroll
+      for (int j = 0; j < RF; ++j) yline[i + j * TS] = v[j];
+    }
+  }
+  if (MODE == MODE_ITER) {
+    __shared__ double red[16];
+    const double tot = block_sum_d(dsum, red);
+    if (tid == 0) part[off.part[b] + blockIdx.x] = tot;
+  }
+}
+
+}  // namespace mor_k

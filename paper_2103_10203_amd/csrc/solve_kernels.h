@@ -27,17 +27,6 @@ struct Offs {
   const int64_t* part;   // [B] in the partial-sum array (entries)
 };
 
-struct Prof {
-  unsigned long long* items;  // [PK_COUNT] or null
-  unsigned long long* bytes;  // [PK_COUNT] or null
-};
-
-__device__ __forceinline__ void prof_add(const Prof& p, int k, unsigned long long items, unsigned long long bytes) {
-  if (p.items) {
-    atomicAdd(p.items + k, items);
-    atomicAdd(p.bytes + k, bytes);
-  }
-}
 
 // Strain/stress component helpers.  2D: strain [11,22,12], stress [11,22,12,33];
 // 3D: [11,22,33,23,13,12].
@@ -191,8 +180,7 @@ template <int C, int MODE, int MAT>
 __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
                                              RveState* __restrict__ st, cpx<float>* __restrict__ Yl, Offs off,
                                              MatDev mat, float* __restrict__ jstate, float* __restrict__ out_eps,
-                                             float* __restrict__ out_sig, double* __restrict__ sig_part, int rb,
-                                             Prof prof) {
+                                             float* __restrict__ out_sig, double* __restrict__ sig_part, int rb) {
   extern __shared__ unsigned char smem_raw[];
   constexpr int S = Comp<C>::S;
   constexpr int NST = Comp<C>::NST;
@@ -315,13 +303,6 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
       double v = block_sum_d(acc[s], red);
       if (threadIdx.x == 0) sig_part[(off.part[b] + blockIdx.x) * S + s] = v;
     }
-    if (threadIdx.x == 0) {
-      unsigned long long by = (unsigned long long)nr * (unsigned long long)(16 * C * nlast + P.nlen);
-      if (out_eps) by += (unsigned long long)nr * P.nlen * 4ull * C;
-      if (out_sig) by += (unsigned long long)nr * P.nlen * 4ull * S;
-      if (MAT == MAT_J2) by += (unsigned long long)nr * P.nlen * 8ull * NST;
-      prof_add(prof, PK_FINAL, nr, by);
-    }
     return;
   }
   __syncthreads();
@@ -338,11 +319,6 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
     const cpx<float> wd = cmul(rtw[k], csub(Zk, Zc));
     Y[c * cstride + (int64_t)j * rows + r0 + r] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
   }
-  if (threadIdx.x == 0) {
-    unsigned long long by = (unsigned long long)nr * (unsigned long long)(16 * C * nlast + P.nlen);
-    if (MAT == MAT_J2) by += (unsigned long long)nr * P.nlen * 4ull * NST;
-    prof_add(prof, PK_ROW, nr, by);
-  }
 }
 
 // ------------------------------------------------------------------ column kernel
@@ -354,8 +330,7 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
                                              RveState* __restrict__ st, const double* __restrict__ ebar,
                                              cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
                                              const cpx<float>* __restrict__ warm, Offs off,
-                                             double* __restrict__ part, MatDev mat, int cb,
-                                             unsigned int* __restrict__ active_count, Prof prof) {
+                                             double* __restrict__ part, MatDev mat, int cb) {
   extern __shared__ unsigned char smem_raw[];
   const int b = rve_list[blockIdx.y];
   if (MODE == MODE_ITER && !st[b].active) return;
@@ -463,44 +438,7 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
   if (MODE == MODE_ITER) {
     __shared__ double red[16];
     const double tot = block_sum_d(dsum, red);
-    if (threadIdx.x == 0) {
-      const int e0 = P.col_off[j0], e1 = P.col_off[j0 + ncb];
-      prof_add(prof, PK_COL, ncb,
-               (unsigned long long)ncb * 16ull * C * n0 + (unsigned long long)(e1 - e0) * (16ull * C + 17ull));
-      const int nblk = (ncol + cb - 1) / cb;
-      part[off.part[b] + blockIdx.x] = tot;
-      __threadfence();
-      const unsigned prev = atomicAdd(&st[b].counter, 1u);
-      if (prev == (unsigned)(nblk - 1)) {
-        __threadfence();
-        double sum = 0.0;
-        const volatile double* pp = part + off.part[b];
-        for (int i = 0; i < nblk; ++i) sum += pp[i];
-        st[b].counter = 0u;
-        const double r = sqrt(sum) / st[b].denom;
-        const int it = st[b].iters + 1;
-        st[b].iters = it;
-        st[b].resid = r;
-        int done = 0;
-        if (!(r == r) || isinf(r)) {
-          st[b].status = MOR_E_NONFINITE;
-          done = 1;
-        } else if (r < st[b].tol) {
-          st[b].status = MOR_OK;
-          done = 1;
-        } else if (it >= st[b].max_iter) {
-          st[b].status = MOR_E_NOT_CONVERGED;
-          done = 1;
-        }
-        if (done) {
-          st[b].active = 0;
-          atomicSub(active_count, 1u);
-        }
-        __threadfence();
-      }
-    }
-  } else {
-    if (threadIdx.x == 0) prof_add(prof, PK_INIT, ncb, (unsigned long long)ncb * 8ull * C * n0);
+    if (threadIdx.x == 0) part[off.part[b] + blockIdx.x] = tot;
   }
 }
 
@@ -511,8 +449,7 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
 template <int C, int DIR>
 __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
                                              RveState* __restrict__ st, cpx<float>* __restrict__ Yl,
-                                             cpx<float>* __restrict__ Yc, Offs off, int xb, int check_active,
-                                             Prof prof) {
+                                             cpx<float>* __restrict__ Yc, Offs off, int xb, int check_active) {
   extern __shared__ unsigned char smem_raw[];
   const int b = rve_list[blockIdx.z];
   if (check_active && !st[b].active) return;
@@ -571,12 +508,43 @@ __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, 
       L[c * lcs + (int64_t)j2 * rows + (int64_t)(x00 + xi) * n1 + x1] = R[(c * xb + xi) * n1 + x1];
     }
   }
-  if (threadIdx.x == 0)
-    prof_add(prof, DIR < 0 ? PK_MIDF : PK_MIDI, nx,
-             (unsigned long long)nx * 8ull * C * (n1 + ng));
 }
 
-// Per-RVE FP64 sum of the stress partials, fixed order.
+// Convergence decision after a column pass (one thread per RVE): FP64 sum of
+// the column blocks' squared coefficient changes in a fixed order, Parseval
+// residual r = sqrt(sum) / (N ||eps_bar||_F), and the stop rules.
+__global__ void k_converge(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, int nrve,
+                           RveState* __restrict__ st, const double* __restrict__ part, Offs off, int cb,
+                           unsigned int* __restrict__ active_count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrve) return;
+  const int b = rve_list[i];
+  RveState& S = st[b];
+  if (!S.active) return;
+  const int nblk = (plans[S.plan].ncol + cb - 1) / cb;
+  double sum = 0.0;
+  for (int q = 0; q < nblk; ++q) sum += part[off.part[b] + q];
+  const double r = sqrt(sum) / S.denom;
+  const int it = S.iters + 1;
+  S.iters = it;
+  S.resid = r;
+  int done = 0;
+  if (!(r == r) || isinf(r)) {
+    S.status = MOR_E_NONFINITE;
+    done = 1;
+  } else if (r < S.tol) {
+    S.status = MOR_OK;
+    done = 1;
+  } else if (it >= S.max_iter) {
+    S.status = MOR_E_NOT_CONVERGED;
+    done = 1;
+  }
+  if (done) {
+    S.active = 0;
+    atomicSub(active_count, 1u);
+  }
+}
+
 // Per-RVE grid mean of the stress: FP64 sum of the block partials in a fixed
 // order, divided by N (paper Sec. 2, volume average).
 template <int S>

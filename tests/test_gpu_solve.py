@@ -150,3 +150,32 @@ def test_deterministic_rerun():
     a = mor.solve(plan, np.array([eb]), native_phases(), 1e-6)
     b = mor.solve(plan, np.array([eb]), native_phases(), 1e-6)
     assert np.array_equal(a.eff_stress, b.eff_stress) and np.array_equal(a.residual, b.residual)
+
+
+@pytest.mark.parametrize("n,R", [(384, 0.05), (512, 0.01), (128, 0.2)])
+def test_other_grid_sizes(n, R):
+    mor = _mor()
+    g = synth.rsa_fibres(n, n, n / 32, n / 16, seed=70 + n, target_vf=0.35).g
+    M = int(math.ceil(R * g.size))
+    eb = [2e-3, -1e-3, 1.5e-3]
+    plan = mor.Plan(g, M)
+    out = mor.solve(plan, np.array([eb]), native_phases(), 1e-6)
+    _, ref = oracle_reduced(g, eb, M, tol=1e-10)
+    sref = stress_comps(ref.sigma_bar, 2)
+    assert np.max(np.abs(out.eff_stress[0] - sref)) / np.max(np.abs(sref)) < 1e-5
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 64, 64), (64, 32, 128)])
+def test_3d_parity(shape):
+    mor = _mor()
+    g = synth.rsa_spheres(*shape, r_lo=min(shape) / 8, r_hi=min(shape) / 5, seed=sum(shape), target_vf=0.2).g
+    M = int(math.ceil(0.03 * g.size))
+    eb = [1e-3, -4e-4, 3e-4, 2e-4, -1e-4, 5e-4]
+    plan = mor.Plan(g, M)
+    out = mor.solve(plan, np.array([eb]), native_phases(), 1e-6, want_fields=True)
+    assert out.status == mor.MOR_OK
+    _, ref = oracle_reduced(g, eb, M, tol=1e-10)
+    sref = stress_comps(ref.sigma_bar, 3)
+    assert np.max(np.abs(out.eff_stress[0] - sref)) / np.max(np.abs(sref)) < 1e-5
+    e_ref, s_ref = _fields_from_oracle(ref, 3)
+    assert rel_l2(out.strain[0].cpu().numpy(), e_ref) < 1e-4
