@@ -13,7 +13,7 @@
 #include <stdint.h>
 
 template <typename T>
-struct cpx {
+struct alignas(2 * sizeof(T)) cpx {
   T x, y;
 };
 

@@ -159,11 +159,11 @@ __host__ __device__ constexpr int seq_stride(int len) {
   return (pad16(len - 1) + 1) | 1;
 }
 
-// Twiddle w^{e} from a table tw[t] = exp(-2 pi i t / (N * TWS)), read at
-// stride TWS (conjugated for SIGN > 0).
+// Twiddle w^{e} from a padded LDS table tw[pad16(t)] = exp(-2 pi i t / (N * TWS)),
+// read at stride TWS (conjugated for SIGN > 0).
 template <int SIGN, int TWS>
 __device__ __forceinline__ cpx<float> twid(const cpx<float>* tw, int e) {
-  cpx<float> w = tw[e * TWS];
+  cpx<float> w = tw[pad16(e * TWS)];  // tables are stored padded, like the data
   return SIGN > 0 ? cconj(w) : w;
 }
 

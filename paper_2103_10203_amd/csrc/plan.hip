@@ -125,7 +125,7 @@ __global__ void k_g_to_cplx(const uint8_t* __restrict__ g, cpx<double>* __restri
 // [outer][na][inner]; `lpw` lines per workgroup.
 __global__ void k_fft_axis_f64(cpx<double>* __restrict__ S, int outer, int na, int inner, int lpw, FftDesc fd,
                                const cpx<double>* __restrict__ tw) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   cpx<double>* twl = reinterpret_cast<cpx<double>*>(smem_raw);
   cpx<double>* A = twl + na;
   cpx<double>* B = A + lpw * na;
@@ -209,7 +209,7 @@ __global__ void k_bitonic_global(SortEl* el, int64_t n, int64_t k, int64_t j) {
 // kmin == 0: full local sort of each tile (k = 2 .. tile).  Otherwise: merge
 // steps j = tile/2 .. 1 for the given k.
 __global__ void k_bitonic_local(SortEl* el, int tile, int64_t kglob) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   SortEl* s = reinterpret_cast<SortEl*>(smem_raw);
   const int64_t base = (int64_t)blockIdx.x * tile;
   for (int t = threadIdx.x; t < tile; t += blockDim.x) s[t] = el[base + t];

@@ -19,14 +19,14 @@ using fftr::RList;
 // reversed.  RB rows per workgroup, NH/RL threads per row.
 template <int C, int NH>
 struct RowCfg;
-template <> struct RowCfg<3, 32>  { static constexpr int RL = 8, RB = 48; using RA = RList<4>; };
-template <> struct RowCfg<3, 64>  { static constexpr int RL = 8, RB = 24; using RA = RList<8>; };
-template <> struct RowCfg<3, 128> { static constexpr int RL = 8, RB = 12; using RA = RList<4, 4>; };
-template <> struct RowCfg<3, 192> { static constexpr int RL = 8, RB = 8;  using RA = RList<4, 3, 2>; };
-template <> struct RowCfg<3, 256> { static constexpr int RL = 8, RB = 6;  using RA = RList<4, 8>; };
-template <> struct RowCfg<6, 32>  { static constexpr int RL = 8, RB = 16; using RA = RList<4>; };
-template <> struct RowCfg<6, 64>  { static constexpr int RL = 8, RB = 8;  using RA = RList<8>; };
-template <> struct RowCfg<6, 128> { static constexpr int RL = 8, RB = 4;  using RA = RList<4, 4>; };
+template <> struct RowCfg<3, 32>  { static constexpr int RL = 4, RB = 48; using RA = RList<8>; };
+template <> struct RowCfg<3, 64>  { static constexpr int RL = 4, RB = 24; using RA = RList<4, 4>; };
+template <> struct RowCfg<3, 128> { static constexpr int RL = 4, RB = 12; using RA = RList<8, 4>; };
+template <> struct RowCfg<3, 192> { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4, 3>; };
+template <> struct RowCfg<3, 256> { static constexpr int RL = 4, RB = 6;  using RA = RList<8, 8>; };
+template <> struct RowCfg<6, 32>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
+template <> struct RowCfg<6, 64>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
+template <> struct RowCfg<6, 128> { static constexpr int RL = 4, RB = 4;  using RA = RList<8, 4>; };
 
 template <int C, int NH>
 constexpr int row_threads() {
@@ -36,9 +36,13 @@ template <int NH>
 constexpr int row_ss() {
   return fftr::seq_stride(NH + 1);  // NH + 1 spectrum slots (Nyquist included)
 }
+template <int NH>
+constexpr int row_tw_len() {
+  return pad16(2 * NH - 1) + 1;  // padded table of exp(-2 pi i t / (2 NH))
+}
 template <int C, int NH>
 constexpr size_t row_lds_bytes() {
-  return (size_t)(2 * NH + C * RowCfg<C, NH>::RB * row_ss<NH>()) * sizeof(cpx<float>);
+  return (size_t)(row_tw_len<NH>() + C * RowCfg<C, NH>::RB * row_ss<NH>()) * sizeof(cpx<float>);
 }
 
 template <int C, int NH, int MODE, int MAT>
@@ -56,7 +60,7 @@ __global__ __launch_bounds__((row_threads<C, NH>())) void k_row_fast(
   constexpr int NST = Comp<C>::NST;
   constexpr int L = 2 * NH;
   static_assert(NT % 64 == 0, "workgroups are whole wavefronts");
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ int lk[NH + 1];
   const int tid = threadIdx.x;
   const int b = rve_list[blockIdx.y];
@@ -69,31 +73,39 @@ __global__ __launch_bounds__((row_threads<C, NH>())) void k_row_fast(
   // T[t] = exp(-2 pi i t / L): the real-FFT twiddles are T[k], the length-NH
   // FFT twiddles are T[2 e].
   cpx<float>* T = reinterpret_cast<cpx<float>*>(smem_raw);
-  cpx<float>* buf = T + L;
+  cpx<float>* buf = T + row_tw_len<NH>();
   const int nlast = P.nlast;
-  for (int t = tid; t < L; t += NT) T[t] = P.rtw[t];
+  for (int t = tid; t < L; t += NT) T[pad16(t)] = P.rtw[t];
   for (int t = tid; t < nlast; t += NT) lk[t] = P.last_k[t];
   for (int t = tid; t < NSEQ * SS; t += NT) buf[t] = {0.f, 0.f};
   __syncthreads();
   cpx<float>* Y = Yl + off.yl[b];
   const int64_t cstride = (int64_t)nlast * rows;
   // gather the row block's last-axis spectra; U independent loads in flight
+  // thread (r = tid % RB, q0 = tid / RB) walks q = c * nlast + j in steps of
+  // NT / RB, keeping (c, j) incrementally
+  static_assert(NT % RB == 0, "row block divides the workgroup");
+  constexpr int QS = NT / RB;
+  const int rg = tid % RB;
+  const bool rlive = rg < nr;
   {
     constexpr int U = 4;
-    const int tot = C * nlast * RB;
-    for (int t0 = tid; t0 < tot; t0 += NT * U) {
+    const int qtot = C * nlast;
+    int j = tid / RB, c = 0;
+    while (j >= nlast && c < C) { j -= nlast; ++c; }
+    const cpx<float>* ysrc = Y + r0 + rg;
+    for (int q0 = tid / RB; q0 < qtot; q0 += QS * U) {
       cpx<float> val[U];
       int dst[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int t = t0 + u * NT;
-        const int r = t % RB, q = t / RB;
         dst[u] = -1;
-        if (t < tot && r < nr) {
-          const int j = q % nlast, c = q / nlast;
-          val[u] = Y[c * cstride + (int64_t)j * rows + r0 + r];
-          dst[u] = (c * RB + r) * SS + pad16(lk[j]);
+        if (c < C && rlive) {
+          val[u] = ysrc[(int64_t)c * cstride + (int64_t)j * rows];
+          dst[u] = (c * RB + rg) * SS + pad16(lk[j]);
         }
+        j += QS;
+        while (j >= nlast && c < C) { j -= nlast; ++c; }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -109,13 +121,13 @@ __global__ __launch_bounds__((row_threads<C, NH>())) void k_row_fast(
     cpx<float>* x = buf + q * SS;
     const cpx<float> Xk = x[pad16(k)], Xm = x[pad16(NH - k)];
     const cpx<float> a = cadd(Xk, cconj(Xm));
-    const cpx<float> d = cmul(csub(Xk, cconj(Xm)), cconj(T[k]));
+    const cpx<float> d = cmul(csub(Xk, cconj(Xm)), cconj(T[pad16(k)]));
     const cpx<float> zk = {a.x - d.y, a.y + d.x};
     if (k == 0 || 2 * k == NH) {
       x[pad16(k)] = zk;
     } else {
       const cpx<float> a2 = cadd(Xm, cconj(Xk));
-      const cpx<float> d2 = cmul(csub(Xm, cconj(Xk)), cconj(T[NH - k]));
+      const cpx<float> d2 = cmul(csub(Xm, cconj(Xk)), cconj(T[pad16(NH - k)]));
       x[pad16(k)] = zk;
       x[pad16(NH - k)] = {a2.x - d2.y, a2.y + d2.x};
     }
@@ -214,18 +226,22 @@ __global__ __launch_bounds__((row_threads<C, NH>())) void k_row_fast(
   __syncthreads();
   fftr::lds_passes<NH, -1, RL, NSEQ, SS, NT, 2>(buf, T, tid,
                                                 typename fftr::Rev<typename Cfg::RA, RList<>>::type{});
-  for (int t = tid; t < C * nlast * RB; t += NT) {
-    const int rr = t % RB;
-    if (rr >= nr) continue;
-    const int q = t / RB;
-    const int j = q % nlast, c = q / nlast;
-    const int k = lk[j];
-    const cpx<float>* z = buf + (c * RB + rr) * SS;
-    const cpx<float> Zk = z[pad16(k == NH ? 0 : k)];
-    const cpx<float> Zc = cconj(z[pad16(k == 0 ? 0 : NH - k)]);
-    const cpx<float> sm = cadd(Zk, Zc);
-    const cpx<float> wd = cmul(T[k], csub(Zk, Zc));
-    Y[c * cstride + (int64_t)j * rows + r0 + rr] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
+  if (rlive) {
+    const int qtot = C * nlast;
+    int j = tid / RB, c = 0;
+    while (j >= nlast && c < C) { j -= nlast; ++c; }
+    cpx<float>* ydst = Y + r0 + rg;
+    for (int q = tid / RB; q < qtot; q += QS) {
+      const int k = lk[j];
+      const cpx<float>* z = buf + (c * RB + rg) * SS;
+      const cpx<float> Zk = z[pad16(k == NH ? 0 : k)];
+      const cpx<float> Zc = cconj(z[pad16(k == 0 ? 0 : NH - k)]);
+      const cpx<float> sm = cadd(Zk, Zc);
+      const cpx<float> wd = cmul(T[pad16(k)], csub(Zk, Zc));
+      ydst[(int64_t)c * cstride + (int64_t)j * rows] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
+      j += QS;
+      while (j >= nlast && c < C) { j -= nlast; ++c; }
+    }
   }
 }
 
@@ -252,7 +268,7 @@ constexpr int col_ss() {
 }
 template <int C, int N0>
 constexpr size_t col_lds_bytes() {
-  return (size_t)(N0 + 2 * C * ColCfg<C, N0>::CB * col_ss<N0>()) * sizeof(cpx<float>);
+  return (size_t)(pad16(N0 - 1) + 1 + 2 * C * ColCfg<C, N0>::CB * col_ss<N0>()) * sizeof(cpx<float>);
 }
 
 template <int C, int N0, int MODE>
@@ -267,7 +283,7 @@ __global__ __launch_bounds__((col_threads<C, N0>())) void k_col_fast(
   constexpr int NSEQ = C * CB;
   constexpr int SS = col_ss<N0>();
   static_assert(NT % 64 == 0, "workgroups are whole wavefronts");
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ int coff[CB + 1];
   const int tid = threadIdx.x;
   const int b = rve_list[blockIdx.y];
@@ -278,9 +294,9 @@ __global__ __launch_bounds__((col_threads<C, N0>())) void k_col_fast(
   if (j0 >= ncol) return;
   const int ncb = min(CB, ncol - j0);
   cpx<float>* tw = reinterpret_cast<cpx<float>*>(smem_raw);
-  cpx<float>* fbuf = tw + N0;          // forward result tau^
-  cpx<float>* ibuf = fbuf + NSEQ * SS;  // new coefficients / inverse transform
-  for (int t = tid; t < N0; t += NT) tw[t] = P.tw0[t];
+  cpx<float>* fbuf = tw + pad16(N0 - 1) + 1;  // forward result tau^
+  cpx<float>* ibuf = fbuf + NSEQ * SS;         // new coefficients / inverse transform
+  for (int t = tid; t < N0; t += NT) tw[pad16(t)] = P.tw0[t];
   for (int t = tid; t < NSEQ * SS; t += NT) ibuf[t] = {0.f, 0.f};
   if (tid <= CB) coff[tid] = P.col_off[j0 + min(tid, ncb)];
   // prefetch this thread's first pattern entry (its loads overlap the FFT)

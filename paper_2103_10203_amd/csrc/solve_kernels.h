@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
                                              RveState* __restrict__ st, cpx<float>* __restrict__ Yl, Offs off,
                                              MatDev mat, float* __restrict__ jstate, float* __restrict__ out_eps,
                                              float* __restrict__ out_sig, double* __restrict__ sig_part, int rb) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   constexpr int S = Comp<C>::S;
   constexpr int NST = Comp<C>::NST;
   const int b = rve_list[blockIdx.y];
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
                                              cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
                                              const cpx<float>* __restrict__ warm, Offs off,
                                              double* __restrict__ part, MatDev mat, int cb) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int b = rve_list[blockIdx.y];
   if (MODE == MODE_ITER && !st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
@@ -450,7 +450,7 @@ template <int C, int DIR>
 __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
                                              RveState* __restrict__ st, cpx<float>* __restrict__ Yl,
                                              cpx<float>* __restrict__ Yc, Offs off, int xb, int check_active) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int b = rve_list[blockIdx.z];
   if (check_active && !st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
