@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--single", type=int, default=32, help="RVEs timed one launch each (plain path)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -158,6 +160,15 @@ def main():
             mor.solve(plans[i], ebs[i:i + 1], ph, TOL)
         torch.cuda.synchronize()
         single = ns / (time.perf_counter() - t)
+
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     line = {
         "metric": METRIC,

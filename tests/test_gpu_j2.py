@@ -1,0 +1,57 @@
+"""GPU parity of the elasto-plastic load path (paper Sec. 2 J2 model; load
+steps as in Sec. 5.2) against the FP64 oracle: effective stress per step and
+the accumulated plastic strain field after the last step.
+
+FP32 radial return near the yield surface can flip single points between
+elastic and plastic relative to FP64; the tolerances are therefore 1e-4
+(effective stress) and 1e-3 (rel. L2 of the accumulated plastic strain)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import pattern, solver
+from tests.gpu_common import ORACLE_J2, native_phases, rel_l2, stress_comps
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,R,steps", [(64, 0.05, 5), (128, 0.05, 4)])
+def test_load_path_matches_oracle(n, R, steps):
+    import torch
+    import paper_2103_10203_amd as mor
+    g = synth.rsa_fibres(n, n, n / 12.8, n / 6.4, seed=11 + n, target_vf=0.4).g
+    M = int(math.ceil(R * g.size))
+    final = np.array([0.02, 0.0, 0.0])
+    path = np.stack([final * (k + 1) / steps for k in range(steps)])
+    plan = mor.Plan(g, M)
+    state = torch.zeros(5 * g.size, dtype=torch.float32, device="cuda")
+    out = mor.solve_path(plan, path, native_phases(j2=True), 1e-6, state)
+    assert out.status == mor.MOR_OK
+    p = pattern.build_pattern(g, M)
+    ref = solver.solve_path(g, ORACLE_J2, solver.macro_tensor(final, 2), steps, mask=p.mask(), tol=1e-10)
+    for k in range(steps):
+        want = stress_comps(ref[k].sigma_bar, 2)
+        err = np.max(np.abs(out.eff_stress[k] - want)) / np.max(np.abs(want))
+        assert err < 1e-4, (k, err)
+    alpha = state.view(5, n, n)[4].double().cpu().numpy()
+    assert rel_l2(alpha, ref[-1].alpha) < 1e-3
+    ep = state.view(5, n, n)[0].double().cpu().numpy()
+    assert rel_l2(ep, ref[-1].eps_p[..., 0, 0]) < 1e-3
+    assert np.max(alpha) > 0.0
+
+
+def test_homogeneous_j2_one_iteration_per_step():
+    import torch
+    import paper_2103_10203_amd as mor
+    g = np.zeros((32, 32), np.uint8)
+    plan = mor.Plan(g, 51)
+    path = np.stack([[0.004 * k, 0.0, 0.0] for k in range(1, 6)])
+    state = torch.zeros(5 * g.size, dtype=torch.float32, device="cuda")
+    out = mor.solve_path(plan, path, native_phases(j2=True), 1e-6, state)
+    assert np.all(out.iterations == 1)
+    ref = solver.solve_path(g, ORACLE_J2, solver.macro_tensor([0.02, 0, 0], 2), 5, tol=1e-12)
+    for k in range(5):
+        want = stress_comps(ref[k].sigma_bar, 2)
+        assert np.max(np.abs(out.eff_stress[k] - want)) < 1e-5 * np.max(np.abs(want))
