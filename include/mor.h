@@ -212,6 +212,66 @@ mor_status mor_solve_path(mor_plan_t plan, const double* macro_strain, int32_t s
                           const mor_phase phase[2], double tol, const mor_solve_opts* opts,
                           float* state, mor_outputs* out);
 
+/* ----------------------------------------------------------------------
+ * Learned warm start (an addition to the paper's method).  A 3-layer
+ * perceptron x -> relu(x W1 + b1) -> relu(. W2 + b2) -> . W3 + b3 maps
+ * features of a microstructure's adapted pattern to the per-unit-macro-strain
+ * strain response at the pattern's first `nslots` conjugate pairs ("slots",
+ * rank order, xi = 0 excluded).  The network learns the correction to the
+ * first-order (Born) term  -Gamma^0(n) : ((C_I - C_M) : e_k) g^(xi)  with the
+ * solver's reference medium C0 (mean Lame constants) -- the coefficients that
+ * the cold start's first iteration produces -- so a zero network output
+ * reproduces one cold iteration.  Its prediction only seeds the fixed-point
+ * iteration, which still runs to tolerance (2D plans only).
+ *
+ * Layouts (row-major, FP32):
+ *   features X [B][4*nslots + 1]: Re g^/count, Im g^/count of every slot's
+ *     pair representative, then its signed frequency (k0/n0, k1/n1), then the
+ *     inclusion volume fraction; zeros beyond the plan's slot count.
+ *   targets / prediction Y [B][nslots][3 strain comps][3 unit macro strains]
+ *     [re, im]: eps^(rep)[c] / N for the unit macro strain e_k, minus its
+ *     Born term.
+ *   phase[2]: the solve's phases (phase[0] matrix, phase[1] inclusion); they
+ *     fix the Born term.  MOR_E_INVALID_ARG if the mean medium has mu0 <= 0.
+ *   parameters: W1 [in][hid], b1 [hid], W2 [hid][hid], b2 [hid], W3 [hid][out], b3 [out].
+ * ---------------------------------------------------------------------- */
+typedef struct mor_mlp* mor_mlp_t;
+enum { MOR_MLP_FP32 = 0, MOR_MLP_BF16 = 1 };
+
+/* He-uniform weights from `seed`, zero biases, zero Adam moments. */
+mor_status mor_mlp_create(int32_t in_dim, int32_t hidden, int32_t out_dim, uint64_t seed, mor_mlp_t* out);
+mor_status mor_mlp_destroy(mor_mlp_t net);
+mor_status mor_mlp_num_params(mor_mlp_t net, int64_t* count);
+/* Copy parameters (which = 0), last gradients (1), Adam first (2) or second
+ * (3) moments to/from host memory, `count` = mor_mlp_num_params. */
+mor_status mor_mlp_get_params(mor_mlp_t net, float* host, int64_t count, int32_t which);
+mor_status mor_mlp_set_params(mor_mlp_t net, const float* host, int64_t count, int32_t which);
+/* Y [B][out] = network(X [B][in]); device pointers; precision MOR_MLP_FP32 or
+ * MOR_MLP_BF16 (weights and activations rounded to bfloat16, FP32 accumulate). */
+mor_status mor_mlp_forward(mor_mlp_t net, const float* X, int64_t B, float* Y, int32_t precision, void* stream);
+/* FP32 forward + analytic backward of loss = sum (Y - T)^2 / (B * out);
+ * gradients are kept in the network; *loss (host, may be NULL) receives the
+ * loss (synchronises the stream when non-NULL). */
+mor_status mor_mlp_grad(mor_mlp_t net, const float* X, const float* T, int64_t B, double* loss, void* stream);
+/* One Adam step with the stored gradients (bias-corrected, step counter kept). */
+mor_status mor_mlp_adam(mor_mlp_t net, float lr, float beta1, float beta2, float eps, void* stream);
+/* Network inputs for B RVEs (RVE b uses plans[plan_of[b]], host arrays). */
+mor_status mor_warm_features(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of, int64_t B,
+                             int32_t nslots, float* X, void* stream);
+/* Training targets from converged coefficients of the three unit macro
+ * strains per RVE: coeffs device complex64, packed per RVE as
+ * [3 unit strains][3 comps][n_coeff] (the layout of mor_solve_multi's
+ * coefficient output for RVEs ordered (b, k)). */
+mor_status mor_warm_targets(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of, int64_t B,
+                            int32_t nslots, const mor_phase phase[2], const float* coeffs, float* T, void* stream);
+/* Warm-start coefficients eps^ = N sum_k (Born[..][k] + Y[..][k]) macro_strain[k]
+ * (host double [B][3]) in the solver's packed coefficient layout (device complex64
+ * [B][3][n_coeff]); coefficients without a slot are zero.  The solver
+ * projects a warm start onto compatible strains before iterating. */
+mor_status mor_warm_apply(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of, int64_t B, int32_t nslots,
+                          const mor_phase phase[2], const float* Y, const double* macro_strain, float* warm,
+                          void* stream);
+
 /* Per-kernel timing over solves while enabled: HIP events bracket every launch
  * of the named kernel on the solve stream; `items` counts the work units the
  * launches processed (converged RVEs exit early and are not counted) and

@@ -90,6 +90,21 @@ _SIGS = {
     "mor_profile_reset": (ct.c_int, []),
     "mor_profile_query": (ct.c_int, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64),
                                      ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]),
+    "mor_mlp_create": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_uint64, ct.POINTER(ct.c_void_p)]),
+    "mor_mlp_destroy": (ct.c_int, [ct.c_void_p]),
+    "mor_mlp_num_params": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_int64)]),
+    "mor_mlp_get_params": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32]),
+    "mor_mlp_set_params": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32]),
+    "mor_mlp_forward": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int32, ct.c_void_p]),
+    "mor_mlp_grad": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_double),
+                                ct.c_void_p]),
+    "mor_mlp_adam": (ct.c_int, [ct.c_void_p, ct.c_float, ct.c_float, ct.c_float, ct.c_float, ct.c_void_p]),
+    "mor_warm_features": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p,
+                                     ct.c_void_p]),
+    "mor_warm_targets": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p,
+                                    ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "mor_warm_apply": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p,
+                                  ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "mor_last_error": (ct.c_char_p, []),
     "mor_version": (ct.c_char_p, []),
 }
@@ -337,3 +352,112 @@ def profile_query(kernel: str):
 
 def version() -> str:
     return lib.mor_version().decode()
+
+
+# ---------------------------------------------------------------- warm-start network
+MLP_FP32 = 0
+MLP_BF16 = 1
+
+
+class MLP:
+    """The library's 3-layer perceptron (mor_mlp_*): FP32 parameters on the device."""
+
+    def __init__(self, in_dim: int, hidden: int, out_dim: int, seed: int = 0):
+        h = ct.c_void_p()
+        _check(lib.mor_mlp_create(int(in_dim), int(hidden), int(out_dim), int(seed), ct.byref(h)))
+        self._h = h
+        self.in_dim, self.hidden, self.out_dim = int(in_dim), int(hidden), int(out_dim)
+        n = ct.c_int64()
+        _check(lib.mor_mlp_num_params(self._h, ct.byref(n)))
+        self.num_params = n.value
+
+    def _get(self, which):
+        out = np.zeros(self.num_params, np.float32)
+        _check(lib.mor_mlp_get_params(self._h, _np_ptr(out), self.num_params, which))
+        return out
+
+    def params(self):
+        return self._get(0)
+
+    def grads(self):
+        return self._get(1)
+
+    def adam_moments(self):
+        return self._get(2), self._get(3)
+
+    def set_params(self, flat, which: int = 0):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib.mor_mlp_set_params(self._h, _np_ptr(a), self.num_params, which))
+
+    def split(self, flat):
+        """[W1, b1, W2, b2, W3, b3] views of a flat parameter vector."""
+        i, h, o = self.in_dim, self.hidden, self.out_dim
+        sizes = [(i, h), (h,), (h, h), (h,), (h, o), (o,)]
+        out, k = [], 0
+        for sh in sizes:
+            n = int(np.prod(sh))
+            out.append(flat[k:k + n].reshape(sh))
+            k += n
+        return out
+
+    def forward(self, X, precision: int = MLP_FP32, stream=None):
+        torch = _torch()
+        B = X.shape[0]
+        Y = torch.empty((B, self.out_dim), dtype=torch.float32, device=X.device)
+        _check(lib.mor_mlp_forward(self._h, ct.c_void_p(X.data_ptr()), B, ct.c_void_p(Y.data_ptr()),
+                                   precision, _stream_ptr(stream)))
+        return Y
+
+    def grad(self, X, T, stream=None) -> float:
+        loss = ct.c_double()
+        _check(lib.mor_mlp_grad(self._h, ct.c_void_p(X.data_ptr()), ct.c_void_p(T.data_ptr()), X.shape[0],
+                                ct.byref(loss), _stream_ptr(stream)))
+        return loss.value
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib.mor_mlp_adam(self._h, float(lr), float(beta1), float(beta2), float(eps), _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.mor_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _plan_array(plans):
+    return (ct.c_void_p * len(plans))(*[p.handle.value for p in plans])
+
+
+def warm_features(plans, plan_of, nslots: int, stream=None):
+    torch = _torch()
+    po = np.ascontiguousarray(plan_of, dtype=np.int64)
+    X = torch.empty((len(po), 4 * nslots + 1), dtype=torch.float32, device="cuda")
+    _check(lib.mor_warm_features(_plan_array(plans), len(plans), _np_ptr(po), len(po), nslots,
+                                 ct.c_void_p(X.data_ptr()), _stream_ptr(stream)))
+    return X
+
+
+def warm_targets(plans, plan_of, nslots: int, phases, coeffs, stream=None):
+    torch = _torch()
+    po = np.ascontiguousarray(plan_of, dtype=np.int64)
+    T = torch.empty((len(po), 18 * nslots), dtype=torch.float32, device="cuda")
+    _check(lib.mor_warm_targets(_plan_array(plans), len(plans), _np_ptr(po), len(po), nslots, _phases(phases),
+                                ct.c_void_p(coeffs.data_ptr()), ct.c_void_p(T.data_ptr()), _stream_ptr(stream)))
+    return T
+
+
+def warm_apply(plans, plan_of, nslots: int, phases, Y, macro_strain, stream=None):
+    torch = _torch()
+    po = np.ascontiguousarray(plan_of, dtype=np.int64)
+    eb = np.ascontiguousarray(macro_strain, dtype=np.float64)
+    n = int(sum(plans[i].n_coeff for i in po)) * 3
+    W = torch.empty(n, dtype=torch.complex64, device="cuda")
+    _check(lib.mor_warm_apply(_plan_array(plans), len(plans), _np_ptr(po), len(po), nslots, _phases(phases),
+                              ct.c_void_p(Y.data_ptr()), _np_ptr(eb), ct.c_void_p(W.data_ptr()),
+                              _stream_ptr(stream)))
+    return W

@@ -86,6 +86,11 @@ struct mor_plan {
   cpx<float>* d_tw = nullptr;    // tw0 | tw1 | twh | rtw
   PlanDev* d_dev = nullptr;      // device copy of `dev`
   PlanDev dev{};
+  // warm-start network tables: slot s = selected pair s+1 in rank order
+  int64_t nslots = 0;
+  int64_t* d_slot_rep = nullptr;     // [nslots] linear index of the pair representative
+  cpx<float>* d_slot_ghat = nullptr; // [nslots] g^(rep) / inclusion count
+  int32_t* d_coef_slot = nullptr;    // [ncoef] slot of the coefficient (-1: xi = 0), bit 30: conjugate member
 };
 
 // ---------------------------------------------------------------- solve

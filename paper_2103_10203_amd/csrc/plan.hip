@@ -236,9 +236,11 @@ __global__ void k_bitonic_local(SortEl* el, int tile, int64_t kglob) {
   for (int t = threadIdx.x; t < tile; t += blockDim.x) el[base + t] = s[t];
 }
 
-// Pair-atomic selection in rank order (single workgroup).
+// Pair-atomic selection in rank order (single workgroup).  Also records, for
+// every selected frequency, its pair index in rank order (bit 30 set for the
+// partner of the pair's representative); Mact[1] = number of selected pairs.
 __global__ void k_select(const SortEl* __restrict__ el, int64_t nreps, Dims d, int64_t M, uint8_t* __restrict__ mask,
-                         int64_t* __restrict__ rank, int64_t* __restrict__ Mact) {
+                         int64_t* __restrict__ rank, int64_t* __restrict__ Mact, int* __restrict__ pairof) {
   __shared__ int lds[32];
   int64_t base = 0;
   for (int64_t c0 = 0; c0 < nreps; c0 += blockDim.x) {
@@ -259,11 +261,16 @@ __global__ void k_select(const SortEl* __restrict__ el, int64_t nreps, Dims d, i
     if (sz && pos < M) {
       rank[pos] = idx;
       mask[idx] = 1;
+      pairof[idx] = (int)i;
       if (sz == 2) {
         rank[pos + 1] = pidx;
         mask[pidx] = 1;
+        pairof[pidx] = (int)i | (1 << 30);
       }
-      if (pos + sz >= M) *Mact = pos + sz;
+      if (pos + sz >= M) {
+        Mact[0] = pos + sz;
+        Mact[1] = i + 1;
+      }
     }
     base += total;
     if (base >= M) break;
@@ -282,6 +289,19 @@ __global__ void k_compact(const uint8_t* __restrict__ mask, int64_t N, int64_t* 
     if (f) sorted[base + ex] = i;
     base += total;
   }
+}
+
+// Slot tables of the warm-start network: slot s = pair s+1 in rank order
+// (pair 0 is xi = 0): representative's linear index and g^(rep) / count.
+__global__ void k_slots(const SortEl* __restrict__ el, int64_t nslots, const cpx<double>* __restrict__ S,
+                        const unsigned long long* count, int64_t* __restrict__ slot_rep, cpx<float>* __restrict__ slot_ghat) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslots) return;
+  const int64_t rep = el[s + 1].idx;
+  const double c = (double)(*count);
+  const cpx<double> v = S[rep];
+  slot_rep[s] = rep;
+  slot_ghat[s] = c > 0.0 ? cpx<float>{(float)(v.x / c), (float)(v.y / c)} : cpx<float>{0.f, 0.f};
 }
 
 // Half-spectrum columns: column c = kh * n1 + k1 (3D) or c = kh (2D), kh the
@@ -361,7 +381,8 @@ __global__ void k_tab_groups(const int* __restrict__ col_kh, const int* __restri
 // Pattern entries of each column, rows ascending, with Green directions.
 __global__ void k_tab_fill(const uint8_t* __restrict__ mask, Dims d, int ncolall, const int* __restrict__ colidx,
                            const int* __restrict__ col_off, int gamma_kind, int* __restrict__ coef_k0,
-                           int64_t* __restrict__ coef_lin, float* __restrict__ coef_n, uint8_t* __restrict__ flag) {
+                           int64_t* __restrict__ coef_lin, float* __restrict__ coef_n, uint8_t* __restrict__ flag,
+                           const int* __restrict__ pairof, int* __restrict__ coef_slot) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncolall) return;
   int j = colidx[c];
@@ -390,6 +411,12 @@ __global__ void k_tab_fill(const uint8_t* __restrict__ mask, Dims d, int ncolall
     if (!mask[lin]) continue;
     coef_k0[e] = k0;
     coef_lin[e] = lin;
+    {
+      // slot s = pair - 1 (pair 0 is xi = 0 -> -1); bit 30: stored member is the partner
+      const int pr = pairof[lin];
+      const int pair = pr & ((1 << 30) - 1);
+      coef_slot[e] = pair == 0 ? -1 : ((pair - 1) | (pr & (1 << 30)));
+    }
     double v[3] = {0.0, 0.0, 0.0};
     uint8_t f = 0;
     bool zero = true, selfc = true;
@@ -468,6 +495,9 @@ static void plan_free(mor_plan* p) {
   (void)hipFree(p->d_coef_flag);
   (void)hipFree(p->d_tw);
   (void)hipFree(p->d_dev);
+  (void)hipFree(p->d_slot_rep);
+  (void)hipFree(p->d_slot_ghat);
+  (void)hipFree(p->d_coef_slot);
   delete p;
 }
 
@@ -544,14 +574,29 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   DevBuf<uint8_t> mask;
   DevBuf<int64_t> mact;
   MOR_HIP_TRY(mask.alloc(N));
-  MOR_HIP_TRY(mact.alloc(1));
+  MOR_HIP_TRY(mact.alloc(2));
   MOR_HIP_TRY(hipMemsetAsync(mask.p, 0, N, st));
   MOR_HIP_TRY(hipMalloc((void**)&P->d_rank, (P->M + 1) * sizeof(int64_t)));
-  k_select<<<1, 1024, 0, st>>>(el.p, nreps, d, P->M, mask.p, P->d_rank, mact.p);
+  DevBuf<int> pairof;
+  MOR_HIP_TRY(pairof.alloc(N));
+  MOR_HIP_TRY(hipMemsetAsync(pairof.p, 0, N * sizeof(int), st));
+  k_select<<<1, 1024, 0, st>>>(el.p, nreps, d, P->M, mask.p, P->d_rank, mact.p, pairof.p);
   MOR_LAUNCH_CHECK("select");
-  MOR_HIP_TRY(hipMemcpyAsync(&P->M_actual, mact.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  int64_t hm[2] = {0, 0};
+  MOR_HIP_TRY(hipMemcpyAsync(hm, mact.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   MOR_HIP_TRY(hipMemcpyAsync(&P->count, cnt.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   MOR_HIP_TRY(hipStreamSynchronize(st));
+  P->M_actual = hm[0];
+  P->nslots = hm[1] - 1;
+
+  // slot tables of the warm-start network
+  MOR_HIP_TRY(hipMalloc((void**)&P->d_slot_rep, std::max<int64_t>(P->nslots, 1) * sizeof(int64_t)));
+  MOR_HIP_TRY(hipMalloc((void**)&P->d_slot_ghat, std::max<int64_t>(P->nslots, 1) * sizeof(cpx<float>)));
+  if (P->nslots > 0) {
+    k_slots<<<(unsigned)((P->nslots + 255) / 256), 256, 0, st>>>(el.p, P->nslots, S.p, cnt.p, P->d_slot_rep,
+                                                                 P->d_slot_ghat);
+    MOR_LAUNCH_CHECK("slots");
+  }
 
   // 5. sorted pattern
   MOR_HIP_TRY(hipMalloc((void**)&P->d_sorted, P->M_actual * sizeof(int64_t)));
@@ -593,8 +638,10 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_lin, std::max(ncoef, 1) * sizeof(int64_t)));
   MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_n, std::max(ncoef, 1) * 3 * sizeof(float)));
   MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_flag, std::max(ncoef, 1)));
+  MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_slot, std::max(ncoef, 1) * sizeof(int)));
   k_tab_fill<<<(ncolall + 255) / 256, 256, 0, st>>>(mask.p, d, ncolall, colidx.p, col_off, P->gamma_kind, coef_k0,
-                                                    P->d_coef_lin, P->d_coef_n, P->d_coef_flag);
+                                                    P->d_coef_lin, P->d_coef_n, P->d_coef_flag, pairof.p,
+                                                    P->d_coef_slot);
   MOR_LAUNCH_CHECK("tab_fill");
 
   // twiddles for the solver transforms

@@ -375,15 +375,25 @@ __global__ __launch_bounds__((col_threads<C, N0>())) void k_col_fast(
       green<C>(nv, tr_, nr_, mat.g_inv_mu0, mat.g_k);
       green<C>(nv, ti_, ni_, mat.g_inv_mu0, mat.g_k);
     } else {
+      if (warm) {
+        float wr[C], wi[C];
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        if (warm) {
+        for (int c = 0; c < C; ++c) {
           const cpx<float> w = warm[off.coef[b] + (int64_t)c * ncoef + e];
-          nr_[c] = w.x;
-          ni_[c] = w.y;
-        } else {
-          nr_[c] = ni_[c] = 0.f;
+          wr[c] = w.x;
+          wi[c] = w.y;
         }
+        float nv[3];
+        if (first) {
+          nv[0] = pn[0]; nv[1] = pn[1]; nv[2] = pn[2];
+        } else {
+          nv[0] = P.coef_n[3 * e]; nv[1] = P.coef_n[3 * e + 1]; nv[2] = P.coef_n[3 * e + 2];
+        }
+        project_compatible<C>(nv, wr, nr_, mat);
+        project_compatible<C>(nv, wi, ni_, mat);
+      } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) nr_[c] = ni_[c] = 0.f;
       }
     }
     if (MODE == MODE_ITER) {

@@ -153,6 +153,22 @@ __device__ __forceinline__ void green(const float* n, const float* t, float* out
   }
 }
 
+// Projection of a strain amplitude onto compatible strains at direction n:
+// P v = Gamma^ : C0 : v = -green(n, C0 : v).  Used on warm starts.
+template <int C>
+__device__ __forceinline__ void project_compatible(const float* n, const float* v, float* out, const MatDev& m) {
+  constexpr int ND = C == 3 ? 2 : 3;
+  float tr = 0.f;
+#pragma unroll
+  for (int i = 0; i < ND; ++i) tr += v[i];
+  float t[C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) t[i] = (i < ND ? m.lam0 * tr : 0.f) + 2.f * m.mu0 * v[i];
+  green<C>(n, t, out, m.g_inv_mu0, m.g_k);
+#pragma unroll
+  for (int i = 0; i < C; ++i) out[i] = -out[i];
+}
+
 template <int C>
 __device__ __forceinline__ float comp_weight(int c) {
   return c < Comp<C>::NDIAG ? 1.f : 2.f;  // Frobenius norm of the symmetric tensor
@@ -397,15 +413,20 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
         green<C>(nv, tr_, nr_, mat.g_inv_mu0, mat.g_k);
         green<C>(nv, ti_, ni_, mat.g_inv_mu0, mat.g_k);
       } else {
+        if (warm) {
+          float wr[C], wi[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-          if (warm) {
+          for (int c = 0; c < C; ++c) {
             const cpx<float> w = warm[off.coef[b] + (int64_t)c * ncoef + e];
-            nr_[c] = w.x;
-            ni_[c] = w.y;
-          } else {
-            nr_[c] = ni_[c] = 0.f;
+            wr[c] = w.x;
+            wi[c] = w.y;
           }
+          const float nv[3] = {P.coef_n[3 * e], P.coef_n[3 * e + 1], P.coef_n[3 * e + 2]};
+          project_compatible<C>(nv, wr, nr_, mat);
+          project_compatible<C>(nv, wi, ni_, mat);
+        } else {
+#pragma unroll
+          for (int c = 0; c < C; ++c) nr_[c] = ni_[c] = 0.f;
         }
       }
       if (MODE == MODE_ITER) {
