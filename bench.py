@@ -6,11 +6,18 @@ each RVE with its own microstructure and macro strain, from its start to
 residual < 1e-6 (every RVE), including the final stress evaluation.  Inputs
 (plans, macro strains) are resident on the device before the timed region.
 
-Prints one JSON line (rank 0).  Beside the headline value it reports the
-per-kernel roofline of the dominant kernel (HIP events around its launches
-inside the timed region, algorithmic bytes counted by the kernels), the plain
-single-RVE rate, the plan-construction cost, and the FP64 CPU oracle on a
-bounded sample of the same workload.
+The headline value is the learned, batched path: the warm-start network
+(trained first, untimed, on the method's own solves of separate training
+microstructures) runs inside every timed step (features, BF16 inference,
+scatter), then the batched solve.  Beside it: the cold-start batched rate,
+the Born-prior-only rate, the plain single-RVE rates (cold and learned), the
+iteration statistics of each start, the training cost, and the effective
+stress difference between learned and cold starts.
+
+Prints one JSON line (rank 0).  It also reports the per-kernel roofline of the
+dominant kernel (HIP events around its launches inside the timed region,
+algorithmic bytes counted by the kernels), the plan-construction cost, and the
+FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -87,6 +94,103 @@ def cpu_baseline(gs, ebs, budget_s=15.0):
     }
 
 
+SOLVE_SOURCES = ("fft_lds.h", "fft_reg.h", "mor_internal.h", "solve_fast.h", "solve_kernels.h", "solve.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_256x256_m3277_b1024_hbm_traffic.txt")
+
+
+def solve_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOLVE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2103_10203_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary (copy-calibrated), or None when the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    want = solve_source_hash()
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 6 and f[0] == "traffic" and f[1] == kernel and f[5] == want:
+                return float(f[2])
+    return None
+
+
+def timed_batched(mor, plans, plan_of, ebs, ph, steps, warmup, warm_fn=None):
+    """Batched solves of the whole workload; warm_fn (if given) builds the warm
+    start inside the timed region (features, network, scatter)."""
+    import torch
+
+    def step():
+        w = warm_fn() if warm_fn else None
+        return mor.solve_multi(plans, plan_of, ebs, ph, TOL, warm_start=w)
+
+    for _ in range(warmup):
+        step()
+    mor.profile_reset()
+    mor.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    mor.profile_enable(False)
+    assert out.status == mor.MOR_OK, out.status
+    kern = {k: mor.profile_query(k) for k in ("row", "col", "final", "init")}
+    return out, elapsed, kern
+
+
+def timed_single(mor, plans, ebs, ph, count, warm_fn=None):
+    """Plain path: one RVE per call (mor_solve), optionally warm-started."""
+    import torch
+
+    def one(i):
+        w = warm_fn(i) if warm_fn else None
+        return mor.solve(plans[i], ebs[i:i + 1], ph, TOL, warm_start=w)
+
+    for i in range(2):
+        one(i)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = []
+    for i in range(count):
+        its.append(int(one(i).iterations[0]))
+    torch.cuda.synchronize()
+    return count / (time.perf_counter() - t), float(np.mean(its))
+
+
+def train_network(mor, ph, ntrain, nslots, epochs, log):
+    """Training data from the method's own solves on seeded training
+    microstructures (seeds 0..ntrain-1), then Adam on the GPU."""
+    import torch
+    from paper_2103_10203_amd import warm
+    cfg = warm.WarmConfig(nslots=nslots, hidden=512, epochs=epochs, batch=512)
+    t = time.perf_counter()
+    gs = warm.generate_microstructures(range(ntrain), n=GRID, workers=min(16, os.cpu_count() or 8))
+    t_gen = time.perf_counter() - t
+    log(f"generated {ntrain} training microstructures in {t_gen:.1f} s")
+    data = warm.build_training_set(gs, M_FREQ, ph, nslots, log=log if ntrain >= 4096 else None)
+    del gs
+    log(f"training set: {data.solves} unit-strain solves, plans {data.gen_s['plans']:.1f} s, "
+        f"solves {data.gen_s['solves']:.1f} s")
+    net = mor.MLP(4 * nslots + 1, cfg.hidden, 18 * nslots, seed=cfg.seed)
+    hist, t_train = warm.train(net, data, cfg)
+    log(f"trained {epochs} epochs in {t_train:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    info = {"microstructures": ntrain, "unit_solves": data.solves, "gen_s": t_gen,
+            "plans_s": data.gen_s["plans"], "solves_s": data.gen_s["solves"], "train_s": t_train,
+            "epochs": epochs, "params": int(net.num_params), "loss_first": hist[0], "loss_last": hist[-1]}
+    del data
+    torch.cuda.empty_cache()
+    return net, info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +198,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--single", type=int, default=32, help="RVEs timed one launch each (plain path)")
+    ap.add_argument("--train", type=int, default=20000,
+                    help="training microstructures of the warm-start network (0: cold start only)")
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--nslots", type=int, default=1024)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -109,12 +217,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     import paper_2103_10203_amd as mor
+    from paper_2103_10203_amd import warm
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     B = args.batch
     t = time.perf_counter()
     gs, ebs = workload(B)
     t_gen = time.perf_counter() - t
     ph = phases()
+    log(f"generated {B} held-out RVEs in {t_gen:.1f} s")
 
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -123,53 +236,65 @@ def main():
     plan_ms = (time.perf_counter() - t) * 1e3 / B
     plan_of = np.arange(B)
 
-    # warmup (untimed)
-    for _ in range(args.warmup):
-        mor.solve_multi(plans, plan_of, ebs, ph, TOL)
+    # cold start, batched
+    cold, el_cold, kern_cold = timed_batched(mor, plans, plan_of, ebs, ph, args.steps, args.warmup)
+    cold_rate = B * args.steps / el_cold
+    log(f"cold batched: {cold_rate:.0f} solves/s, mean iterations {cold.iterations.mean():.2f}")
 
-    # timed region, with per-kernel HIP events inside the library
-    mor.profile_reset()
-    mor.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = None
-    for _ in range(args.steps):
-        out = mor.solve_multi(plans, plan_of, ebs, ph, TOL)
-        iters = out.iterations
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    mor.profile_enable(False)
-    assert out.status == mor.MOR_OK, out.status
-    kern = {k: mor.profile_query(k) for k in ("row", "col", "final", "init")}
+    # prior alone (Born term, zero network output)
+    S = args.nslots
+    born_fn = lambda: warm.born_warm(plans, plan_of, ebs, ph, S)  # noqa: E731
+    born, el_born, _ = timed_batched(mor, plans, plan_of, ebs, ph, args.steps, 1, born_fn)
+    born_rate = B * args.steps / el_born
+
+    learned = None
+    net = None
+    if args.train > 0:
+        net, tinfo = train_network(mor, ph, args.train, S, args.epochs, log)
+        warm_fn = lambda: warm.predict_warm(net, plans, plan_of, ebs, ph, S)  # noqa: E731
+        hot, el_hot, kern_hot = timed_batched(mor, plans, plan_of, ebs, ph, args.steps, args.warmup, warm_fn)
+        hot_rate = B * args.steps / el_hot
+        log(f"learned batched: {hot_rate:.0f} solves/s, mean iterations {hot.iterations.mean():.2f}")
+        dstress = float(np.max(np.abs(hot.eff_stress - cold.eff_stress)) / np.max(np.abs(cold.eff_stress)))
+        learned = {"rate": hot_rate, "elapsed": el_hot, "kern": kern_hot, "out": hot, "train": tinfo,
+                   "eff_stress_rel_diff_vs_cold": dstress}
+
+    if learned is not None:
+        head_out, head_el, kern, start = learned["out"], learned["elapsed"], learned["kern"], "learned"
+    else:
+        head_out, head_el, kern, start = cold, el_cold, kern_cold, "cold"
+    value = B * args.steps / head_el
+    ms_per_step = head_el * 1e3 / args.steps
+    iters = head_out.iterations
     dom = max(kern, key=lambda k: kern[k]["ms"])
     kd = kern[dom]
     achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9 if kd["ms"] > 0 else 0.0
 
-    value = B * args.steps / elapsed
-    ms_per_step = elapsed * 1e3 / args.steps
-
-    # plain path: one RVE per launch
+    # plain path: one RVE per launch, cold and warm
     ns = min(args.single, B)
-    single = None
+    single_cold = single_warm = None
     if ns > 0:
-        for i in range(2):
-            mor.solve(plans[i], ebs[i:i + 1], ph, TOL)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for i in range(ns):
-            mor.solve(plans[i], ebs[i:i + 1], ph, TOL)
-        torch.cuda.synchronize()
-        single = ns / (time.perf_counter() - t)
+        single_cold = timed_single(mor, plans, ebs, ph, ns)
+        if net is not None:
+            single_warm = timed_single(
+                mor, plans, ebs, ph, ns,
+                lambda i: warm.predict_warm(net, [plans[i]], [0], ebs[i:i + 1], ph, S))
 
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
 
+    def itstats(it):
+        return {"mean": float(np.mean(it)), "p50": float(np.percentile(it, 50)),
+                "p95": float(np.percentile(it, 95)), "max": int(np.max(it))}
+
+    start_desc = ("learned warm start (Born prior + MLP correction, BF16 MFMA inference inside the timed step)"
+                  if start == "learned" else "cold start")
     line = {
         "metric": METRIC,
         "value": value,
@@ -186,12 +311,12 @@ def main():
         "config": {
             "workload": f"held-out random-fibre RVEs {GRID}x{GRID} (vf~U[0.2,0.5], r~U[8,16] px), "
                         f"adapted pattern M={M_FREQ} (5%), batch {B} in one mor_solve_multi call, "
-                        f"residual {TOL:g}, cold start",
+                        f"residual {TOL:g}, {start_desc}",
             "grid": [GRID, GRID],
             "M": M_FREQ,
             "batch": B,
             "tol": TOL,
-            "start": "cold",
+            "start": start,
             "fields": "FP32, FP64 residual and stress sums",
         },
         "roofline": {
@@ -201,20 +326,38 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dom),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_us": kd["ms"] * 1e3 / max(kd["launches"], 1),
             "launches": kd["launches"],
         },
         "kernels": {k: {"ms": v["ms"], "launches": v["launches"],
                         "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0}
                     for k, v in kern.items()},
-        "iterations": {"mean": float(np.mean(iters)), "p50": float(np.percentile(iters, 50)),
-                       "p95": float(np.percentile(iters, 95)), "max": int(np.max(iters))},
-        "plain_single_rve_solves_per_s": single,
+        "iterations": itstats(iters),
+        "table_solves_per_s": {
+            "batched_cold": cold_rate,
+            "batched_born_prior": born_rate,
+            "batched_learned": learned["rate"] if learned else None,
+            "single_cold": single_cold[0] if single_cold else None,
+            "single_learned": single_warm[0] if single_warm else None,
+        },
+        "learned_vs_plain": {
+            "vs_batched_cold": (learned["rate"] / cold_rate) if learned else None,
+            "vs_single_cold": (learned["rate"] / single_cold[0]) if (learned and single_cold) else None,
+        },
+        "iterations_by_start": {
+            "cold": itstats(cold.iterations),
+            "born_prior": itstats(born.iterations),
+            "learned": itstats(learned["out"].iterations) if learned else None,
+        },
         "plan_ms_per_rve": plan_ms,
         "end_to_end_solves_per_s": 1.0 / (1.0 / value + plan_ms * 1e-3),
         "workload_gen_s": t_gen,
     }
+    if learned:
+        line["training"] = learned["train"]
+        line["eff_stress_rel_diff_learned_vs_cold"] = learned["eff_stress_rel_diff_vs_cold"]
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(gs, ebs, args.cpu_budget)
     print(json.dumps(line), flush=True)

@@ -266,7 +266,8 @@ mor_status mor_warm_targets(const mor_plan_t* plans, int64_t nplans, const int64
                             int32_t nslots, const mor_phase phase[2], const float* coeffs, float* T, void* stream);
 /* Warm-start coefficients eps^ = N sum_k (Born[..][k] + Y[..][k]) macro_strain[k]
  * (host double [B][3]) in the solver's packed coefficient layout (device complex64
- * [B][3][n_coeff]); coefficients without a slot are zero.  The solver
+ * [B][3][n_coeff]); the Born term covers every coefficient of the pattern,
+ * the network's correction only slots below nslots; xi = 0 is zero.  The solver
  * projects a warm start onto compatible strains before iterating. */
 mor_status mor_warm_apply(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of, int64_t B, int32_t nslots,
                           const mor_phase phase[2], const float* Y, const double* macro_strain, float* warm,

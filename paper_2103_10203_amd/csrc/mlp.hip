@@ -348,8 +348,8 @@ __global__ void k_warm_targets(const PlanSlots* __restrict__ ps, const int* __re
 }
 
 // Warm start: eps^(m)[c] = N sum_k (Born[c][k] + Y[b][s][c][k]) eps_bar[b][k]
-// (conjugated for partner coefficients); zero for coefficients without a slot
-// below S.
+// (conjugated for partner coefficients), Y taken as zero for slots s >= S;
+// zero at xi = 0 (the solver sets the mean).
 __global__ void k_warm_apply(const PlanSlots* __restrict__ ps, const int* __restrict__ plan_of,
                              const int64_t* __restrict__ coef_base, int B, int S, const float* __restrict__ Y,
                              const double* __restrict__ ebar, BornPar bp, cpx<float>* __restrict__ warm) {
@@ -363,8 +363,10 @@ __global__ void k_warm_apply(const PlanSlots* __restrict__ ps, const int* __rest
   if (sl >= 0) {
     const int s = sl & ((1 << 30) - 1);
     const bool conj = (sl >> 30) & 1;
-    if (s < S) {
-      const float* y = Y + (int64_t)b * (18 * S) + (int64_t)s * 18;
+    {
+      // the prior covers every pair of the pattern; the network's correction
+      // the first S slots
+      const float* y = s < S ? Y + (int64_t)b * (18 * S) + (int64_t)s * 18 : nullptr;
       const float Nf = (float)P.N;
       cpx<float> bt[3][3];
       born_coef(P, e, s, bp, bt);
@@ -372,8 +374,9 @@ __global__ void k_warm_apply(const PlanSlots* __restrict__ ps, const int* __rest
         float re = 0.f, im = 0.f;
         for (int k = 0; k < 3; ++k) {
           const float eb = (float)ebar[(int64_t)b * 3 + k];
-          re += (y[(c * 3 + k) * 2] + bt[c][k].x) * eb;
-          im += (y[(c * 3 + k) * 2 + 1] + bt[c][k].y) * eb;
+          const float yr = y ? y[(c * 3 + k) * 2] : 0.f, yi = y ? y[(c * 3 + k) * 2 + 1] : 0.f;
+          re += (yr + bt[c][k].x) * eb;
+          im += (yi + bt[c][k].y) * eb;
         }
         out[c] = {re * Nf, conj ? -im * Nf : im * Nf};
       }

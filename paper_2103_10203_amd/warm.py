@@ -56,7 +56,7 @@ class TrainingSet:
     gen_s: dict = field(default_factory=dict)
 
 
-def build_training_set(gs, M, phases, nslots, tol=1e-6, chunk=512):
+def build_training_set(gs, M, phases, nslots, tol=1e-6, chunk=512, log=None):
     """Features and targets for microstructures `gs`: three unit-strain solves
     each (RVE order (b, k)), converged coefficients gathered to slot targets."""
     import torch
@@ -80,6 +80,8 @@ def build_training_set(gs, M, phases, nslots, tol=1e-6, chunk=512):
         Xs.append(nat.warm_features(plans, po, nslots))
         Ts.append(nat.warm_targets(plans, po, nslots, phases, out.coeffs))
         del plans
+        if log:
+            log(f"training set: {c0 + nb} of {len(gs)} microstructures solved")
     X = torch.cat(Xs)
     T = torch.cat(Ts)
     return TrainingSet(X=X, T=T, solves=solves, gen_s={"plans": t_plan, "solves": t_solve})

@@ -127,9 +127,11 @@ def test_slot_targets_and_apply_round_trip():
     assert o2.iterations[0] <= 3
 
 
-def test_zero_correction_is_the_first_cold_iterate():
+@pytest.mark.parametrize("S", [8, 400])
+def test_zero_correction_is_the_first_cold_iterate(S):
     """With a zero network output the warm start is the Born prior, which is
-    the FP64 oracle's first iterate from the cold start; starting there saves
+    the FP64 oracle's first iterate from the cold start at every coefficient
+    of the pattern (also beyond the network's slots); starting there saves
     exactly one iteration."""
     import torch
     from paper_2103_10203_amd import warm
@@ -139,7 +141,6 @@ def test_zero_correction_is_the_first_cold_iterate():
     ebs = synth.macro_strains(6, 3, 5e-3, seed=77)
     plans = [mor.Plan(g, M) for g in gs]
     po = np.arange(6)
-    S = max(p.info["M_actual"] for p in plans)
     W = warm.born_warm(plans, po, ebs, native_phases(), S)
     off = 0
     for b, (g, p) in enumerate(zip(gs, plans)):
