@@ -273,6 +273,29 @@ mor_status mor_warm_apply(const mor_plan_t* plans, int64_t nplans, const int64_t
                           const mor_phase phase[2], const float* Y, const double* macro_strain, float* warm,
                           void* stream);
 
+/* ----------------------------------------------------------------------
+ * Kernel variants and autotuning (launch shape and FFT factorisation of the
+ * row kernel; not part of the paper's method).  Variants of one size give the
+ * same results up to FP32 rounding; a solve uses the variant selected for its
+ * (ndim, last-axis length) when it starts, default 0.  The selection is per
+ * process, shared by all threads and devices.
+ *   kernel  MOR_KERNEL_ROW
+ *   ndim    2 or 3; length = the grid's last-axis length (n[ndim-1])
+ * MOR_E_INVALID_ARG when that size has no specialised row kernel or the
+ * variant is out of range.
+ * ---------------------------------------------------------------------- */
+enum { MOR_KERNEL_ROW = 0 };
+mor_status mor_tune_variants(int32_t kernel, int32_t ndim, int32_t length, int32_t* count);
+mor_status mor_tune_get(int32_t kernel, int32_t ndim, int32_t length, int32_t* variant);
+mor_status mor_tune_set(int32_t kernel, int32_t ndim, int32_t length, int32_t variant);
+/* Autotuner: for every row length present among `plans`, runs the batched
+ * solve (mor_solve_multi arguments) once untimed and `reps` times timed with
+ * each variant, keeps the fastest (minimum wall time) and leaves it selected.
+ * The solves' outputs are discarded. */
+mor_status mor_autotune(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of_rve,
+                        const double* macro_strain, int64_t B, const mor_phase phase[2], double tol,
+                        int32_t reps, void* stream);
+
 /* Per-kernel timing over solves while enabled: HIP events bracket every launch
  * of the named kernel on the solve stream; `items` counts the work units the
  * launches processed (converged RVEs exit early and are not counted) and

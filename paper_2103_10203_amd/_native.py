@@ -105,6 +105,11 @@ _SIGS = {
                                     ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "mor_warm_apply": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p,
                                   ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "mor_tune_variants": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32)]),
+    "mor_tune_get": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32)]),
+    "mor_tune_set": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32]),
+    "mor_autotune": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p,
+                                ct.c_double, ct.c_int32, ct.c_void_p]),
     "mor_last_error": (ct.c_char_p, []),
     "mor_version": (ct.c_char_p, []),
 }
@@ -461,3 +466,30 @@ def warm_apply(plans, plan_of, nslots: int, phases, Y, macro_strain, stream=None
                               ct.c_void_p(Y.data_ptr()), _np_ptr(eb), ct.c_void_p(W.data_ptr()),
                               _stream_ptr(stream)))
     return W
+
+
+# ---------------------------------------------------------------- kernel variants / autotuner
+KERNEL_ROW = 0
+
+
+def tune_variants(ndim: int, length: int, kernel: int = KERNEL_ROW) -> int:
+    n = ct.c_int32(0)
+    _check(lib.mor_tune_variants(kernel, ndim, length, ct.byref(n)))
+    return n.value
+
+
+def tune_get(ndim: int, length: int, kernel: int = KERNEL_ROW) -> int:
+    v = ct.c_int32(0)
+    _check(lib.mor_tune_get(kernel, ndim, length, ct.byref(v)))
+    return v.value
+
+
+def tune_set(ndim: int, length: int, variant: int, kernel: int = KERNEL_ROW) -> None:
+    _check(lib.mor_tune_set(kernel, ndim, length, variant))
+
+
+def autotune(plans, plan_of, macro_strain, phases, tol: float, reps: int = 2, stream=None) -> None:
+    po = np.ascontiguousarray(plan_of, dtype=np.int64)
+    eb = np.ascontiguousarray(macro_strain, dtype=np.float64)
+    _check(lib.mor_autotune(_plan_array(plans), len(plans), _np_ptr(po), _np_ptr(eb), len(po), _phases(phases),
+                            float(tol), reps, _stream_ptr(stream)))

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -113,6 +114,7 @@ struct Group {
   std::vector<int> rves;
   int ncol_max = 0, nlast_max = 0;
   int rb = 1, cb = 1, xb = 1;
+  int rvar = 0;  // row-kernel variant
   bool fast_row = false, fast_col = false;
   int* d_list = nullptr;
 };
@@ -126,20 +128,60 @@ bool has_fast_col(int C, int n0) {
   if (C == 3) return n0 == 64 || n0 == 128 || n0 == 256 || n0 == 384 || n0 == 512;
   return n0 == 64 || n0 == 128;
 }
-int fast_rb(int C, int nh) {
+// ------------------------------------------------------------------ kernel variants
+// Row-kernel variants per (C, half length): the selected one (default 0) is
+// kept per process; mor_tune_set / mor_autotune change it.
+std::mutex g_var_mu;
+std::map<std::pair<int, int>, int> g_row_var;  // (C, nh) -> variant
+
+template <int C, int NH, int V = 0>
+int row_rb_v(int v) {
+  if constexpr (V < RowVar<C, NH>::count) {
+    return v == V ? RowCfg<C, NH, V>::RB : row_rb_v<C, NH, V + 1>(v);
+  } else {
+    return -1;
+  }
+}
+
+int row_variants(int C, int nh) {
   if (C == 3) {
     switch (nh) {
-      case 32: return RowCfg<3, 32>::RB;
-      case 64: return RowCfg<3, 64>::RB;
-      case 128: return RowCfg<3, 128>::RB;
-      case 192: return RowCfg<3, 192>::RB;
-      default: return RowCfg<3, 256>::RB;
+      case 32: return RowVar<3, 32>::count;
+      case 64: return RowVar<3, 64>::count;
+      case 128: return RowVar<3, 128>::count;
+      case 192: return RowVar<3, 192>::count;
+      case 256: return RowVar<3, 256>::count;
+      default: return 0;
     }
   }
   switch (nh) {
-    case 32: return RowCfg<6, 32>::RB;
-    case 64: return RowCfg<6, 64>::RB;
-    default: return RowCfg<6, 128>::RB;
+    case 32: return RowVar<6, 32>::count;
+    case 64: return RowVar<6, 64>::count;
+    case 128: return RowVar<6, 128>::count;
+    default: return 0;
+  }
+}
+
+int row_variant(int C, int nh) {
+  std::lock_guard<std::mutex> lk(g_var_mu);
+  auto it = g_row_var.find({C, nh});
+  return it == g_row_var.end() ? 0 : it->second;
+}
+
+int fast_rb(int C, int nh, int v) {
+  if (C == 3) {
+    switch (nh) {
+      case 32: return row_rb_v<3, 32>(v);
+      case 64: return row_rb_v<3, 64>(v);
+      case 128: return row_rb_v<3, 128>(v);
+      case 192: return row_rb_v<3, 192>(v);
+      default: return row_rb_v<3, 256>(v);
+    }
+  }
+  switch (nh) {
+    case 32: return row_rb_v<6, 32>(v);
+    case 64: return row_rb_v<6, 64>(v);
+    default: return row_rb_v<6, 128>(v);
   }
 }
 int fast_cb(int C, int n0) {
@@ -254,11 +296,27 @@ void ev_end(SolveCtx& cx, int kind, hipEvent_t a) {
 
 
 // ------------------------------------------------------------------ launches
+template <int C, int NH, int V, int MODE, int MAT>
+void go_row_fast_v(SolveCtx& cx, Group& g, float* eps, float* sig, int rows) {
+  if constexpr (V < RowVar<C, NH>::count) {
+    using Cfg = RowCfg<C, NH, V>;
+    dim3 gr((rows + Cfg::RB - 1) / Cfg::RB, (unsigned)g.rves.size());
+    k_row_fast<C, NH, V, MODE, MAT><<<gr, row_threads<C, NH, V>(), row_lds_bytes<C, NH, V>(), cx.st>>>(
+        cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat, cx.d_jstate, eps, sig, cx.d_sigpart);
+  }
+}
+
 template <int C, int NH, int MODE, int MAT>
 void go_row_fast(SolveCtx& cx, Group& g, float* eps, float* sig, int rows) {
-  dim3 gr((rows + RowCfg<C, NH>::RB - 1) / RowCfg<C, NH>::RB, (unsigned)g.rves.size());
-  k_row_fast<C, NH, MODE, MAT><<<gr, row_threads<C, NH>(), row_lds_bytes<C, NH>(), cx.st>>>(
-      cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat, cx.d_jstate, eps, sig, cx.d_sigpart);
+  static_assert(RowVar<C, NH>::count <= 6, "dispatch covers six variants");
+  switch (g.rvar) {
+    case 0: go_row_fast_v<C, NH, 0, MODE, MAT>(cx, g, eps, sig, rows); break;
+    case 1: go_row_fast_v<C, NH, 1, MODE, MAT>(cx, g, eps, sig, rows); break;
+    case 2: go_row_fast_v<C, NH, 2, MODE, MAT>(cx, g, eps, sig, rows); break;
+    case 3: go_row_fast_v<C, NH, 3, MODE, MAT>(cx, g, eps, sig, rows); break;
+    case 4: go_row_fast_v<C, NH, 4, MODE, MAT>(cx, g, eps, sig, rows); break;
+    default: go_row_fast_v<C, NH, 5, MODE, MAT>(cx, g, eps, sig, rows); break;
+  }
 }
 
 template <int C, int MODE, int MAT>
@@ -471,7 +529,12 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     const int nlen = g.ndim == 2 ? g.n1 : g.n2;
     g.fast_row = has_fast_row(cx.C, nlen / 2);
     g.fast_col = has_fast_col(cx.C, g.n0);
-    g.rb = g.fast_row ? fast_rb(cx.C, nlen / 2) : rows_per_block(cx.C, nlen);
+    if (g.fast_row) {
+      g.rvar = std::min(row_variant(cx.C, nlen / 2), row_variants(cx.C, nlen / 2) - 1);
+      g.rb = fast_rb(cx.C, nlen / 2, g.rvar);
+    } else {
+      g.rb = rows_per_block(cx.C, nlen);
+    }
     g.cb = g.fast_col ? fast_cb(cx.C, g.n0) : cols_per_block(cx.C, g.n0);
     g.xb = g.ndim == 3 ? cols_per_block(cx.C, g.n1) : 1;
     const int rows = g.ndim == 2 ? g.n0 : g.n0 * g.n1;
@@ -892,4 +955,119 @@ extern "C" mor_status mor_profile_query(const char* kernel, double* total_ms, in
   }
   mor_set_error(std::string("mor_profile_query: unknown kernel ") + kernel);
   return MOR_E_INVALID_ARG;
+}
+
+// ------------------------------------------------------------------ kernel variants (ABI)
+namespace {
+int comps_of_ndim(int ndim) { return ndim == 2 ? 3 : ndim == 3 ? 6 : 0; }
+
+mor_status check_tune_args(int32_t kernel, int32_t ndim, int32_t length, int* C, int* nh, const char* who) {
+  *C = comps_of_ndim(ndim);
+  *nh = length / 2;
+  if (kernel != MOR_KERNEL_ROW || *C == 0 || length < 2 || (length & 1) || row_variants(*C, *nh) == 0) {
+    mor_set_error(std::string(who) + ": no tunable kernel for this (kernel, ndim, length)");
+    return MOR_E_INVALID_ARG;
+  }
+  return MOR_OK;
+}
+}  // namespace
+
+extern "C" mor_status mor_tune_variants(int32_t kernel, int32_t ndim, int32_t length, int32_t* count) {
+  int C, nh;
+  if (!count) {
+    mor_set_error("mor_tune_variants: NULL count");
+    return MOR_E_INVALID_ARG;
+  }
+  mor_status s = check_tune_args(kernel, ndim, length, &C, &nh, "mor_tune_variants");
+  if (s != MOR_OK) return s;
+  *count = row_variants(C, nh);
+  return MOR_OK;
+}
+
+extern "C" mor_status mor_tune_get(int32_t kernel, int32_t ndim, int32_t length, int32_t* variant) {
+  int C, nh;
+  if (!variant) {
+    mor_set_error("mor_tune_get: NULL variant");
+    return MOR_E_INVALID_ARG;
+  }
+  mor_status s = check_tune_args(kernel, ndim, length, &C, &nh, "mor_tune_get");
+  if (s != MOR_OK) return s;
+  *variant = row_variant(C, nh);
+  return MOR_OK;
+}
+
+extern "C" mor_status mor_tune_set(int32_t kernel, int32_t ndim, int32_t length, int32_t variant) {
+  int C, nh;
+  mor_status s = check_tune_args(kernel, ndim, length, &C, &nh, "mor_tune_set");
+  if (s != MOR_OK) return s;
+  if (variant < 0 || variant >= row_variants(C, nh)) {
+    mor_set_error("mor_tune_set: variant out of range");
+    return MOR_E_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lk(g_var_mu);
+  g_row_var[{C, nh}] = variant;
+  return MOR_OK;
+}
+
+// Autotuner: for every distinct row length among the plans, time `reps`
+// batched solves of the given workload with each variant (the other sizes
+// keep their current choice) and keep the fastest.  The workload's results
+// are discarded; the tuned choice applies to later solves in this process.
+extern "C" mor_status mor_autotune(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of_rve,
+                                   const double* macro_strain_packed, int64_t B, const mor_phase phase[2],
+                                   double tol, int32_t reps, void* stream) {
+  if (!plans || nplans < 1 || !plan_of_rve || B < 1 || reps < 1 || !macro_strain_packed) {
+    mor_set_error("mor_autotune: invalid argument");
+    return MOR_E_INVALID_ARG;
+  }
+  std::vector<std::pair<int, int>> sizes;  // (ndim, last-axis length)
+  for (int64_t i = 0; i < nplans; ++i) {
+    if (!plans[i]) {
+      mor_set_error("mor_autotune: NULL plan");
+      return MOR_E_INVALID_ARG;
+    }
+    const int nd = plans[i]->ndim;
+    std::pair<int, int> key{nd, plans[i]->n[nd - 1]};
+    if (std::find(sizes.begin(), sizes.end(), key) == sizes.end()) sizes.push_back(key);
+  }
+  mor_solve_opts o{};
+  o.stream = stream;
+  const int C0 = comps_of_ndim(plans[0]->ndim);
+  std::vector<double> eff((size_t)B * (C0 == 3 ? 4 : 6));
+  std::vector<int32_t> its(B);
+  std::vector<double> res(B);
+  mor_outputs out{};
+  out.eff_stress = eff.data();
+  out.iterations = its.data();
+  out.residual = res.data();
+  for (auto [nd, len] : sizes) {
+    const int C = comps_of_ndim(nd), nh = len / 2;
+    const int nv = (len % 2 == 0) ? row_variants(C, nh) : 0;
+    if (nv < 2) continue;
+    int best = row_variant(C, nh);
+    double best_t = 1e300;
+    for (int v = 0; v < nv; ++v) {
+      {
+        std::lock_guard<std::mutex> lk(g_var_mu);
+        g_row_var[{C, nh}] = v;
+      }
+      mor_status s = mor_solve_multi(plans, nplans, plan_of_rve, macro_strain_packed, B, phase, tol, &o, &out);
+      if (s != MOR_OK && s != MOR_E_NOT_CONVERGED) return s;
+      double tmin = 1e300;
+      for (int r = 0; r < reps; ++r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        s = mor_solve_multi(plans, nplans, plan_of_rve, macro_strain_packed, B, phase, tol, &o, &out);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (s != MOR_OK && s != MOR_E_NOT_CONVERGED) return s;
+        tmin = std::min(tmin, std::chrono::duration<double>(t1 - t0).count());
+      }
+      if (tmin < best_t) {
+        best_t = tmin;
+        best = v;
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_var_mu);
+    g_row_var[{C, nh}] = best;
+  }
+  return MOR_OK;
 }

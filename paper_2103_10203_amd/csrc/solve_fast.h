@@ -16,21 +16,54 @@ using fftr::RList;
 
 // Row kernel configuration for a half length NH (row length L = 2 NH):
 // inverse passes RA..., then the register pass RL; forward RL, then RA
-// reversed.  RB rows per workgroup, NH/RL threads per row.
-template <int C, int NH>
+// reversed.  RB rows per workgroup, NH/RL threads per row.  The LDS buffer
+// holds one strain component of the row block at a time (the register pass
+// keeps all C components of a thread's points in registers), so the LDS
+// footprint per row is one sequence and many rows fit a CU.  Each (C, NH) has
+// RowVar<C, NH>::count variants V (different factorisations and row blocks,
+// same results up to FP32 rounding); the host picks one per size (a fixed
+// default, or the autotuner's measurement).
+template <int C, int NH, int V>
 struct RowCfg;
-template <> struct RowCfg<3, 32>  { static constexpr int RL = 4, RB = 48; using RA = RList<8>; };
-template <> struct RowCfg<3, 64>  { static constexpr int RL = 4, RB = 24; using RA = RList<4, 4>; };
-template <> struct RowCfg<3, 128> { static constexpr int RL = 4, RB = 12; using RA = RList<8, 4>; };
-template <> struct RowCfg<3, 192> { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4, 3>; };
-template <> struct RowCfg<3, 256> { static constexpr int RL = 4, RB = 6;  using RA = RList<8, 8>; };
-template <> struct RowCfg<6, 32>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
-template <> struct RowCfg<6, 64>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
-template <> struct RowCfg<6, 128> { static constexpr int RL = 4, RB = 4;  using RA = RList<8, 4>; };
-
 template <int C, int NH>
+struct RowVar {
+  static constexpr int count = 1;
+};
+template <> struct RowCfg<3, 32, 0>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
+template <> struct RowCfg<3, 32, 1>  { static constexpr int RL = 8, RB = 32; using RA = RList<4>; };
+template <> struct RowCfg<3, 32, 2>  { static constexpr int RL = 4, RB = 32; using RA = RList<8>; };
+template <> struct RowVar<3, 32> { static constexpr int count = 3; };
+template <> struct RowCfg<3, 64, 0>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
+template <> struct RowCfg<3, 64, 1>  { static constexpr int RL = 8, RB = 16; using RA = RList<8>; };
+template <> struct RowCfg<3, 64, 2>  { static constexpr int RL = 8, RB = 32; using RA = RList<8>; };
+template <> struct RowCfg<3, 64, 3>  { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4>; };
+template <> struct RowCfg<3, 64, 4>  { static constexpr int RL = 8, RB = 8;  using RA = RList<8>; };
+template <> struct RowVar<3, 64> { static constexpr int count = 5; };
+template <> struct RowCfg<3, 128, 0> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 4>; };
+template <> struct RowCfg<3, 128, 1> { static constexpr int RL = 4, RB = 16; using RA = RList<8, 4>; };
+template <> struct RowCfg<3, 128, 2> { static constexpr int RL = 4, RB = 4;  using RA = RList<8, 4>; };
+template <> struct RowCfg<3, 128, 3> { static constexpr int RL = 8, RB = 16; using RA = RList<16>; };
+template <> struct RowCfg<3, 128, 4> { static constexpr int RL = 8, RB = 8;  using RA = RList<16>; };
+template <> struct RowCfg<3, 128, 5> { static constexpr int RL = 8, RB = 8;  using RA = RList<4, 4>; };
+template <> struct RowVar<3, 128> { static constexpr int count = 6; };
+template <> struct RowCfg<3, 192, 0> { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4, 3>; };
+template <> struct RowCfg<3, 192, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<8, 3>; };
+template <> struct RowCfg<3, 192, 2> { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4, 3>; };
+template <> struct RowCfg<3, 192, 3> { static constexpr int RL = 4, RB = 8;  using RA = RList<3, 4, 4>; };
+template <> struct RowVar<3, 192> { static constexpr int count = 4; };
+template <> struct RowCfg<3, 256, 0> { static constexpr int RL = 8, RB = 8;  using RA = RList<4, 8>; };
+template <> struct RowCfg<3, 256, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<16, 2>; };
+template <> struct RowCfg<3, 256, 2> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 8>; };
+template <> struct RowCfg<3, 256, 3> { static constexpr int RL = 4, RB = 4;  using RA = RList<8, 8>; };
+template <> struct RowCfg<3, 256, 4> { static constexpr int RL = 8, RB = 4;  using RA = RList<4, 8>; };
+template <> struct RowVar<3, 256> { static constexpr int count = 5; };
+template <> struct RowCfg<6, 32, 0>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
+template <> struct RowCfg<6, 64, 0>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
+template <> struct RowCfg<6, 128, 0> { static constexpr int RL = 4, RB = 4;  using RA = RList<8, 4>; };
+
+template <int C, int NH, int V>
 constexpr int row_threads() {
-  return RowCfg<C, NH>::RB * (NH / RowCfg<C, NH>::RL);
+  return RowCfg<C, NH, V>::RB * (NH / RowCfg<C, NH, V>::RL);
 }
 template <int NH>
 constexpr int row_ss() {
@@ -40,28 +73,30 @@ template <int NH>
 constexpr int row_tw_len() {
   return pad16(2 * NH - 1) + 1;  // padded table of exp(-2 pi i t / (2 NH))
 }
-template <int C, int NH>
+template <int C, int NH, int V>
 constexpr size_t row_lds_bytes() {
-  return (size_t)(row_tw_len<NH>() + C * RowCfg<C, NH>::RB * row_ss<NH>()) * sizeof(cpx<float>);
+  return (size_t)(row_tw_len<NH>() + RowCfg<C, NH, V>::RB * row_ss<NH>()) * sizeof(cpx<float>);
 }
 
-template <int C, int NH, int MODE, int MAT>
-__global__ __launch_bounds__((row_threads<C, NH>())) void k_row_fast(
+template <int C, int NH, int V, int MODE, int MAT>
+__global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
     const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
     cpx<float>* __restrict__ Yl, Offs off, MatDev mat, float* __restrict__ jstate, float* __restrict__ out_eps,
     float* __restrict__ out_sig, double* __restrict__ sig_part) {
-  using Cfg = RowCfg<C, NH>;
+  using Cfg = RowCfg<C, NH, V>;
   constexpr int RL = Cfg::RL, RB = Cfg::RB;
   constexpr int TR = NH / RL;  // threads per row in the register pass
   constexpr int NT = RB * TR;
   constexpr int SS = row_ss<NH>();
-  constexpr int NSEQ = C * RB;
   constexpr int S = Comp<C>::S;
   constexpr int NST = Comp<C>::NST;
   constexpr int L = 2 * NH;
+  constexpr int KH = NH / 2 + 1;
   static_assert(NT % 64 == 0, "workgroups are whole wavefronts");
+  static_assert(NT % RB == 0, "row block divides the workgroup");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-  __shared__ int lk[NH + 1];
+  __shared__ int lk[NH + 1];    // last-axis frequency of spectrum entry j
+  __shared__ int kpos[NH + 1];  // entry j of last-axis frequency k, -1 if not sampled
   const int tid = threadIdx.x;
   const int b = rve_list[blockIdx.y];
   if (MODE == MODE_ITER && !st[b].active) return;
@@ -73,81 +108,82 @@ __global__ __launch_bounds__((row_threads<C, NH>())) void k_row_fast(
   // T[t] = exp(-2 pi i t / L): the real-FFT twiddles are T[k], the length-NH
   // FFT twiddles are T[2 e].
   cpx<float>* T = reinterpret_cast<cpx<float>*>(smem_raw);
-  cpx<float>* buf = T + row_tw_len<NH>();
+  cpx<float>* buf = T + row_tw_len<NH>();  // RB sequences, one component
   const int nlast = P.nlast;
   for (int t = tid; t < L; t += NT) T[pad16(t)] = P.rtw[t];
+  for (int t = tid; t <= NH; t += NT) kpos[t] = -1;
   for (int t = tid; t < nlast; t += NT) lk[t] = P.last_k[t];
-  for (int t = tid; t < NSEQ * SS; t += NT) buf[t] = {0.f, 0.f};
+  __syncthreads();
+  for (int t = tid; t < nlast; t += NT) kpos[lk[t]] = t;
   __syncthreads();
   cpx<float>* Y = Yl + off.yl[b];
   const int64_t cstride = (int64_t)nlast * rows;
-  // gather the row block's last-axis spectra; U independent loads in flight
-  // thread (r = tid % RB, q0 = tid / RB) walks q = c * nlast + j in steps of
-  // NT / RB, keeping (c, j) incrementally
-  static_assert(NT % RB == 0, "row block divides the workgroup");
   constexpr int QS = NT / RB;
-  const int rg = tid % RB;
+  const int rg = tid % RB;      // row of this thread in gather / scatter loops
   const bool rlive = rg < nr;
-  {
-    constexpr int U = 4;
-    const int qtot = C * nlast;
-    int j = tid / RB, c = 0;
-    while (j >= nlast && c < C) { j -= nlast; ++c; }
-    const cpx<float>* ysrc = Y + r0 + rg;
-    for (int q0 = tid / RB; q0 < qtot; q0 += QS * U) {
-      cpx<float> val[U];
-      int dst[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        dst[u] = -1;
-        if (c < C && rlive) {
-          val[u] = ysrc[(int64_t)c * cstride + (int64_t)j * rows];
-          dst[u] = (c * RB + rg) * SS + pad16(lk[j]);
-        }
-        j += QS;
-        while (j >= nlast && c < C) { j -= nlast; ++c; }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (dst[u] >= 0) buf[dst[u]] = val[u];
-    }
-  }
-  __syncthreads();
-  // pack the half spectrum X[0..NH] into the length-NH sequence
-  //   z[k] = (X[k] + conj X[NH-k]) + i (X[k] - conj X[NH-k]) conj(T[k]);
-  // each thread owns the pair (k, NH-k), so the update is in place.
-  for (int t = tid; t < NSEQ * (NH / 2 + 1); t += NT) {
-    const int q = t / (NH / 2 + 1), k = t % (NH / 2 + 1);
-    cpx<float>* x = buf + q * SS;
-    const cpx<float> Xk = x[pad16(k)], Xm = x[pad16(NH - k)];
-    const cpx<float> a = cadd(Xk, cconj(Xm));
-    const cpx<float> d = cmul(csub(Xk, cconj(Xm)), cconj(T[pad16(k)]));
-    const cpx<float> zk = {a.x - d.y, a.y + d.x};
-    if (k == 0 || 2 * k == NH) {
-      x[pad16(k)] = zk;
-    } else {
-      const cpx<float> a2 = cadd(Xm, cconj(Xk));
-      const cpx<float> d2 = cmul(csub(Xm, cconj(Xk)), cconj(T[pad16(NH - k)]));
-      x[pad16(k)] = zk;
-      x[pad16(NH - k)] = {a2.x - d2.y, a2.y + d2.x};
-    }
-  }
-  __syncthreads();
-  fftr::lds_passes<NH, +1, 1, NSEQ, SS, NT, 2>(buf, T, tid, typename Cfg::RA{});
-
-  // register pass: last inverse stage (radix RL, span TR)
-  const int r = tid / TR, i = tid % TR;
+  const int r = tid / TR, i = tid % TR;  // row and butterfly in the register pass
   cpx<float> v[C][RL];
+
+  // ---- inverse transform, one component at a time
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    const cpx<float>* src = buf + (c * RB + r) * SS;
+    // gather the half spectra X[0..NH] of component c and pack them into
+    // length-NH sequences
+    //   z[k] = (X[k] + conj X[NH-k]) + i (X[k] - conj X[NH-k]) conj(T[k]);
+    // item (k, row) for k = 0..NH/2 writes z[k] and z[NH-k]; rows are the
+    // fastest index, so a wavefront reads runs of RB consecutive entries.
+    // Frequencies outside the pattern are zero; every z position is written.
+    {
+      constexpr int TOT = KH * RB;
+      constexpr int U = 4;
+      const cpx<float>* ysrc = Y + (int64_t)c * cstride + r0 + rg;
+      for (int t0 = tid; t0 < TOT; t0 += NT * U) {
+        cpx<float> xa[U], xb[U];
 #pragma unroll
-    for (int j = 0; j < RL; ++j) v[c][j] = src[pad16(i + j * TR)];
-    fftr::pass_twiddle<NH, RL, TR, +1, 2>(v[c], i, T);
-    Dft<RL, +1>::run(v[c]);
+        for (int u = 0; u < U; ++u) {
+          const int t = t0 + u * NT;  // t % RB == rg
+          xa[u] = {0.f, 0.f};
+          xb[u] = {0.f, 0.f};
+          if (t < TOT && rlive) {
+            const int k = t / RB;
+            const int ja = kpos[k], jb = kpos[NH - k];
+            if (ja >= 0) xa[u] = ysrc[(int64_t)ja * rows];
+            if (jb >= 0) xb[u] = ysrc[(int64_t)jb * rows];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int t = t0 + u * NT;
+          if (t < TOT) {
+            const int k = t / RB;
+            cpx<float>* x = buf + rg * SS;
+            const cpx<float> Xk = xa[u], Xm = xb[u];
+            const cpx<float> a = cadd(Xk, cconj(Xm));
+            const cpx<float> d = cmul(csub(Xk, cconj(Xm)), cconj(T[pad16(k)]));
+            x[pad16(k)] = {a.x - d.y, a.y + d.x};
+            if (k != 0 && 2 * k != NH) {
+              const cpx<float> a2 = cadd(Xm, cconj(Xk));
+              const cpx<float> d2 = cmul(csub(Xm, cconj(Xk)), cconj(T[pad16(NH - k)]));
+              x[pad16(NH - k)] = {a2.x - d2.y, a2.y + d2.x};
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    fftr::lds_passes<NH, +1, 1, RB, SS, NT, 2>(buf, T, tid, typename Cfg::RA{});
+    // register pass: last inverse stage (radix RL, span TR)
+    {
+      const cpx<float>* src = buf + r * SS;
+#pragma unroll
+      for (int j = 0; j < RL; ++j) v[c][j] = src[pad16(i + j * TR)];
+      fftr::pass_twiddle<NH, RL, TR, +1, 2>(v[c], i, T);
+      Dft<RL, +1>::run(v[c]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // pointwise step a): thread holds points 2t, 2t+1 of row r0+r for t = i + j TR
+
+  // ---- pointwise step a): thread holds points 2t, 2t+1 of row r0+r for t = i + j TR
   const bool live = r < nr;
   const int64_t row = r0 + r;
   double acc[S];
@@ -215,33 +251,35 @@ __global__ __launch_bounds__((row_threads<C, NH>())) void k_row_fast(
     }
     return;
   }
-  // register pass: first forward stage (radix RL, span 1), then the rest
+
+  // ---- forward transform, one component at a time
 #pragma unroll
   for (int c = 0; c < C; ++c) {
+    // register pass: first forward stage (radix RL, span 1)
     Dft<RL, -1>::run(v[c]);
-    cpx<float>* dst = buf + (c * RB + r) * SS;
+    {
+      cpx<float>* dst = buf + r * SS;
 #pragma unroll
-    for (int j = 0; j < RL; ++j) dst[pad16(i * RL + j)] = v[c][j];
-  }
-  __syncthreads();
-  fftr::lds_passes<NH, -1, RL, NSEQ, SS, NT, 2>(buf, T, tid,
-                                                typename fftr::Rev<typename Cfg::RA, RList<>>::type{});
-  if (rlive) {
-    const int qtot = C * nlast;
-    int j = tid / RB, c = 0;
-    while (j >= nlast && c < C) { j -= nlast; ++c; }
-    cpx<float>* ydst = Y + r0 + rg;
-    for (int q = tid / RB; q < qtot; q += QS) {
-      const int k = lk[j];
-      const cpx<float>* z = buf + (c * RB + rg) * SS;
-      const cpx<float> Zk = z[pad16(k == NH ? 0 : k)];
-      const cpx<float> Zc = cconj(z[pad16(k == 0 ? 0 : NH - k)]);
-      const cpx<float> sm = cadd(Zk, Zc);
-      const cpx<float> wd = cmul(T[pad16(k)], csub(Zk, Zc));
-      ydst[(int64_t)c * cstride + (int64_t)j * rows] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
-      j += QS;
-      while (j >= nlast && c < C) { j -= nlast; ++c; }
+      for (int j = 0; j < RL; ++j) dst[pad16(i * RL + j)] = v[c][j];
     }
+    __syncthreads();
+    fftr::lds_passes<NH, -1, RL, RB, SS, NT, 2>(buf, T, tid,
+                                                typename fftr::Rev<typename Cfg::RA, RList<>>::type{});
+    // unpack X[k] = (Z[k] + conj Z[NH-k]) / 2 - i T[k] (Z[k] - conj Z[NH-k]) / 2
+    // at the sampled frequencies and store them
+    if (rlive) {
+      const cpx<float>* z = buf + rg * SS;
+      cpx<float>* ydst = Y + (int64_t)c * cstride + r0 + rg;
+      for (int j = tid / RB; j < nlast; j += QS) {
+        const int k = lk[j];
+        const cpx<float> Zk = z[pad16(k == NH ? 0 : k)];
+        const cpx<float> Zc = cconj(z[pad16(k == 0 ? 0 : NH - k)]);
+        const cpx<float> sm = cadd(Zk, Zc);
+        const cpx<float> wd = cmul(T[pad16(k)], csub(Zk, Zc));
+        ydst[(int64_t)j * rows] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
+      }
+    }
+    if (c + 1 < C) __syncthreads();
   }
 }
 

@@ -58,3 +58,21 @@ def test_null_arguments():
     assert nat.lib.mor_plan_destroy(None) == nat.MOR_OK
     assert nat.lib.mor_profile_query(None, None, None, None, None) == nat.MOR_E_INVALID_ARG
     assert nat.lib.mor_profile_query(b"nope", None, None, None, None) == nat.MOR_E_INVALID_ARG
+
+
+def test_tune_api_host_side():
+    """Variant selection is host state: counts, get/set round trip and the
+    rejected arguments (no GPU needed)."""
+    import paper_2103_10203_amd as mor
+    assert mor.tune_variants(2, 256) >= 2
+    keep = mor.tune_get(2, 256)
+    mor.tune_set(2, 256, 1)
+    assert mor.tune_get(2, 256) == 1
+    mor.tune_set(2, 256, keep)
+    for args in [(2, 100), (4, 256), (2, 255)]:
+        with pytest.raises(mor.MorError):
+            mor.tune_variants(*args)
+    with pytest.raises(mor.MorError):
+        mor.tune_set(2, 256, mor.tune_variants(2, 256))
+    with pytest.raises(mor.MorError):
+        mor.tune_set(2, 256, -1)

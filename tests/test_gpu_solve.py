@@ -179,3 +179,53 @@ def test_3d_parity(shape):
     assert np.max(np.abs(out.eff_stress[0] - sref)) / np.max(np.abs(sref)) < 1e-5
     e_ref, s_ref = _fields_from_oracle(ref, 3)
     assert rel_l2(out.strain[0].cpu().numpy(), e_ref) < 1e-4
+
+
+@pytest.mark.parametrize("n", [64, 128, 256, 384, 512])
+def test_row_kernel_variants(n):
+    """Every row-kernel variant of a size (factorisation, row block) against
+    the FP64 oracle on a random-fibre RVE."""
+    mor = _mor()
+    g = synth.fibre_rve_256(11, n).g
+    eb = [2e-3, -1e-3, 5e-4]
+    M = int(math.ceil(0.05 * n * n))
+    _, ref = oracle_reduced(g, eb, M, tol=1e-11)
+    sref = stress_comps(ref.sigma_bar, 2)
+    e_ref, s_ref = _fields_from_oracle(ref, 2)
+    plan = mor.Plan(g, M)
+    keep = mor.tune_get(2, n)
+    nv = mor.tune_variants(2, n)
+    assert nv >= 1
+    try:
+        for v in range(nv):
+            mor.tune_set(2, n, v)
+            out = mor.solve(plan, np.array([eb]), native_phases(), 1e-7, want_fields=True)
+            assert out.status == mor.MOR_OK
+            err = np.max(np.abs(out.eff_stress[0] - sref)) / np.max(np.abs(sref))
+            assert err < 1e-5, (v, err)
+            assert rel_l2(out.strain[0].cpu().numpy(), e_ref) < 1e-4, v
+            assert rel_l2(out.stress[0].cpu().numpy(), s_ref) < 1e-4, v
+    finally:
+        mor.tune_set(2, n, keep)
+
+
+def test_autotune_keeps_results():
+    """The autotuner leaves a valid variant selected for each size of a mixed
+    batch, and solves after tuning agree with solves before it."""
+    mor = _mor()
+    gs = [synth.fibre_rve_256(20 + i, n).g for i, n in enumerate((128, 256, 256, 128))]
+    plans = [mor.Plan(g, int(math.ceil(0.05 * g.size))) for g in gs]
+    po = np.array([0, 1, 2, 3, 1, 0])
+    ebs = synth.macro_strains(len(po), 3, 5e-3, seed=5)
+    keep = {n: mor.tune_get(2, n) for n in (128, 256)}
+    try:
+        before = mor.solve_multi(plans, po, ebs, native_phases(), 1e-7)
+        mor.autotune(plans, po, ebs, native_phases(), 1e-7, reps=1)
+        for n in (128, 256):
+            assert 0 <= mor.tune_get(2, n) < mor.tune_variants(2, n)
+        after = mor.solve_multi(plans, po, ebs, native_phases(), 1e-7)
+        rel = np.max(np.abs(after.eff_stress - before.eff_stress)) / np.max(np.abs(before.eff_stress))
+        assert rel < 2e-6
+    finally:
+        for n, v in keep.items():
+            mor.tune_set(2, n, v)
