@@ -147,13 +147,14 @@ def timed_batched(mor, plans, plan_of, ebs, ph, steps, warmup, warm_fn=None):
     return out, elapsed, kern
 
 
-def timed_single(mor, plans, ebs, ph, count, warm_fn=None):
-    """Plain path: one RVE per call (mor_solve), optionally warm-started."""
+def timed_single(mor, plans, ebs, ph, count, warm_fn=None, use_graph=0):
+    """Plain path: one RVE per call (mor_solve), optionally warm-started and
+    with the iteration chunks replayed from a hipGraph."""
     import torch
 
     def one(i):
         w = warm_fn(i) if warm_fn else None
-        return mor.solve(plans[i], ebs[i:i + 1], ph, TOL, warm_start=w)
+        return mor.solve(plans[i], ebs[i:i + 1], ph, TOL, warm_start=w, use_graph=use_graph)
 
     for i in range(2):
         one(i)
@@ -272,9 +273,10 @@ def main():
 
     # plain path: one RVE per launch, cold and warm
     ns = min(args.single, B)
-    single_cold = single_warm = None
+    single_cold = single_warm = single_graph = None
     if ns > 0:
         single_cold = timed_single(mor, plans, ebs, ph, ns)
+        single_graph = timed_single(mor, plans, ebs, ph, ns, use_graph=1)
         if net is not None:
             single_warm = timed_single(
                 mor, plans, ebs, ph, ns,
@@ -340,6 +342,7 @@ def main():
             "batched_born_prior": born_rate,
             "batched_learned": learned["rate"] if learned else None,
             "single_cold": single_cold[0] if single_cold else None,
+            "single_cold_hipgraph": single_graph[0] if single_graph else None,
             "single_learned": single_warm[0] if single_warm else None,
         },
         "learned_vs_plain": {

@@ -323,13 +323,14 @@ def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int 
 
 
 def solve_path(plan: Plan, macro_strains, phases, tol: float, state, max_iter: int = 0, stream=None,
-               want_fields: bool = False, check_every: int = 0, allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
+               want_fields: bool = False, check_every: int = 0, use_graph: int = 0,
+               allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
     """mor_solve_path: macro_strains [steps][ncomp]; state: torch float32 cuda [nstate][N] (in/out)."""
     eb = np.ascontiguousarray(np.atleast_2d(macro_strains), dtype=np.float64)
     steps, C = eb.shape
     S = plan.nstress
     out, eff, its, res, strain, stress, coeffs = _outputs(steps, S, steps, want_fields, False, plan.N, C, 0)
-    opts = _opts(max_iter, check_every, None, stream)
+    opts = _opts(max_iter, check_every, None, stream, use_graph=use_graph)
     st = _check(lib.mor_solve_path(plan.handle, _np_ptr(eb), steps, _phases(phases), float(tol), ct.byref(opts),
                                    ct.c_void_p(state.data_ptr()), ct.byref(out)), allow)
     if strain is not None:

@@ -45,6 +45,7 @@ struct EventPair {
 struct Workspace {
   std::map<std::string, std::pair<void*, size_t>> bufs;
   unsigned int* h_active = nullptr;  // pinned
+  hipStream_t cap = nullptr;         // private stream for hipGraph capture
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
   ~Workspace() {}
@@ -70,6 +71,10 @@ struct Workspace {
     bufs[name] = {p, alloc};
     *out = reinterpret_cast<T*>(p);
     return MOR_OK;
+  }
+  hipStream_t capture_stream() {
+    if (!cap) (void)hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    return cap;
   }
   hipEvent_t event() {
     if (evnext == evpool.size()) {
@@ -224,6 +229,7 @@ struct SolveCtx {
   std::vector<std::vector<char>> keep;  // host staging that must outlive async copies
   std::vector<PlanDev> plan_dev;         // plan of every RVE (host copy)
   bool want_eps = false, want_sig = false;
+  bool capturing = false;  // kernels are being recorded into a hipGraph: no timing events
 };
 
 // Asynchronous upload from a host copy kept alive until the solve ends.
@@ -282,13 +288,13 @@ MatDev make_mat(const mor_phase* ph) {
 
 
 void ev_begin(SolveCtx& cx, int kind, hipEvent_t* a) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || cx.capturing) return;
   *a = cx.ws->event();
   (void)hipEventRecord(*a, cx.st);
   (void)kind;
 }
 void ev_end(SolveCtx& cx, int kind, hipEvent_t a) {
-  if (!g_prof_on) return;
+  if (!g_prof_on || cx.capturing) return;
   hipEvent_t b = cx.ws->event();
   (void)hipEventRecord(b, cx.st);
   cx.events.push_back({a, b, kind});
@@ -643,6 +649,39 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   return MOR_OK;
 }
 
+// One captured chunk of iterations (owns the graph and its executable).
+struct GraphChunk {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~GraphChunk() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  mor_status record(SolveCtx& cx, int check) {
+    hipStream_t solve_st = cx.st;
+    cx.st = cx.ws->capture_stream();
+    cx.capturing = true;
+    mor_status s = MOR_OK;
+    hipError_t e = hipStreamBeginCapture(cx.st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int k = 0; k < check && s == MOR_OK; ++k)
+        for (auto& g : cx.groups)
+          if ((s = do_iter(cx, g)) != MOR_OK) break;
+      hipError_t e2 = hipStreamEndCapture(cx.st, &graph);
+      if (e2 != hipSuccess && s == MOR_OK) e = e2;
+    }
+    cx.st = solve_st;
+    cx.capturing = false;
+    if (s != MOR_OK) return s;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      mor_set_error(std::string("hipGraph capture of the iteration chunk failed: ") + hipGetErrorString(e));
+      return MOR_E_DEVICE;
+    }
+    return MOR_OK;
+  }
+};
+
 mor_status run(SolveCtx& cx, const cpx<float>* warm, const mor_solve_opts* opts, float* eps, float* sig) {
   mor_status s;
   for (auto& g : cx.groups)
@@ -650,10 +689,23 @@ mor_status run(SolveCtx& cx, const cpx<float>* warm, const mor_solve_opts* opts,
   const int check = (opts && opts->check_every > 0) ? opts->check_every : 8;
   int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10000;
   int done = 0;
+  // With use_graph, one chunk of `check` iterations over all groups is
+  // recorded once (on a private stream: capture only records) and replayed
+  // as a single graph launch per chunk on the solve stream.  Every launch of
+  // a chunk has the same arguments (the iteration state lives in device
+  // memory), so the replays are the eager sequence.
+  GraphChunk gc;
+  if (opts && opts->use_graph) {
+    if ((s = gc.record(cx, check)) != MOR_OK) return s;
+  }
   while (true) {
-    for (int k = 0; k < check; ++k)
-      for (auto& g : cx.groups)
-        if ((s = do_iter(cx, g)) != MOR_OK) return s;
+    if (gc.exec) {
+      MOR_HIP_TRY(hipGraphLaunch(gc.exec, cx.st));
+    } else {
+      for (int k = 0; k < check; ++k)
+        for (auto& g : cx.groups)
+          if ((s = do_iter(cx, g)) != MOR_OK) return s;
+    }
     done += check;
     MOR_HIP_TRY(hipMemcpyAsync(cx.ws->h_active, cx.d_active, sizeof(unsigned int), hipMemcpyDeviceToHost, cx.st));
     MOR_HIP_TRY(hipStreamSynchronize(cx.st));

@@ -55,3 +55,20 @@ def test_homogeneous_j2_one_iteration_per_step():
     for k in range(5):
         want = stress_comps(ref[k].sigma_bar, 2)
         assert np.max(np.abs(out.eff_stress[k] - want)) < 1e-5 * np.max(np.abs(want))
+
+
+def test_load_path_graph_replay_matches_eager():
+    """The J2 load path with hipGraph-replayed iteration chunks equals the
+    eager path exactly (stress per step, iterations, final state)."""
+    import torch
+    import paper_2103_10203_amd as mor
+    g = synth.rsa_fibres(64, 64, 5.0, 10.0, seed=75, target_vf=0.4).g
+    plan = mor.Plan(g, 205)
+    path = np.stack([[0.005 * k, 0.0, 0.0] for k in range(1, 5)])
+    se = torch.zeros(5 * g.size, dtype=torch.float32, device="cuda")
+    sg = torch.zeros(5 * g.size, dtype=torch.float32, device="cuda")
+    oe = mor.solve_path(plan, path, native_phases(j2=True), 1e-6, se)
+    og = mor.solve_path(plan, path, native_phases(j2=True), 1e-6, sg, use_graph=1)
+    assert np.array_equal(oe.eff_stress, og.eff_stress)
+    assert np.array_equal(oe.iterations, og.iterations)
+    assert bool((se == sg).all())
