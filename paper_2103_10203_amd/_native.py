@@ -306,6 +306,7 @@ def solve(plan: Plan, macro_strain, phases, tol: float, max_iter: int = 0, warm_
 
 def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int = 0, warm_start=None, stream=None,
                 want_fields: bool = False, want_coeffs: bool = False, check_every: int = 0, use_graph: int = 0,
+                precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO,
                 allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
     """mor_solve_multi: RVE b uses plans[plan_of[b]]; outputs packed per RVE."""
     eb = np.ascontiguousarray(np.atleast_2d(macro_strain), dtype=np.float64)
@@ -316,7 +317,7 @@ def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int 
     npts = int(sum(plans[i].N for i in po))
     ncoef = int(sum(plans[i].n_coeff for i in po)) * C
     out, eff, its, res, strain, stress, coeffs = _outputs(B, S, B, want_fields, want_coeffs, npts, C, ncoef)
-    opts = _opts(max_iter, check_every, warm_start, stream, use_graph=use_graph)
+    opts = _opts(max_iter, check_every, warm_start, stream, precision, transform, use_graph)
     st = _check(lib.mor_solve_multi(handles, len(plans), _np_ptr(po), _np_ptr(eb), B, _phases(phases), float(tol),
                                     ct.byref(opts), ct.byref(out)), allow)
     return SolveResult(st, eff, its, res, strain, stress, coeffs)
@@ -324,13 +325,14 @@ def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int 
 
 def solve_path(plan: Plan, macro_strains, phases, tol: float, state, max_iter: int = 0, stream=None,
                want_fields: bool = False, check_every: int = 0, use_graph: int = 0,
+               precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO,
                allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
     """mor_solve_path: macro_strains [steps][ncomp]; state: torch float32 cuda [nstate][N] (in/out)."""
     eb = np.ascontiguousarray(np.atleast_2d(macro_strains), dtype=np.float64)
     steps, C = eb.shape
     S = plan.nstress
     out, eff, its, res, strain, stress, coeffs = _outputs(steps, S, steps, want_fields, False, plan.N, C, 0)
-    opts = _opts(max_iter, check_every, None, stream, use_graph=use_graph)
+    opts = _opts(max_iter, check_every, None, stream, precision, transform, use_graph)
     st = _check(lib.mor_solve_path(plan.handle, _np_ptr(eb), steps, _phases(phases), float(tol), ct.byref(opts),
                                    ct.c_void_p(state.data_ptr()), ct.byref(out)), allow)
     if strain is not None:

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "dft_kernels.h"
 #include "solve_fast.h"
 
 using namespace mor_k;
@@ -230,6 +231,9 @@ struct SolveCtx {
   std::vector<PlanDev> plan_dev;         // plan of every RVE (host copy)
   bool want_eps = false, want_sig = false;
   bool capturing = false;  // kernels are being recorded into a hipGraph: no timing events
+  bool dft = false;        // last-axis transform as MFMA GEMMs instead of the row FFT
+  int dft_prec = DFT_F32;  // DFT_F32 or DFT_X3 (split bf16)
+  float* d_dfte = nullptr; // DFT path: real field per RVE [C][N] (strain, then polarisation)
 };
 
 // Asynchronous upload from a host copy kept alive until the solve ends.
@@ -393,6 +397,35 @@ mor_status launch_init(SolveCtx& cx, Group& g, const cpx<float>* warm) {
   return MOR_OK;
 }
 
+// Last-axis stage of an iteration on the DFT path: inverse GEMM, pointwise
+// step a), forward GEMM.
+constexpr int kDftLmax = 512;
+constexpr int kDftRb = 8;  // rows per block of the pointwise kernel
+
+template <int PREC>
+void dft_inverse(SolveCtx& cx, Group& g, int C, int rows, int L, int mode_iter) {
+  dim3 gi(L / DFT_T, C * rows / DFT_T, (unsigned)g.rves.size());
+  k_dft_inv<PREC, kDftLmax><<<gi, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.d_dfte, C,
+                                                   mode_iter);
+}
+
+template <int PREC>
+void dft_forward(SolveCtx& cx, Group& g, int C, int rows) {
+  dim3 gf((2 * g.nlast_max + DFT_T - 1) / DFT_T, C * rows / DFT_T, (unsigned)g.rves.size());
+  k_dft_fwd<PREC, kDftLmax><<<gf, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.d_dfte, C);
+}
+
+template <int C, int MAT>
+void launch_dft_stage(SolveCtx& cx, Group& g, int rows, int L) {
+  if (cx.dft_prec == DFT_X3) dft_inverse<DFT_X3>(cx, g, C, rows, L, 1);
+  else dft_inverse<DFT_F32>(cx, g, C, rows, L, 1);
+  dim3 gp((rows + kDftRb - 1) / kDftRb, (unsigned)g.rves.size());
+  k_dft_point<C, MODE_ITER, MAT><<<gp, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.off, cx.mat, cx.d_dfte,
+                                                        cx.d_jstate, nullptr, nullptr, nullptr, kDftRb);
+  if (cx.dft_prec == DFT_X3) dft_forward<DFT_X3>(cx, g, C, rows);
+  else dft_forward<DFT_F32>(cx, g, C, rows);
+}
+
 template <int C, int MAT>
 mor_status launch_iter(SolveCtx& cx, Group& g) {
   const int nlen = C == 3 ? g.n1 : g.n2;
@@ -402,7 +435,9 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
   dim3 gr((rows + g.rb - 1) / g.rb, (unsigned)g.rves.size());
   hipEvent_t a{};
   ev_begin(cx, PK_ROW, &a);
-  if (g.fast_row)
+  if (cx.dft)
+    launch_dft_stage<C, MAT>(cx, g, rows, nlen);
+  else if (g.fast_row)
     row_fast<C, MODE_ITER, MAT>(cx, g, nullptr, nullptr);
   else
     k_row<C, MODE_ITER, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
@@ -450,7 +485,13 @@ mor_status launch_final(SolveCtx& cx, Group& g, float* eps, float* sig) {
   dim3 gr((rows + g.rb - 1) / g.rb, (unsigned)g.rves.size());
   hipEvent_t a{};
   ev_begin(cx, PK_FINAL, &a);
-  if (g.fast_row)
+  if (cx.dft) {
+    if (cx.dft_prec == DFT_X3) dft_inverse<DFT_X3>(cx, g, C, rows, nlen, 0);
+    else dft_inverse<DFT_F32>(cx, g, C, rows, nlen, 0);
+    dim3 gp((rows + kDftRb - 1) / kDftRb, (unsigned)g.rves.size());
+    k_dft_point<C, MODE_FINAL, MAT><<<gp, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.off, cx.mat, cx.d_dfte,
+                                                           cx.d_jstate, eps, sig, cx.d_sigpart, kDftRb);
+  } else if (g.fast_row)
     row_fast<C, MODE_FINAL, MAT>(cx, g, eps, sig);
   else
     k_row<C, MODE_FINAL, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
@@ -531,11 +572,24 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   cx.coef_off_h.resize(B);
   cx.field_off_h.resize(B);
   cx.ncoef_h.resize(B);
+  // transform of the last axis: the row FFT (default, and AUTO: measured
+  // faster on every size), or the MFMA partial DFT
+  if (opts && (opts->transform == MOR_TRANSFORM_DFT || opts->precision == MOR_PREC_BF16X3)) {
+    cx.dft = true;
+    cx.dft_prec = opts->precision == MOR_PREC_BF16X3 ? DFT_X3 : DFT_F32;
+  }
   for (auto& g : cx.groups) {
     const int nlen = g.ndim == 2 ? g.n1 : g.n2;
+    const int rows = g.ndim == 2 ? g.n0 : g.n0 * g.n1;
+    if (cx.dft && (rows % DFT_T != 0 || nlen % DFT_T != 0 || nlen > kDftLmax)) {
+      mor_set_error("the DFT transform needs rows and last-axis length multiples of 64 (length <= 512)");
+      return MOR_E_UNSUPPORTED;
+    }
     g.fast_row = has_fast_row(cx.C, nlen / 2);
     g.fast_col = has_fast_col(cx.C, g.n0);
-    if (g.fast_row) {
+    if (cx.dft) {
+      g.rb = kDftRb;
+    } else if (g.fast_row) {
       g.rvar = std::min(row_variant(cx.C, nlen / 2), row_variants(cx.C, nlen / 2) - 1);
       g.rb = fast_rb(cx.C, nlen / 2, g.rvar);
     } else {
@@ -543,8 +597,7 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     }
     g.cb = g.fast_col ? fast_cb(cx.C, g.n0) : cols_per_block(cx.C, g.n0);
     g.xb = g.ndim == 3 ? cols_per_block(cx.C, g.n1) : 1;
-    const int rows = g.ndim == 2 ? g.n0 : g.n0 * g.n1;
-    if (!g.fast_row) g.rb = std::min(g.rb, rows);
+    if (!g.fast_row && !cx.dft) g.rb = std::min(g.rb, rows);
   }
   std::vector<int> gof(B);
   for (size_t gi = 0; gi < cx.groups.size(); ++gi)
@@ -589,6 +642,7 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     cx.d_yc = cx.d_yl;
   }
   if ((s = ws.get("coef", (size_t)co, &cx.d_coef)) != MOR_OK) return s;
+  if (cx.dft && (s = ws.get("dfte", (size_t)fo * cx.C, &cx.d_dfte)) != MOR_OK) return s;
   if ((s = ws.get("part", (size_t)pa, &cx.d_part)) != MOR_OK) return s;
   if ((s = ws.get("sigpart", (size_t)pa * cx.S, &cx.d_sigpart)) != MOR_OK) return s;
   if ((s = ws.get("eff", (size_t)B * cx.S, &cx.d_eff)) != MOR_OK) return s;
@@ -760,10 +814,14 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
       const double it = hs[b].iters;
       const double C = cx.C, L = d.nlen;
       double row = d.rows * (16.0 * C * d.nlast + L);
+      // DFT path: spectra in/out plus the real field written, read,
+      // rewritten and read again between the GEMMs
+      if (cx.dft) row += 16.0 * C * d.N;
       if (cx.j2) row += d.rows * L * 4.0 * cx.NST;
       const double col = d.ncol * 16.0 * C * d.n0 + d.ncoef * (16.0 * C + 17.0);
       const double mid = cx.ndim == 3 ? d.n0 * 8.0 * C * ((double)d.nlast * d.n1 + d.ncol) : 0.0;
       double fin = d.rows * (8.0 * C * d.nlast + L);
+      if (cx.dft) fin += 8.0 * C * d.N;
       if (cx.want_eps) fin += (double)d.N * 4.0 * C;
       if (cx.want_sig) fin += (double)d.N * 4.0 * cx.S;
       if (cx.j2) fin += (double)d.N * 8.0 * cx.NST;
@@ -826,12 +884,16 @@ mor_status check_common(const double* ebar, int64_t B, int C, const mor_phase* p
       mor_set_error("max_iter and check_every must be >= 0");
       return MOR_E_INVALID_ARG;
     }
-    if (opts->precision != MOR_PREC_FP32) {
-      mor_set_error("only MOR_PREC_FP32 is available in this build");
-      return MOR_E_UNSUPPORTED;
+    if (opts->precision != MOR_PREC_FP32 && opts->precision != MOR_PREC_BF16X3) {
+      mor_set_error("precision must be MOR_PREC_FP32 or MOR_PREC_BF16X3");
+      return MOR_E_INVALID_ARG;
     }
-    if (opts->transform != MOR_TRANSFORM_AUTO && opts->transform != MOR_TRANSFORM_FFT) {
-      mor_set_error("only the FFT transform is available in this build");
+    if (opts->transform < MOR_TRANSFORM_AUTO || opts->transform > MOR_TRANSFORM_DFT) {
+      mor_set_error("unknown transform");
+      return MOR_E_INVALID_ARG;
+    }
+    if (opts->precision == MOR_PREC_BF16X3 && opts->transform == MOR_TRANSFORM_FFT) {
+      mor_set_error("MOR_PREC_BF16X3 applies to the DFT transform only");
       return MOR_E_UNSUPPORTED;
     }
   }

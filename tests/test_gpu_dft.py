@@ -1,0 +1,107 @@
+"""The last-axis partial DFT on the matrix cores (FP32 MFMA and split-bf16
+"bf16x3" MFMA with FP32 accumulation) against the FP64 oracle, and against
+the FFT path of the same library.
+
+Tolerances: FP32 MFMA as the FFT path (effective stress rel. 1e-5, fields
+rel. L2 1e-4); bf16x3: effective stress rel. 1e-4, fields rel. L2 1e-4, solved
+to residual 1e-5 (the split-bf16 products carry ~2^-16 relative error per
+term, which sets the residual floor)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import solver
+from tests.gpu_common import ORACLE_J2, native_phases, oracle_reduced, rel_l2, stress_comps
+
+pytestmark = pytest.mark.gpu
+
+
+def _mor():
+    import paper_2103_10203_amd as mor
+    return mor
+
+
+def _fields(res, dim):
+    eps = np.moveaxis(solver.tensor_comps(res.eps, dim), -1, 0)
+    sig = np.moveaxis(solver.tensor_comps(res.sigma, dim, with_s33=True), -1, 0)
+    return eps, sig
+
+
+CASES = [
+    ("disk64", 2), ("fibres256", 2), ("box3d", 3),
+]
+
+
+def _case(name):
+    if name == "disk64":
+        n = 64
+        return synth.disk(n, n, math.sqrt(0.3 * n * n / math.pi)), [1e-3, 0.0, 0.0], 205
+    if name == "fibres256":
+        g, eb = synth.metric_rve(5)
+        return g, list(eb), 3277
+    g = synth.rsa_spheres(32, 64, 64, 5.0, 9.0, seed=3, target_vf=0.25).g
+    eb = [1e-3, -5e-4, 2e-4, 3e-4, -1e-4, 4e-4]
+    return g, eb, int(math.ceil(0.02 * g.size))
+
+
+@pytest.mark.parametrize("name,dim", CASES)
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_dft_against_oracle(name, dim, prec):
+    mor = _mor()
+    g, eb, M = _case(name)
+    plan = mor.Plan(g, M)
+    p = mor.PREC_FP32 if prec == "fp32" else mor.PREC_BF16X3
+    tol = 1e-6 if prec == "fp32" else 1e-5
+    out = mor.solve(plan, np.array([eb]), native_phases(), tol, want_fields=True,
+                    transform=mor.TRANSFORM_DFT, precision=p)
+    assert out.status == mor.MOR_OK
+    _, ref = oracle_reduced(g, eb, M, tol=1e-12 if dim == 2 else 1e-10)
+    sref = stress_comps(ref.sigma_bar, dim)
+    err = np.max(np.abs(out.eff_stress[0] - sref)) / np.max(np.abs(sref))
+    assert err < (1e-5 if prec == "fp32" else 1e-4), err
+    e_ref, s_ref = _fields(ref, dim)
+    assert rel_l2(out.strain[0].cpu().numpy(), e_ref) < 1e-4
+    assert rel_l2(out.stress[0].cpu().numpy(), s_ref) < 1e-4
+    fft = mor.solve(plan, np.array([eb]), native_phases(), tol, transform=mor.TRANSFORM_FFT)
+    assert abs(int(out.iterations[0]) - int(fft.iterations[0])) <= 1
+
+
+def test_dft_batched_uneven_grids():
+    mor = _mor()
+    gs = [synth.fibre_rve_256(60 + i, n).g for i, n in enumerate((64, 128, 256))]
+    plans = [mor.Plan(g, int(math.ceil(0.05 * g.size))) for g in gs]
+    po = np.array([0, 1, 2, 2, 1, 0, 2])
+    ebs = synth.macro_strains(len(po), 3, 5e-3, seed=13)
+    fft = mor.solve_multi(plans, po, ebs, native_phases(), 1e-6)
+    d32 = mor.solve_multi(plans, po, ebs, native_phases(), 1e-6, transform=mor.TRANSFORM_DFT)
+    x3 = mor.solve_multi(plans, po, ebs, native_phases(), 1e-5, precision=mor.PREC_BF16X3)
+    scale = np.max(np.abs(fft.eff_stress))
+    assert np.max(np.abs(d32.eff_stress - fft.eff_stress)) < 2e-6 * scale
+    assert np.max(np.abs(x3.eff_stress - fft.eff_stress)) < 1e-4 * scale
+
+
+def test_dft_j2_load_path():
+    import torch
+    mor = _mor()
+    g = synth.rsa_fibres(64, 64, 5.0, 10.0, seed=75, target_vf=0.4).g
+    plan = mor.Plan(g, 205)
+    path = np.stack([[0.005 * k, 0.0, 0.0] for k in range(1, 4)])
+    s1 = torch.zeros(5 * g.size, dtype=torch.float32, device="cuda")
+    s2 = torch.zeros(5 * g.size, dtype=torch.float32, device="cuda")
+    a = mor.solve_path(plan, path, native_phases(j2=True), 1e-6, s1)
+    b = mor.solve_path(plan, path, native_phases(j2=True), 1e-6, s2, transform=mor.TRANSFORM_DFT)
+    assert np.max(np.abs(a.eff_stress - b.eff_stress)) < 1e-4 * np.max(np.abs(a.eff_stress))
+    assert rel_l2(s2.view(5, -1)[4].double().cpu().numpy(), s1.view(5, -1)[4].double().cpu().numpy()) < 1e-3
+
+
+def test_dft_rejects_unsupported_sizes():
+    mor = _mor()
+    g = synth.disk(96, 96, 20.0)
+    plan = mor.Plan(g, 461)
+    with pytest.raises(mor.MorError):
+        mor.solve(plan, np.array([[1e-3, 0, 0]]), native_phases(), 1e-6, transform=mor.TRANSFORM_DFT)
+    with pytest.raises(mor.MorError):
+        mor.solve(plan, np.array([[1e-3, 0, 0]]), native_phases(), 1e-6, precision=mor.PREC_BF16X3,
+                  transform=mor.TRANSFORM_FFT)
