@@ -121,6 +121,9 @@ def measured_traffic(kernel):
     return None
 
 
+SOLVE_KW = {}  # transform / precision of every solve (command line)
+
+
 def timed_batched(mor, plans, plan_of, ebs, ph, steps, warmup, warm_fn=None):
     """Batched solves of the whole workload; warm_fn (if given) builds the warm
     start inside the timed region (features, network, scatter)."""
@@ -128,7 +131,7 @@ def timed_batched(mor, plans, plan_of, ebs, ph, steps, warmup, warm_fn=None):
 
     def step():
         w = warm_fn() if warm_fn else None
-        return mor.solve_multi(plans, plan_of, ebs, ph, TOL, warm_start=w)
+        return mor.solve_multi(plans, plan_of, ebs, ph, TOL, warm_start=w, **SOLVE_KW)
 
     for _ in range(warmup):
         step()
@@ -154,7 +157,7 @@ def timed_single(mor, plans, ebs, ph, count, warm_fn=None, use_graph=0):
 
     def one(i):
         w = warm_fn(i) if warm_fn else None
-        return mor.solve(plans[i], ebs[i:i + 1], ph, TOL, warm_start=w, use_graph=use_graph)
+        return mor.solve(plans[i], ebs[i:i + 1], ph, TOL, warm_start=w, use_graph=use_graph, **SOLVE_KW)
 
     for i in range(2):
         one(i)
@@ -203,6 +206,10 @@ def main():
                     help="training microstructures of the warm-start network (0: cold start only)")
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--nslots", type=int, default=1024)
+    ap.add_argument("--transform", choices=["auto", "fft", "dft"], default="auto",
+                    help="last-axis transform of every solve (auto = the pruned FFT)")
+    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",
+                    help="bf16x3: split-bf16 MFMA partial DFT (implies --transform dft)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -222,6 +229,14 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    global TOL
+    SOLVE_KW["transform"] = {"auto": mor.TRANSFORM_AUTO, "fft": mor.TRANSFORM_FFT,
+                             "dft": mor.TRANSFORM_DFT}[args.transform]
+    SOLVE_KW["precision"] = mor.PREC_BF16X3 if args.precision == "bf16x3" else mor.PREC_FP32
+    dft = args.transform == "dft" or args.precision == "bf16x3"
+    if args.precision == "bf16x3":
+        TOL = 1e-5  # split-bf16 products set a residual floor near 1e-6
 
     B = args.batch
     t = time.perf_counter()
@@ -270,6 +285,22 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms"])
     kd = kern[dom]
     achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9 if kd["ms"] > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "avg_launch_us": kd["ms"] * 1e3 / max(kd["launches"], 1), "launches": kd["launches"]}
+    if dft:
+        # the last-axis stage is two dense GEMMs: 8 C rows nlast L flops per RVE-iteration
+        fl = sum(8.0 * p.ncomp * (p.N // p.shape[-1]) * p.info["n_last"] * p.shape[-1] * it
+                 for p, it in zip(plans, head_out.iterations)) * args.steps
+        kr = kern["row"]
+        bf = args.precision == "bf16x3"
+        mfma = fl * (3.0 if bf else 1.0) / (kr["ms"] * 1e-3) / 1e12
+        peak = 2500.0 if bf else 157.3
+        roof = {"bound": "mfma", "kernel": "row (DFT GEMMs + pointwise)", "achieved": mfma, "peak": peak,
+                "unit": "TFLOP/s", "frac": mfma / peak, "traffic": None,
+                "flops_note": "MFMA flops (bf16x3: three bf16 products per FP32 product)",
+                "avg_launch_us": kr["ms"] * 1e3 / max(kr["launches"], 1), "launches": kr["launches"]}
 
     # plain path: one RVE per launch, cold and warm
     ns = min(args.single, B)
@@ -308,7 +339,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16x3" if args.precision == "bf16x3" else "f32",
         "data": "synthetic",
         "config": {
             "workload": f"held-out random-fibre RVEs {GRID}x{GRID} (vf~U[0.2,0.5], r~U[8,16] px), "
@@ -320,19 +351,9 @@ def main():
             "tol": TOL,
             "start": start,
             "fields": "FP32, FP64 residual and stress sums",
+            "transform": args.transform, "precision": args.precision,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": dom,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom),
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "avg_launch_us": kd["ms"] * 1e3 / max(kd["launches"], 1),
-            "launches": kd["launches"],
-        },
+        "roofline": roof,
         "kernels": {k: {"ms": v["ms"], "launches": v["launches"],
                         "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else 0.0}
                     for k, v in kern.items()},
