@@ -29,22 +29,22 @@ template <int C, int NH>
 struct RowVar {
   static constexpr int count = 1;
 };
-template <> struct RowCfg<3, 32, 0>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
+template <> struct RowCfg<3, 32, 0>  { static constexpr int RL = 4, RB = 32; using RA = RList<8>; };
 template <> struct RowCfg<3, 32, 1>  { static constexpr int RL = 8, RB = 32; using RA = RList<4>; };
-template <> struct RowCfg<3, 32, 2>  { static constexpr int RL = 4, RB = 32; using RA = RList<8>; };
+template <> struct RowCfg<3, 32, 2>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
 template <> struct RowVar<3, 32> { static constexpr int count = 3; };
-template <> struct RowCfg<3, 64, 0>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
-template <> struct RowCfg<3, 64, 1>  { static constexpr int RL = 8, RB = 16; using RA = RList<8>; };
+template <> struct RowCfg<3, 64, 0>  { static constexpr int RL = 8, RB = 16; using RA = RList<8>; };
+template <> struct RowCfg<3, 64, 1>  { static constexpr int RL = 8, RB = 8;  using RA = RList<8>; };
 template <> struct RowCfg<3, 64, 2>  { static constexpr int RL = 8, RB = 32; using RA = RList<8>; };
 template <> struct RowCfg<3, 64, 3>  { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4>; };
-template <> struct RowCfg<3, 64, 4>  { static constexpr int RL = 8, RB = 8;  using RA = RList<8>; };
+template <> struct RowCfg<3, 64, 4>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
 template <> struct RowVar<3, 64> { static constexpr int count = 5; };
-template <> struct RowCfg<3, 128, 0> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 4>; };
-template <> struct RowCfg<3, 128, 1> { static constexpr int RL = 4, RB = 16; using RA = RList<8, 4>; };
-template <> struct RowCfg<3, 128, 2> { static constexpr int RL = 4, RB = 4;  using RA = RList<8, 4>; };
-template <> struct RowCfg<3, 128, 3> { static constexpr int RL = 8, RB = 16; using RA = RList<16>; };
-template <> struct RowCfg<3, 128, 4> { static constexpr int RL = 8, RB = 8;  using RA = RList<16>; };
-template <> struct RowCfg<3, 128, 5> { static constexpr int RL = 8, RB = 8;  using RA = RList<4, 4>; };
+template <> struct RowCfg<3, 128, 0> { static constexpr int RL = 8, RB = 16; using RA = RList<16>; };
+template <> struct RowCfg<3, 128, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<16>; };
+template <> struct RowCfg<3, 128, 2> { static constexpr int RL = 8, RB = 32; using RA = RList<16>; };
+template <> struct RowCfg<3, 128, 3> { static constexpr int RL = 8, RB = 16; using RA = RList<4, 4>; };
+template <> struct RowCfg<3, 128, 4> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 4>; };
+template <> struct RowCfg<3, 128, 5> { static constexpr int RL = 8, RB = 4;  using RA = RList<16>; };
 template <> struct RowVar<3, 128> { static constexpr int count = 6; };
 template <> struct RowCfg<3, 192, 0> { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4, 3>; };
 template <> struct RowCfg<3, 192, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<8, 3>; };
@@ -53,13 +53,21 @@ template <> struct RowCfg<3, 192, 3> { static constexpr int RL = 4, RB = 8;  usi
 template <> struct RowVar<3, 192> { static constexpr int count = 4; };
 template <> struct RowCfg<3, 256, 0> { static constexpr int RL = 8, RB = 8;  using RA = RList<4, 8>; };
 template <> struct RowCfg<3, 256, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<16, 2>; };
-template <> struct RowCfg<3, 256, 2> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 8>; };
-template <> struct RowCfg<3, 256, 3> { static constexpr int RL = 4, RB = 4;  using RA = RList<8, 8>; };
-template <> struct RowCfg<3, 256, 4> { static constexpr int RL = 8, RB = 4;  using RA = RList<4, 8>; };
+template <> struct RowCfg<3, 256, 2> { static constexpr int RL = 8, RB = 16; using RA = RList<4, 8>; };
+template <> struct RowCfg<3, 256, 3> { static constexpr int RL = 8, RB = 4;  using RA = RList<4, 8>; };
+template <> struct RowCfg<3, 256, 4> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 8>; };
 template <> struct RowVar<3, 256> { static constexpr int count = 5; };
 template <> struct RowCfg<6, 32, 0>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
+template <> struct RowCfg<6, 32, 1>  { static constexpr int RL = 8, RB = 16; using RA = RList<4>; };
+template <> struct RowVar<6, 32> { static constexpr int count = 2; };
 template <> struct RowCfg<6, 64, 0>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
+template <> struct RowCfg<6, 64, 1>  { static constexpr int RL = 8, RB = 8;  using RA = RList<8>; };
+template <> struct RowCfg<6, 64, 2>  { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4>; };
+template <> struct RowVar<6, 64> { static constexpr int count = 3; };
 template <> struct RowCfg<6, 128, 0> { static constexpr int RL = 4, RB = 4;  using RA = RList<8, 4>; };
+template <> struct RowCfg<6, 128, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<16>; };
+template <> struct RowCfg<6, 128, 2> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 4>; };
+template <> struct RowVar<6, 128> { static constexpr int count = 3; };
 
 template <int C, int NH, int V>
 constexpr int row_threads() {
@@ -125,51 +133,58 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
   cpx<float> v[C][RL];
 
   // ---- inverse transform, one component at a time
+  // Gather of the half spectra X[0..NH] of a component: item (k, row) for
+  // k = 0..NH/2 loads X[k] and X[NH-k] (zero outside the pattern); rows are the
+  // fastest index, so a wavefront reads runs of RB consecutive entries.  The
+  // loads of component c+1 are issued before the LDS passes of component c,
+  // so their latency overlaps the transform.
+  constexpr int GT = KH * RB;             // gather items per component
+  constexpr int GU = (GT + NT - 1) / NT;  // items per thread
+  cpx<float> xa[GU], xb[GU];
+  auto gather = [&](int c) {
+    const cpx<float>* ysrc = Y + (int64_t)c * cstride + r0 + rg;
+#pragma unroll
+    for (int u = 0; u < GU; ++u) {
+      const int t = tid + u * NT;  // t % RB == rg
+      xa[u] = {0.f, 0.f};
+      xb[u] = {0.f, 0.f};
+      if (t < GT && rlive) {
+        const int k = t / RB;
+        const int ja = kpos[k], jb = kpos[NH - k];
+        if (ja >= 0) xa[u] = ysrc[(int64_t)ja * rows];
+        if (jb >= 0) xb[u] = ysrc[(int64_t)jb * rows];
+      }
+    }
+  };
+  // register-pass twiddles (the same for every component; conjugated for the
+  // forward transform)
+  cpx<float> rtw[RL];
+#pragma unroll
+  for (int j = 0; j < RL; ++j) rtw[j] = fftr::twid<+1, 2>(T, j * i * (NH / (TR * RL)));
+  gather(0);
 #pragma unroll
   for (int c = 0; c < C; ++c) {
-    // gather the half spectra X[0..NH] of component c and pack them into
-    // length-NH sequences
+    // pack into the length-NH sequence
     //   z[k] = (X[k] + conj X[NH-k]) + i (X[k] - conj X[NH-k]) conj(T[k]);
-    // item (k, row) for k = 0..NH/2 writes z[k] and z[NH-k]; rows are the
-    // fastest index, so a wavefront reads runs of RB consecutive entries.
-    // Frequencies outside the pattern are zero; every z position is written.
-    {
-      constexpr int TOT = KH * RB;
-      constexpr int U = 4;
-      const cpx<float>* ysrc = Y + (int64_t)c * cstride + r0 + rg;
-      for (int t0 = tid; t0 < TOT; t0 += NT * U) {
-        cpx<float> xa[U], xb[U];
+    // item (k, row) writes z[k] and z[NH-k]; every z position is written.
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int t = t0 + u * NT;  // t % RB == rg
-          xa[u] = {0.f, 0.f};
-          xb[u] = {0.f, 0.f};
-          if (t < TOT && rlive) {
-            const int k = t / RB;
-            const int ja = kpos[k], jb = kpos[NH - k];
-            if (ja >= 0) xa[u] = ysrc[(int64_t)ja * rows];
-            if (jb >= 0) xb[u] = ysrc[(int64_t)jb * rows];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int t = t0 + u * NT;
-          if (t < TOT) {
-            const int k = t / RB;
-            cpx<float>* x = buf + rg * SS;
-            const cpx<float> Xk = xa[u], Xm = xb[u];
-            const cpx<float> a = cadd(Xk, cconj(Xm));
-            const cpx<float> d = cmul(csub(Xk, cconj(Xm)), cconj(T[pad16(k)]));
-            x[pad16(k)] = {a.x - d.y, a.y + d.x};
-            if (k != 0 && 2 * k != NH) {
-              const cpx<float> a2 = cadd(Xm, cconj(Xk));
-              const cpx<float> d2 = cmul(csub(Xm, cconj(Xk)), cconj(T[pad16(NH - k)]));
-              x[pad16(NH - k)] = {a2.x - d2.y, a2.y + d2.x};
-            }
-          }
+    for (int u = 0; u < GU; ++u) {
+      const int t = tid + u * NT;
+      if (t < GT) {
+        const int k = t / RB;
+        cpx<float>* x = buf + rg * SS;
+        const cpx<float> Xk = xa[u], Xm = xb[u];
+        const cpx<float> a = cadd(Xk, cconj(Xm));
+        const cpx<float> d = cmul(csub(Xk, cconj(Xm)), cconj(T[pad16(k)]));
+        x[pad16(k)] = {a.x - d.y, a.y + d.x};
+        if (k != 0 && 2 * k != NH) {
+          const cpx<float> a2 = cadd(Xm, cconj(Xk));
+          const cpx<float> d2 = cmul(csub(Xm, cconj(Xk)), cconj(T[pad16(NH - k)]));
+          x[pad16(NH - k)] = {a2.x - d2.y, a2.y + d2.x};
         }
       }
     }
+    if (c + 1 < C) gather(c + 1);
     __syncthreads();
     fftr::lds_passes<NH, +1, 1, RB, SS, NT, 2>(buf, T, tid, typename Cfg::RA{});
     // register pass: last inverse stage (radix RL, span TR)
@@ -177,7 +192,8 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
       const cpx<float>* src = buf + r * SS;
 #pragma unroll
       for (int j = 0; j < RL; ++j) v[c][j] = src[pad16(i + j * TR)];
-      fftr::pass_twiddle<NH, RL, TR, +1, 2>(v[c], i, T);
+#pragma unroll
+      for (int j = 1; j < RL; ++j) v[c][j] = cmul(v[c][j], rtw[j]);
       Dft<RL, +1>::run(v[c]);
     }
     __syncthreads();

@@ -252,3 +252,28 @@ def test_graph_replay_matches_eager():
     one_g = mor.solve(plans[1], ebs[:2], native_phases(), 1e-6, want_fields=True, use_graph=1)
     assert np.array_equal(one_e.eff_stress, one_g.eff_stress)
     assert bool((one_e.strain == one_g.strain).all())
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 64), (8, 16, 128), (8, 8, 256)])
+def test_row_kernel_variants_3d(shape):
+    """Every 3D row-kernel variant (six strain components) against the oracle."""
+    mor = _mor()
+    g = synth.rsa_spheres(*shape, r_lo=3.0, r_hi=5.0, seed=sum(shape), target_vf=0.2).g
+    M = int(math.ceil(0.03 * g.size))
+    eb = [1e-3, -4e-4, 3e-4, 2e-4, -1e-4, 5e-4]
+    _, ref = oracle_reduced(g, eb, M, tol=1e-10)
+    sref = stress_comps(ref.sigma_bar, 3)
+    e_ref, _ = _fields_from_oracle(ref, 3)
+    plan = mor.Plan(g, M)
+    L = shape[-1]
+    keep = mor.tune_get(3, L)
+    try:
+        for v in range(mor.tune_variants(3, L)):
+            mor.tune_set(3, L, v)
+            out = mor.solve(plan, np.array([eb]), native_phases(), 1e-7, want_fields=True)
+            assert out.status == mor.MOR_OK
+            err = np.max(np.abs(out.eff_stress[0] - sref)) / np.max(np.abs(sref))
+            assert err < 1e-5, (v, err)
+            assert rel_l2(out.strain[0].cpu().numpy(), e_ref) < 1e-4, v
+    finally:
+        mor.tune_set(3, L, keep)
