@@ -275,20 +275,21 @@ mor_status mor_warm_apply(const mor_plan_t* plans, int64_t nplans, const int64_t
 
 /* ----------------------------------------------------------------------
  * Kernel variants and autotuning (launch shape and FFT factorisation of the
- * row kernel; not part of the paper's method).  Variants of one size give the
- * same results up to FP32 rounding; a solve uses the variant selected for its
- * (ndim, last-axis length) when it starts, default 0.  The selection is per
+ * row and column kernels; not part of the paper's method).  Variants of one
+ * size give the same results up to FP32 rounding; a solve uses the variants
+ * selected for its sizes when it starts, default 0.  The selection is per
  * process, shared by all threads and devices.
- *   kernel  MOR_KERNEL_ROW
- *   ndim    2 or 3; length = the grid's last-axis length (n[ndim-1])
+ *   kernel  MOR_KERNEL_ROW (last axis) or MOR_KERNEL_COL (axis 0)
+ *   ndim    2 or 3; length = the grid's last-axis length n[ndim-1] (row) or
+ *           its axis-0 length n[0] (column)
  * MOR_E_INVALID_ARG when that size has no specialised row kernel or the
  * variant is out of range.
  * ---------------------------------------------------------------------- */
-enum { MOR_KERNEL_ROW = 0 };
+enum { MOR_KERNEL_ROW = 0, MOR_KERNEL_COL = 1 };
 mor_status mor_tune_variants(int32_t kernel, int32_t ndim, int32_t length, int32_t* count);
 mor_status mor_tune_get(int32_t kernel, int32_t ndim, int32_t length, int32_t* variant);
 mor_status mor_tune_set(int32_t kernel, int32_t ndim, int32_t length, int32_t variant);
-/* Autotuner: for every row length present among `plans`, runs the batched
+/* Autotuner: for every row and column length present among `plans`, runs the batched
  * solve (mor_solve_multi arguments) once untimed and `reps` times timed with
  * each variant, keeps the fastest (minimum wall time) and leaves it selected.
  * The solves' outputs are discarded. */

@@ -473,6 +473,7 @@ def warm_apply(plans, plan_of, nslots: int, phases, Y, macro_strain, stream=None
 
 # ---------------------------------------------------------------- kernel variants / autotuner
 KERNEL_ROW = 0
+KERNEL_COL = 1
 
 
 def tune_variants(ndim: int, length: int, kernel: int = KERNEL_ROW) -> int:

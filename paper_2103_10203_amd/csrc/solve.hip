@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "dft_kernels.h"
@@ -121,6 +122,7 @@ struct Group {
   int ncol_max = 0, nlast_max = 0;
   int rb = 1, cb = 1, xb = 1;
   int rvar = 0;  // row-kernel variant
+  int cvar = 0;  // column-kernel variant
   bool fast_row = false, fast_col = false;
   int* d_list = nullptr;
 };
@@ -190,17 +192,53 @@ int fast_rb(int C, int nh, int v) {
     default: return row_rb_v<6, 128>(v);
   }
 }
-int fast_cb(int C, int n0) {
+// Column-kernel variants per (C, n0), selected like the row variants.
+std::map<std::pair<int, int>, int> g_col_var;  // (C, n0) -> variant
+
+template <int C, int N0, int V = 0>
+int col_cb_v(int v) {
+  if constexpr (V < ColVar<C, N0>::count) {
+    return v == V ? ColCfg<C, N0, V>::CB : col_cb_v<C, N0, V + 1>(v);
+  } else {
+    return -1;
+  }
+}
+
+int col_variants(int C, int n0) {
   if (C == 3) {
     switch (n0) {
-      case 64: return ColCfg<3, 64>::CB;
-      case 128: return ColCfg<3, 128>::CB;
-      case 256: return ColCfg<3, 256>::CB;
-      case 384: return ColCfg<3, 384>::CB;
-      default: return ColCfg<3, 512>::CB;
+      case 64: return ColVar<3, 64>::count;
+      case 128: return ColVar<3, 128>::count;
+      case 256: return ColVar<3, 256>::count;
+      case 384: return ColVar<3, 384>::count;
+      case 512: return ColVar<3, 512>::count;
+      default: return 0;
     }
   }
-  return n0 == 64 ? ColCfg<6, 64>::CB : ColCfg<6, 128>::CB;
+  switch (n0) {
+    case 64: return ColVar<6, 64>::count;
+    case 128: return ColVar<6, 128>::count;
+    default: return 0;
+  }
+}
+
+int col_variant(int C, int n0) {
+  std::lock_guard<std::mutex> lk(g_var_mu);
+  auto it = g_col_var.find({C, n0});
+  return it == g_col_var.end() ? 0 : it->second;
+}
+
+int fast_cb(int C, int n0, int v) {
+  if (C == 3) {
+    switch (n0) {
+      case 64: return col_cb_v<3, 64>(v);
+      case 128: return col_cb_v<3, 128>(v);
+      case 256: return col_cb_v<3, 256>(v);
+      case 384: return col_cb_v<3, 384>(v);
+      default: return col_cb_v<3, 512>(v);
+    }
+  }
+  return n0 == 64 ? col_cb_v<6, 64>(v) : col_cb_v<6, 128>(v);
 }
 
 struct SolveCtx {
@@ -350,11 +388,27 @@ void row_fast(SolveCtx& cx, Group& g, float* eps, float* sig) {
   }
 }
 
+template <int C, int N0, int V, int MODE>
+void go_col_fast_v(SolveCtx& cx, Group& g, const cpx<float>* warm) {
+  if constexpr (V < ColVar<C, N0>::count) {
+    using Cfg = ColCfg<C, N0, V>;
+    dim3 gc((g.ncol_max + Cfg::CB - 1) / Cfg::CB, (unsigned)g.rves.size());
+    k_col_fast<C, N0, V, MODE><<<gc, col_threads<C, N0, V>(), col_lds_bytes<C, N0, V>(), cx.st>>>(
+        cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef, warm, cx.off, cx.d_part, cx.mat);
+  }
+}
+
 template <int C, int N0, int MODE>
 void go_col_fast(SolveCtx& cx, Group& g, const cpx<float>* warm) {
-  dim3 gc((g.ncol_max + ColCfg<C, N0>::CB - 1) / ColCfg<C, N0>::CB, (unsigned)g.rves.size());
-  k_col_fast<C, N0, MODE><<<gc, col_threads<C, N0>(), col_lds_bytes<C, N0>(), cx.st>>>(
-      cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef, warm, cx.off, cx.d_part, cx.mat);
+  static_assert(ColVar<C, N0>::count <= 6, "dispatch covers six variants");
+  switch (g.cvar) {
+    case 0: go_col_fast_v<C, N0, 0, MODE>(cx, g, warm); break;
+    case 1: go_col_fast_v<C, N0, 1, MODE>(cx, g, warm); break;
+    case 2: go_col_fast_v<C, N0, 2, MODE>(cx, g, warm); break;
+    case 3: go_col_fast_v<C, N0, 3, MODE>(cx, g, warm); break;
+    case 4: go_col_fast_v<C, N0, 4, MODE>(cx, g, warm); break;
+    default: go_col_fast_v<C, N0, 5, MODE>(cx, g, warm); break;
+  }
 }
 
 template <int C, int MODE>
@@ -595,7 +649,12 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     } else {
       g.rb = rows_per_block(cx.C, nlen);
     }
-    g.cb = g.fast_col ? fast_cb(cx.C, g.n0) : cols_per_block(cx.C, g.n0);
+    if (g.fast_col) {
+      g.cvar = std::min(col_variant(cx.C, g.n0), col_variants(cx.C, g.n0) - 1);
+      g.cb = fast_cb(cx.C, g.n0, g.cvar);
+    } else {
+      g.cb = cols_per_block(cx.C, g.n0);
+    }
     g.xb = g.ndim == 3 ? cols_per_block(cx.C, g.n1) : 1;
     if (!g.fast_row && !cx.dft) g.rb = std::min(g.rb, rows);
   }
@@ -1075,10 +1134,23 @@ extern "C" mor_status mor_profile_query(const char* kernel, double* total_ms, in
 namespace {
 int comps_of_ndim(int ndim) { return ndim == 2 ? 3 : ndim == 3 ? 6 : 0; }
 
+// Variant table of (kernel, C, length): key size = half row length (row) or
+// n0 (column).
+int tune_count(int kernel, int C, int length) {
+  if (C == 0 || length < 2) return 0;
+  if (kernel == MOR_KERNEL_ROW) return (length & 1) ? 0 : row_variants(C, length / 2);
+  if (kernel == MOR_KERNEL_COL) return col_variants(C, length);
+  return 0;
+}
+std::map<std::pair<int, int>, int>& tune_table(int kernel) { return kernel == MOR_KERNEL_ROW ? g_row_var : g_col_var; }
+std::pair<int, int> tune_key(int kernel, int C, int length) {
+  return {C, kernel == MOR_KERNEL_ROW ? length / 2 : length};
+}
+
 mor_status check_tune_args(int32_t kernel, int32_t ndim, int32_t length, int* C, int* nh, const char* who) {
   *C = comps_of_ndim(ndim);
-  *nh = length / 2;
-  if (kernel != MOR_KERNEL_ROW || *C == 0 || length < 2 || (length & 1) || row_variants(*C, *nh) == 0) {
+  *nh = length;
+  if (tune_count(kernel, *C, length) == 0) {
     mor_set_error(std::string(who) + ": no tunable kernel for this (kernel, ndim, length)");
     return MOR_E_INVALID_ARG;
   }
@@ -1094,7 +1166,7 @@ extern "C" mor_status mor_tune_variants(int32_t kernel, int32_t ndim, int32_t le
   }
   mor_status s = check_tune_args(kernel, ndim, length, &C, &nh, "mor_tune_variants");
   if (s != MOR_OK) return s;
-  *count = row_variants(C, nh);
+  *count = tune_count(kernel, C, length);
   return MOR_OK;
 }
 
@@ -1106,7 +1178,10 @@ extern "C" mor_status mor_tune_get(int32_t kernel, int32_t ndim, int32_t length,
   }
   mor_status s = check_tune_args(kernel, ndim, length, &C, &nh, "mor_tune_get");
   if (s != MOR_OK) return s;
-  *variant = row_variant(C, nh);
+  std::lock_guard<std::mutex> lk(g_var_mu);
+  auto& t = tune_table(kernel);
+  auto it = t.find(tune_key(kernel, C, length));
+  *variant = it == t.end() ? 0 : it->second;
   return MOR_OK;
 }
 
@@ -1114,12 +1189,12 @@ extern "C" mor_status mor_tune_set(int32_t kernel, int32_t ndim, int32_t length,
   int C, nh;
   mor_status s = check_tune_args(kernel, ndim, length, &C, &nh, "mor_tune_set");
   if (s != MOR_OK) return s;
-  if (variant < 0 || variant >= row_variants(C, nh)) {
+  if (variant < 0 || variant >= tune_count(kernel, C, length)) {
     mor_set_error("mor_tune_set: variant out of range");
     return MOR_E_INVALID_ARG;
   }
   std::lock_guard<std::mutex> lk(g_var_mu);
-  g_row_var[{C, nh}] = variant;
+  tune_table(kernel)[tune_key(kernel, C, length)] = variant;
   return MOR_OK;
 }
 
@@ -1134,15 +1209,18 @@ extern "C" mor_status mor_autotune(const mor_plan_t* plans, int64_t nplans, cons
     mor_set_error("mor_autotune: invalid argument");
     return MOR_E_INVALID_ARG;
   }
-  std::vector<std::pair<int, int>> sizes;  // (ndim, last-axis length)
+  // (kernel, ndim, length): the row kernel of every last-axis length and the
+  // column kernel of every axis-0 length present
+  std::vector<std::tuple<int, int, int>> sizes;
   for (int64_t i = 0; i < nplans; ++i) {
     if (!plans[i]) {
       mor_set_error("mor_autotune: NULL plan");
       return MOR_E_INVALID_ARG;
     }
     const int nd = plans[i]->ndim;
-    std::pair<int, int> key{nd, plans[i]->n[nd - 1]};
-    if (std::find(sizes.begin(), sizes.end(), key) == sizes.end()) sizes.push_back(key);
+    for (auto key : {std::make_tuple((int)MOR_KERNEL_ROW, nd, plans[i]->n[nd - 1]),
+                     std::make_tuple((int)MOR_KERNEL_COL, nd, plans[i]->n[0])})
+      if (std::find(sizes.begin(), sizes.end(), key) == sizes.end()) sizes.push_back(key);
   }
   mor_solve_opts o{};
   o.stream = stream;
@@ -1154,16 +1232,22 @@ extern "C" mor_status mor_autotune(const mor_plan_t* plans, int64_t nplans, cons
   out.eff_stress = eff.data();
   out.iterations = its.data();
   out.residual = res.data();
-  for (auto [nd, len] : sizes) {
-    const int C = comps_of_ndim(nd), nh = len / 2;
-    const int nv = (len % 2 == 0) ? row_variants(C, nh) : 0;
+  for (auto [kernel, nd, len] : sizes) {
+    const int C = comps_of_ndim(nd);
+    const int nv = tune_count(kernel, C, len);
     if (nv < 2) continue;
-    int best = row_variant(C, nh);
+    const auto key = tune_key(kernel, C, len);
+    int best = 0;
+    {
+      std::lock_guard<std::mutex> lk(g_var_mu);
+      auto it = tune_table(kernel).find(key);
+      if (it != tune_table(kernel).end()) best = it->second;
+    }
     double best_t = 1e300;
     for (int v = 0; v < nv; ++v) {
       {
         std::lock_guard<std::mutex> lk(g_var_mu);
-        g_row_var[{C, nh}] = v;
+        tune_table(kernel)[key] = v;
       }
       mor_status s = mor_solve_multi(plans, nplans, plan_of_rve, macro_strain_packed, B, phase, tol, &o, &out);
       if (s != MOR_OK && s != MOR_E_NOT_CONVERGED) return s;
@@ -1181,7 +1265,7 @@ extern "C" mor_status mor_autotune(const mor_plan_t* plans, int64_t nplans, cons
       }
     }
     std::lock_guard<std::mutex> lk(g_var_mu);
-    g_row_var[{C, nh}] = best;
+    tune_table(kernel)[key] = best;
   }
   return MOR_OK;
 }

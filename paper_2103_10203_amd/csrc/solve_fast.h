@@ -301,36 +301,57 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
 
 // Column kernel configuration for axis-0 length N0: forward RF (register,
 // from global), then FA...; inverse FA reversed, then RF (register, to
-// global).  CB columns per workgroup, N0/RF threads per sequence.
-template <int C, int N0>
+// global).  CB columns per workgroup, N0/RF threads per sequence.  Variants V
+// as for the row kernel (RowVar): same results up to FP32 rounding.
+template <int C, int N0, int V>
 struct ColCfg;
-template <> struct ColCfg<3, 64>  { static constexpr int RF = 8, CB = 8; using FA = RList<8>; };
-template <> struct ColCfg<3, 128> { static constexpr int RF = 8, CB = 4; using FA = RList<4, 4>; };
-template <> struct ColCfg<3, 256> { static constexpr int RF = 8, CB = 2; using FA = RList<8, 4>; };
-template <> struct ColCfg<3, 384> { static constexpr int RF = 6, CB = 1; using FA = RList<8, 8>; };
-template <> struct ColCfg<3, 512> { static constexpr int RF = 8, CB = 1; using FA = RList<8, 8>; };
-template <> struct ColCfg<6, 64>  { static constexpr int RF = 8, CB = 4; using FA = RList<8>; };
-template <> struct ColCfg<6, 128> { static constexpr int RF = 8, CB = 2; using FA = RList<4, 4>; };
-
 template <int C, int N0>
+struct ColVar {
+  static constexpr int count = 1;
+};
+template <> struct ColCfg<3, 64, 0>  { static constexpr int RF = 8,  CB = 8; using FA = RList<8>; };
+template <> struct ColCfg<3, 64, 1>  { static constexpr int RF = 4,  CB = 4; using FA = RList<4, 4>; };
+template <> struct ColVar<3, 64> { static constexpr int count = 2; };
+template <> struct ColCfg<3, 128, 0> { static constexpr int RF = 4,  CB = 2; using FA = RList<8, 4>; };
+template <> struct ColCfg<3, 128, 1> { static constexpr int RF = 16, CB = 8; using FA = RList<8>; };
+template <> struct ColCfg<3, 128, 2> { static constexpr int RF = 8,  CB = 4; using FA = RList<4, 4>; };
+template <> struct ColVar<3, 128> { static constexpr int count = 3; };
+template <> struct ColCfg<3, 256, 0> { static constexpr int RF = 8,  CB = 2; using FA = RList<8, 4>; };
+template <> struct ColCfg<3, 256, 1> { static constexpr int RF = 4,  CB = 1; using FA = RList<8, 8>; };
+template <> struct ColCfg<3, 256, 2> { static constexpr int RF = 16, CB = 4; using FA = RList<16>; };
+template <> struct ColCfg<3, 256, 3> { static constexpr int RF = 8,  CB = 4; using FA = RList<8, 4>; };
+template <> struct ColCfg<3, 256, 4> { static constexpr int RF = 8,  CB = 2; using FA = RList<4, 8>; };
+template <> struct ColCfg<3, 256, 5> { static constexpr int RF = 16, CB = 8; using FA = RList<16>; };
+template <> struct ColVar<3, 256> { static constexpr int count = 6; };
+template <> struct ColCfg<3, 384, 0> { static constexpr int RF = 6,  CB = 1; using FA = RList<8, 8>; };
+template <> struct ColCfg<3, 512, 0> { static constexpr int RF = 8,  CB = 1; using FA = RList<8, 8>; };
+template <> struct ColCfg<3, 512, 1> { static constexpr int RF = 16, CB = 4; using FA = RList<8, 4>; };
+template <> struct ColCfg<3, 512, 2> { static constexpr int RF = 8,  CB = 2; using FA = RList<8, 8>; };
+template <> struct ColVar<3, 512> { static constexpr int count = 3; };
+template <> struct ColCfg<6, 64, 0>  { static constexpr int RF = 8,  CB = 4; using FA = RList<8>; };
+template <> struct ColCfg<6, 128, 0> { static constexpr int RF = 16, CB = 4; using FA = RList<8>; };
+template <> struct ColCfg<6, 128, 1> { static constexpr int RF = 8,  CB = 2; using FA = RList<4, 4>; };
+template <> struct ColVar<6, 128> { static constexpr int count = 2; };
+
+template <int C, int N0, int V>
 constexpr int col_threads() {
-  return ColCfg<C, N0>::CB * C * (N0 / ColCfg<C, N0>::RF);
+  return ColCfg<C, N0, V>::CB * C * (N0 / ColCfg<C, N0, V>::RF);
 }
 template <int N0>
 constexpr int col_ss() {
   return fftr::seq_stride(N0);
 }
-template <int C, int N0>
+template <int C, int N0, int V>
 constexpr size_t col_lds_bytes() {
-  return (size_t)(pad16(N0 - 1) + 1 + 2 * C * ColCfg<C, N0>::CB * col_ss<N0>()) * sizeof(cpx<float>);
+  return (size_t)(pad16(N0 - 1) + 1 + 2 * C * ColCfg<C, N0, V>::CB * col_ss<N0>()) * sizeof(cpx<float>);
 }
 
-template <int C, int N0, int MODE>
-__global__ __launch_bounds__((col_threads<C, N0>())) void k_col_fast(
+template <int C, int N0, int V, int MODE>
+__global__ __launch_bounds__((col_threads<C, N0, V>())) void k_col_fast(
     const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
     const double* __restrict__ ebar, cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
     const cpx<float>* __restrict__ warm, Offs off, double* __restrict__ part, MatDev mat) {
-  using Cfg = ColCfg<C, N0>;
+  using Cfg = ColCfg<C, N0, V>;
   constexpr int RF = Cfg::RF, CB = Cfg::CB;
   constexpr int TS = N0 / RF;
   constexpr int NT = CB * C * TS;

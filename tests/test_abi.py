@@ -76,3 +76,12 @@ def test_tune_api_host_side():
         mor.tune_set(2, 256, mor.tune_variants(2, 256))
     with pytest.raises(mor.MorError):
         mor.tune_set(2, 256, -1)
+    assert mor.tune_variants(2, 256, mor.KERNEL_COL) >= 2
+    mor.tune_set(2, 256, 1, mor.KERNEL_COL)
+    assert mor.tune_get(2, 256, mor.KERNEL_COL) == 1
+    assert mor.tune_get(2, 256) == keep  # the row table is separate
+    mor.tune_set(2, 256, 0, mor.KERNEL_COL)
+    with pytest.raises(mor.MorError):
+        mor.tune_variants(2, 100, mor.KERNEL_COL)
+    with pytest.raises(mor.MorError):
+        mor.tune_variants(2, 256, 7)

@@ -277,3 +277,35 @@ def test_row_kernel_variants_3d(shape):
             assert rel_l2(out.strain[0].cpu().numpy(), e_ref) < 1e-4, v
     finally:
         mor.tune_set(3, L, keep)
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (128, 128), (256, 256), (512, 64), (128, 16, 16)])
+def test_col_kernel_variants(shape):
+    """Every column-kernel variant (axis-0 FFT factorisation, columns per
+    workgroup) against the FP64 oracle."""
+    mor = _mor()
+    nd = len(shape)
+    if nd == 2:
+        g = synth.rsa_fibres(*shape, r_lo=min(shape) / 16, r_hi=min(shape) / 8, seed=sum(shape), target_vf=0.35).g
+        eb = [2e-3, -1e-3, 5e-4]
+        M = int(math.ceil(0.05 * g.size))
+    else:
+        g = synth.rsa_spheres(*shape, r_lo=3.0, r_hi=5.0, seed=sum(shape), target_vf=0.2).g
+        eb = [1e-3, -4e-4, 3e-4, 2e-4, -1e-4, 5e-4]
+        M = int(math.ceil(0.03 * g.size))
+    _, ref = oracle_reduced(g, eb, M, tol=1e-11 if nd == 2 else 1e-10)
+    sref = stress_comps(ref.sigma_bar, nd)
+    e_ref, _ = _fields_from_oracle(ref, nd)
+    plan = mor.Plan(g, M)
+    n0 = shape[0]
+    keep = mor.tune_get(nd, n0, mor.KERNEL_COL)
+    try:
+        for v in range(mor.tune_variants(nd, n0, mor.KERNEL_COL)):
+            mor.tune_set(nd, n0, v, mor.KERNEL_COL)
+            out = mor.solve(plan, np.array([eb]), native_phases(), 1e-7, want_fields=True)
+            assert out.status == mor.MOR_OK
+            err = np.max(np.abs(out.eff_stress[0] - sref)) / np.max(np.abs(sref))
+            assert err < 1e-5, (v, err)
+            assert rel_l2(out.strain[0].cpu().numpy(), e_ref) < 1e-4, v
+    finally:
+        mor.tune_set(nd, n0, keep, mor.KERNEL_COL)
