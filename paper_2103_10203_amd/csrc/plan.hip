@@ -99,12 +99,25 @@ __global__ void k_twiddle_f64(cpx<double>* tw, int n) {
   tw[t] = {c, -s};
 }
 
-__global__ void k_twiddle_f32(cpx<float>* tw, int n, int len) {
-  // tw[t] = exp(-2 pi i t / n), t < len
+// The four solver twiddle tables in one launch, packed tw0 [n0] | tw1 [n1] |
+// twh [nh] | rtw [nl], each exp(-2 pi i t / length) rounded from FP64.
+__global__ void k_twiddle4_f32(cpx<float>* tw, int n0, int n1, int nh, int nl) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= len) return;
+  int n;
+  int u = t;
+  if (u < n0) {
+    n = n0;
+  } else if ((u -= n0) < n1) {
+    n = n1;
+  } else if ((u -= n1) < nh) {
+    n = nh;
+  } else if ((u -= nh) < nl) {
+    n = nl;
+  } else {
+    return;
+  }
   double s, c;
-  sincospi(2.0 * (double)t / (double)n, &s, &c);
+  sincospi(2.0 * (double)u / (double)n, &s, &c);
   tw[t] = {(float)c, (float)(-s)};
 }
 
@@ -278,14 +291,47 @@ __global__ void k_select(const SortEl* __restrict__ el, int64_t nreps, Dims d, i
 }
 
 // Mask -> ascending linear indices (single workgroup).
-__global__ void k_compact(const uint8_t* __restrict__ mask, int64_t N, int64_t* __restrict__ sorted) {
+// Sorted pattern (increasing linear index) in three launches: per-chunk
+// counts, an exclusive scan of the counts, and the scatter of each chunk.
+constexpr int kCompactChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_compact_count(const uint8_t* __restrict__ mask, int64_t N,
+                                                       int* __restrict__ ccount) {
   __shared__ int lds[32];
-  int64_t base = 0;
-  for (int64_t c0 = 0; c0 < N; c0 += blockDim.x) {
-    int64_t i = c0 + threadIdx.x;
-    int f = (i < N) ? (int)mask[i] : 0;
+  const int64_t c0 = (int64_t)blockIdx.x * kCompactChunk;
+  int n = 0;
+  for (int t = threadIdx.x; t < kCompactChunk; t += 256) {
+    const int64_t i = c0 + t;
+    n += (i < N) ? (int)mask[i] : 0;
+  }
+  int total;
+  (void)block_excl_scan(n, lds, &total);
+  if (threadIdx.x == 0) ccount[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_compact_scan(int* __restrict__ ccount, int nchunk) {
+  __shared__ int lds[32];
+  int base = 0;
+  for (int c0 = 0; c0 < nchunk; c0 += 1024) {
+    const int i = c0 + threadIdx.x;
+    const int v = i < nchunk ? ccount[i] : 0;
     int total;
-    int ex = block_excl_scan(f, lds, &total);
+    const int ex = block_excl_scan(v, lds, &total);
+    if (i < nchunk) ccount[i] = base + ex;
+    base += total;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_compact_scatter(const uint8_t* __restrict__ mask, int64_t N,
+                                                         const int* __restrict__ cbase, int64_t* __restrict__ sorted) {
+  __shared__ int lds[32];
+  const int64_t c0 = (int64_t)blockIdx.x * kCompactChunk;
+  int base = cbase[blockIdx.x];
+  for (int t0 = 0; t0 < kCompactChunk; t0 += 256) {
+    const int64_t i = c0 + t0 + threadIdx.x;
+    const int f = (i < N) ? (int)mask[i] : 0;
+    int total;
+    const int ex = block_excl_scan(f, lds, &total);
     if (f) sorted[base + ex] = i;
     base += total;
   }
@@ -306,18 +352,22 @@ __global__ void k_slots(const SortEl* __restrict__ el, int64_t nslots, const cpx
 
 // Half-spectrum columns: column c = kh * n1 + k1 (3D) or c = kh (2D), kh the
 // last-axis frequency in [0, nlen/2].
-__global__ void k_tab_count(const uint8_t* __restrict__ mask, Dims d, int ncolall, int* __restrict__ cnt,
-                            int* __restrict__ lastcnt) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_tab_count(const uint8_t* __restrict__ mask, Dims d, int ncolall,
+                                                   int* __restrict__ cnt, int* __restrict__ lastcnt) {
+  // one wavefront per column: lanes stride over k0, wavefront sum
+  const int c = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
   if (c >= ncolall) return;
   int n = 0;
+  const int kh = d.nd == 2 ? c : c / d.n1;
   if (d.nd == 2) {
-    for (int k0 = 0; k0 < d.n0; ++k0) n += mask[(int64_t)k0 * d.n1 + c];
-    cnt[c] = n;
-    if (n) atomicAdd(&lastcnt[c], n);
+    for (int k0 = lane; k0 < d.n0; k0 += 64) n += mask[(int64_t)k0 * d.n1 + c];
   } else {
-    int kh = c / d.n1, k1 = c - kh * d.n1;
-    for (int k0 = 0; k0 < d.n0; ++k0) n += mask[((int64_t)k0 * d.n1 + k1) * d.n2 + kh];
+    const int k1 = c - kh * d.n1;
+    for (int k0 = lane; k0 < d.n0; k0 += 64) n += mask[((int64_t)k0 * d.n1 + k1) * d.n2 + kh];
+  }
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_down(n, o, 64);
+  if (lane == 0) {
     cnt[c] = n;
     if (n) atomicAdd(&lastcnt[kh], n);
   }
@@ -379,16 +429,81 @@ __global__ void k_tab_groups(const int* __restrict__ col_kh, const int* __restri
 }
 
 // Pattern entries of each column, rows ascending, with Green directions.
-__global__ void k_tab_fill(const uint8_t* __restrict__ mask, Dims d, int ncolall, const int* __restrict__ colidx,
-                           const int* __restrict__ col_off, int gamma_kind, int* __restrict__ coef_k0,
-                           int64_t* __restrict__ coef_lin, float* __restrict__ coef_n, uint8_t* __restrict__ flag,
-                           const int* __restrict__ pairof, int* __restrict__ coef_slot) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ void coef_entry(const uint8_t* __restrict__ mask, Dims d, int gamma_kind, const int* k, int64_t lin, int e,
+                           int* __restrict__ coef_k0, int64_t* __restrict__ coef_lin, float* __restrict__ coef_n,
+                           uint8_t* __restrict__ flag, const int* __restrict__ pairof, int* __restrict__ coef_slot) {
+  const int n[3] = {d.n0, d.n1, d.n2};
+  coef_k0[e] = k[0];
+  coef_lin[e] = lin;
+  {
+    // slot s = pair - 1 (pair 0 is xi = 0 -> -1); bit 30: stored member is the partner
+    const int pr = pairof[lin];
+    const int pair = pr & ((1 << 30) - 1);
+    coef_slot[e] = pair == 0 ? -1 : ((pair - 1) | (pr & (1 << 30)));
+  }
+  double v[3] = {0.0, 0.0, 0.0};
+  uint8_t f = 0;
+  bool zero = true, selfc = true;
+  int nyq = 0, nyq_axis = -1;
+  for (int a = 0; a < d.nd; ++a) {
+    if (k[a] != 0) zero = false;
+    bool isn = (n[a] % 2 == 0) && (k[a] == n[a] / 2);
+    if (isn) {
+      ++nyq;
+      nyq_axis = a;
+    }
+    if (!(k[a] == 0 || isn)) selfc = false;
+  }
+  if (zero) {
+    f = COEF_ZERO;
+  } else if (gamma_kind == MOR_GAMMA_ROTATED) {
+    if (nyq >= 2) {
+      f = COEF_DEAD;
+    } else if (nyq == 1) {
+      v[nyq_axis] = 1.0;
+    } else {
+      double nn = 0.0;
+      for (int a = 0; a < d.nd; ++a) {
+        v[a] = tan(M_PI * (double)k[a] / (double)n[a]);
+        nn += v[a] * v[a];
+      }
+      nn = sqrt(nn);
+      for (int a = 0; a < d.nd; ++a) v[a] /= nn;
+    }
+  } else {
+    if (nyq >= 1 && !selfc) {
+      f = COEF_DEAD;
+    } else {
+      double nn = 0.0;
+      for (int a = 0; a < d.nd; ++a) {
+        v[a] = (double)signed_k(k[a], n[a]);
+        nn += v[a] * v[a];
+      }
+      nn = sqrt(nn);
+      for (int a = 0; a < d.nd; ++a) v[a] /= nn;
+    }
+  }
+  coef_n[3 * e + 0] = (float)v[0];
+  coef_n[3 * e + 1] = (float)v[1];
+  coef_n[3 * e + 2] = (float)v[2];
+  flag[e] = f;
+}
+
+// Coefficient tables: one wavefront per half-spectrum column c walks k0 in
+// chunks of 64; a ballot and the popcount of the lower lanes give each
+// selected entry its slot (entries of a column stay in increasing k0).
+__global__ __launch_bounds__(256) void k_tab_fill(const uint8_t* __restrict__ mask, Dims d, int ncolall,
+                                                  const int* __restrict__ colidx, const int* __restrict__ col_off,
+                                                  int gamma_kind, int* __restrict__ coef_k0,
+                                                  int64_t* __restrict__ coef_lin, float* __restrict__ coef_n,
+                                                  uint8_t* __restrict__ flag, const int* __restrict__ pairof,
+                                                  int* __restrict__ coef_slot) {
+  const int c = blockIdx.x * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
   if (c >= ncolall) return;
-  int j = colidx[c];
+  const int j = colidx[c];
   if (j < 0) return;
   int e = col_off[j];
-  const int n[3] = {d.n0, d.n1, d.n2};
   int kh, k1;
   if (d.nd == 2) {
     kh = c;
@@ -397,7 +512,8 @@ __global__ void k_tab_fill(const uint8_t* __restrict__ mask, Dims d, int ncolall
     kh = c / d.n1;
     k1 = c - kh * d.n1;
   }
-  for (int k0 = 0; k0 < d.n0; ++k0) {
+  for (int base = 0; base < d.n0; base += 64) {
+    const int k0 = base + lane;
     int k[3];
     k[0] = k0;
     if (d.nd == 2) {
@@ -407,63 +523,14 @@ __global__ void k_tab_fill(const uint8_t* __restrict__ mask, Dims d, int ncolall
       k[1] = k1;
       k[2] = kh;
     }
-    int64_t lin = ravel(d, k);
-    if (!mask[lin]) continue;
-    coef_k0[e] = k0;
-    coef_lin[e] = lin;
-    {
-      // slot s = pair - 1 (pair 0 is xi = 0 -> -1); bit 30: stored member is the partner
-      const int pr = pairof[lin];
-      const int pair = pr & ((1 << 30) - 1);
-      coef_slot[e] = pair == 0 ? -1 : ((pair - 1) | (pr & (1 << 30)));
+    const int64_t lin = k0 < d.n0 ? ravel(d, k) : 0;
+    const bool sel = k0 < d.n0 && mask[lin];
+    const unsigned long long bal = __ballot(sel);
+    if (sel) {
+      const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+      coef_entry(mask, d, gamma_kind, k, lin, e + pos, coef_k0, coef_lin, coef_n, flag, pairof, coef_slot);
     }
-    double v[3] = {0.0, 0.0, 0.0};
-    uint8_t f = 0;
-    bool zero = true, selfc = true;
-    int nyq = 0, nyq_axis = -1;
-    for (int a = 0; a < d.nd; ++a) {
-      if (k[a] != 0) zero = false;
-      bool isn = (n[a] % 2 == 0) && (k[a] == n[a] / 2);
-      if (isn) {
-        ++nyq;
-        nyq_axis = a;
-      }
-      if (!(k[a] == 0 || isn)) selfc = false;
-    }
-    if (zero) {
-      f = COEF_ZERO;
-    } else if (gamma_kind == MOR_GAMMA_ROTATED) {
-      if (nyq >= 2) {
-        f = COEF_DEAD;
-      } else if (nyq == 1) {
-        v[nyq_axis] = 1.0;
-      } else {
-        double nn = 0.0;
-        for (int a = 0; a < d.nd; ++a) {
-          v[a] = tan(M_PI * (double)k[a] / (double)n[a]);
-          nn += v[a] * v[a];
-        }
-        nn = sqrt(nn);
-        for (int a = 0; a < d.nd; ++a) v[a] /= nn;
-      }
-    } else {
-      if (nyq >= 1 && !selfc) {
-        f = COEF_DEAD;
-      } else {
-        double nn = 0.0;
-        for (int a = 0; a < d.nd; ++a) {
-          v[a] = (double)signed_k(k[a], n[a]);
-          nn += v[a] * v[a];
-        }
-        nn = sqrt(nn);
-        for (int a = 0; a < d.nd; ++a) v[a] /= nn;
-      }
-    }
-    coef_n[3 * e + 0] = (float)v[0];
-    coef_n[3 * e + 1] = (float)v[1];
-    coef_n[3 * e + 2] = (float)v[2];
-    flag[e] = f;
-    ++e;
+    e += __popcll(bal);
   }
 }
 
@@ -600,8 +667,15 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
 
   // 5. sorted pattern
   MOR_HIP_TRY(hipMalloc((void**)&P->d_sorted, P->M_actual * sizeof(int64_t)));
-  k_compact<<<1, 1024, 0, st>>>(mask.p, N, P->d_sorted);
-  MOR_LAUNCH_CHECK("compact");
+  {
+    const int nchunk = (int)((N + kCompactChunk - 1) / kCompactChunk);
+    DevBuf<int> ccount;
+    MOR_HIP_TRY(ccount.alloc(nchunk));
+    k_compact_count<<<nchunk, 256, 0, st>>>(mask.p, N, ccount.p);
+    k_compact_scan<<<1, 1024, 0, st>>>(ccount.p, nchunk);
+    k_compact_scatter<<<nchunk, 256, 0, st>>>(mask.p, N, ccount.p, P->d_sorted);
+    MOR_LAUNCH_CHECK("compact");
+  }
 
   // 6. tables
   const int nkh = nlen / 2 + 1;
@@ -624,7 +698,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   int32_t* last_k = col_off + cap_col + 1;
   int32_t* last_off = last_k + cap_last;
   int32_t* coef_k0 = last_off + cap_last + 1;
-  k_tab_count<<<(ncolall + 255) / 256, 256, 0, st>>>(mask.p, d, ncolall, cntc.p, lastcnt.p);
+  k_tab_count<<<(ncolall + 3) / 4, 256, 0, st>>>(mask.p, d, ncolall, cntc.p, lastcnt.p);
   MOR_LAUNCH_CHECK("tab_count");
   k_tab_scan<<<1, 1024, 0, st>>>(cntc.p, lastcnt.p, d, ncolall, nkh, colidx.p, col_k, col_kh.p, col_off, lastidx.p,
                                  last_k, meta.p);
@@ -639,7 +713,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_n, std::max(ncoef, 1) * 3 * sizeof(float)));
   MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_flag, std::max(ncoef, 1)));
   MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_slot, std::max(ncoef, 1) * sizeof(int)));
-  k_tab_fill<<<(ncolall + 255) / 256, 256, 0, st>>>(mask.p, d, ncolall, colidx.p, col_off, P->gamma_kind, coef_k0,
+  k_tab_fill<<<(ncolall + 3) / 4, 256, 0, st>>>(mask.p, d, ncolall, colidx.p, col_off, P->gamma_kind, coef_k0,
                                                     P->d_coef_lin, P->d_coef_n, P->d_coef_flag, pairof.p,
                                                     P->d_coef_slot);
   MOR_LAUNCH_CHECK("tab_fill");
@@ -652,11 +726,12 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   cpx<float>* tw1 = tw0 + n0;
   cpx<float>* twh = tw1 + n1;
   cpx<float>* rtw = twh + nlen / 2;
-  k_twiddle_f32<<<(n0 + 255) / 256, 256, 0, st>>>(tw0, n0, n0);
-  k_twiddle_f32<<<(n1 + 255) / 256, 256, 0, st>>>(tw1, n1, n1);
-  k_twiddle_f32<<<(nlen / 2 + 255) / 256, 256, 0, st>>>(twh, nlen / 2, nlen / 2);
-  k_twiddle_f32<<<(nlen + 255) / 256, 256, 0, st>>>(rtw, nlen, nlen);
+  k_twiddle4_f32<<<(ntw + 255) / 256, 256, 0, st>>>(P->d_tw, n0, n1, nlen / 2, nlen);
   MOR_LAUNCH_CHECK("twiddle_f32");
+  (void)tw0;
+  (void)tw1;
+  (void)twh;
+  (void)rtw;
 
   PlanDev& v = P->dev;
   v.ndim = nd;
