@@ -153,6 +153,12 @@ struct Dft<16, SIGN> {
 // wavefront spread over all banks.
 __host__ __device__ constexpr int pad16(int i) { return i + (i >> 4); }
 
+// Data layout with one pad slot after every 2^PS elements (PS = 4: pad16).
+template <int PS>
+__host__ __device__ constexpr int padp(int i) {
+  return i + (i >> PS);
+}
+
 // Sequence stride in LDS for `len` logical elements (odd, so that sequences
 // start on different banks).
 __host__ __device__ constexpr int seq_stride(int len) {
@@ -177,9 +183,9 @@ __device__ __forceinline__ void pass_twiddle(cpx<float>* v, int k, const cpx<flo
   }
 }
 
-// One in-place Stockham pass over NS sequences (base + s*SS, padded
-// positions) by NT threads.
-template <int N, int R, int P, int SIGN, int NS, int SS, int NT, int TWS>
+// One in-place Stockham pass over NS sequences (base + s*SS, positions
+// padded by padp<PS>) by NT threads.
+template <int N, int R, int P, int SIGN, int NS, int SS, int NT, int TWS, int PS = 4>
 __device__ __forceinline__ void lds_pass(cpx<float>* buf, const cpx<float>* tw, int tid) {
   constexpr int NB = N / R;
   constexpr int TOTAL = NS * NB;
@@ -193,7 +199,7 @@ __device__ __forceinline__ void lds_pass(cpx<float>* buf, const cpx<float>* tw, 
       const int k = i % P;
       const cpx<float>* src = buf + s * SS;
 #pragma unroll
-      for (int j = 0; j < R; ++j) v[q][j] = src[pad16(i + j * NB)];
+      for (int j = 0; j < R; ++j) v[q][j] = src[padp<PS>(i + j * NB)];
       pass_twiddle<N, R, P, SIGN, TWS>(v[q], k, tw);
       Dft<R, SIGN>::run(v[q]);
     }
@@ -208,7 +214,7 @@ __device__ __forceinline__ void lds_pass(cpx<float>* buf, const cpx<float>* tw, 
       cpx<float>* dst = buf + s * SS;
       const int o = (i - k) * R + k;
 #pragma unroll
-      for (int j = 0; j < R; ++j) dst[pad16(o + j * P)] = v[q][j];
+      for (int j = 0; j < R; ++j) dst[padp<PS>(o + j * P)] = v[q][j];
     }
   }
   __syncthreads();
@@ -218,13 +224,13 @@ template <int... Rs>
 struct RList {};
 
 // Runs the passes of RList in order starting with span P.
-template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS>
+template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS, int PS = 4>
 __device__ __forceinline__ void lds_passes(cpx<float>*, const cpx<float>*, int, RList<>) {}
 
-template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS, int R, int... Rest>
+template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS, int PS = 4, int R, int... Rest>
 __device__ __forceinline__ void lds_passes(cpx<float>* buf, const cpx<float>* tw, int tid, RList<R, Rest...>) {
-  lds_pass<N, R, P, SIGN, NS, SS, NT, TWS>(buf, tw, tid);
-  lds_passes<N, SIGN, P * R, NS, SS, NT, TWS>(buf, tw, tid, RList<Rest...>{});
+  lds_pass<N, R, P, SIGN, NS, SS, NT, TWS, PS>(buf, tw, tid);
+  lds_passes<N, SIGN, P * R, NS, SS, NT, TWS, PS>(buf, tw, tid, RList<Rest...>{});
 }
 
 template <int... Rs>

@@ -356,14 +356,17 @@ void go_row_fast_v(SolveCtx& cx, Group& g, float* eps, float* sig, int rows) {
 
 template <int C, int NH, int MODE, int MAT>
 void go_row_fast(SolveCtx& cx, Group& g, float* eps, float* sig, int rows) {
-  static_assert(RowVar<C, NH>::count <= 6, "dispatch covers six variants");
+  static_assert(RowVar<C, NH>::count <= 9, "dispatch covers nine variants");
   switch (g.rvar) {
     case 0: go_row_fast_v<C, NH, 0, MODE, MAT>(cx, g, eps, sig, rows); break;
     case 1: go_row_fast_v<C, NH, 1, MODE, MAT>(cx, g, eps, sig, rows); break;
     case 2: go_row_fast_v<C, NH, 2, MODE, MAT>(cx, g, eps, sig, rows); break;
     case 3: go_row_fast_v<C, NH, 3, MODE, MAT>(cx, g, eps, sig, rows); break;
     case 4: go_row_fast_v<C, NH, 4, MODE, MAT>(cx, g, eps, sig, rows); break;
-    default: go_row_fast_v<C, NH, 5, MODE, MAT>(cx, g, eps, sig, rows); break;
+    case 5: go_row_fast_v<C, NH, 5, MODE, MAT>(cx, g, eps, sig, rows); break;
+    case 6: go_row_fast_v<C, NH, 6, MODE, MAT>(cx, g, eps, sig, rows); break;
+    case 7: go_row_fast_v<C, NH, 7, MODE, MAT>(cx, g, eps, sig, rows); break;
+    default: go_row_fast_v<C, NH, 8, MODE, MAT>(cx, g, eps, sig, rows); break;
   }
 }
 

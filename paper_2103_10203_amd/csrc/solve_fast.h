@@ -38,14 +38,16 @@ template <> struct RowCfg<3, 64, 1>  { static constexpr int RL = 8, RB = 8;  usi
 template <> struct RowCfg<3, 64, 2>  { static constexpr int RL = 8, RB = 32; using RA = RList<8>; };
 template <> struct RowCfg<3, 64, 3>  { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4>; };
 template <> struct RowCfg<3, 64, 4>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
-template <> struct RowVar<3, 64> { static constexpr int count = 5; };
+template <> struct RowCfg<3, 64, 5>  { static constexpr int RL = 8, RB = 16, PS = 5; using RA = RList<8>; };
+template <> struct RowVar<3, 64> { static constexpr int count = 6; };
 template <> struct RowCfg<3, 128, 0> { static constexpr int RL = 8, RB = 16; using RA = RList<16>; };
 template <> struct RowCfg<3, 128, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<16>; };
 template <> struct RowCfg<3, 128, 2> { static constexpr int RL = 8, RB = 32; using RA = RList<16>; };
 template <> struct RowCfg<3, 128, 3> { static constexpr int RL = 8, RB = 16; using RA = RList<4, 4>; };
 template <> struct RowCfg<3, 128, 4> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 4>; };
 template <> struct RowCfg<3, 128, 5> { static constexpr int RL = 8, RB = 4;  using RA = RList<16>; };
-template <> struct RowVar<3, 128> { static constexpr int count = 6; };
+template <> struct RowCfg<3, 128, 6> { static constexpr int RL = 8, RB = 16, PS = 5; using RA = RList<16>; };
+template <> struct RowVar<3, 128> { static constexpr int count = 7; };
 template <> struct RowCfg<3, 192, 0> { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4, 3>; };
 template <> struct RowCfg<3, 192, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<8, 3>; };
 template <> struct RowCfg<3, 192, 2> { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4, 3>; };
@@ -69,13 +71,25 @@ template <> struct RowCfg<6, 128, 1> { static constexpr int RL = 8, RB = 8;  usi
 template <> struct RowCfg<6, 128, 2> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 4>; };
 template <> struct RowVar<6, 128> { static constexpr int count = 3; };
 
+// Data padding of a variant: one slot after every 2^PS elements (default 4).
+template <typename Cfg, typename = void>
+struct PadOf {
+  static constexpr int v = 4;
+};
+template <typename Cfg>
+struct PadOf<Cfg, decltype((void)Cfg::PS)> {
+  static constexpr int v = Cfg::PS;
+};
+
 template <int C, int NH, int V>
 constexpr int row_threads() {
   return RowCfg<C, NH, V>::RB * (NH / RowCfg<C, NH, V>::RL);
 }
-template <int NH>
+template <int NH, int PS = 4>
 constexpr int row_ss() {
-  return fftr::seq_stride(NH + 1);  // NH + 1 spectrum slots (Nyquist included)
+  // NH + 1 spectrum slots (Nyquist included); odd, so sequences start on
+  // different banks
+  return (fftr::padp<PS>(NH) + 1) | 1;
 }
 template <int NH>
 constexpr int row_tw_len() {
@@ -83,7 +97,8 @@ constexpr int row_tw_len() {
 }
 template <int C, int NH, int V>
 constexpr size_t row_lds_bytes() {
-  return (size_t)(row_tw_len<NH>() + RowCfg<C, NH, V>::RB * row_ss<NH>()) * sizeof(cpx<float>);
+  return (size_t)(row_tw_len<NH>() + RowCfg<C, NH, V>::RB * row_ss<NH, PadOf<RowCfg<C, NH, V>>::v>()) *
+         sizeof(cpx<float>);
 }
 
 template <int C, int NH, int V, int MODE, int MAT>
@@ -93,9 +108,10 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
     float* __restrict__ out_sig, double* __restrict__ sig_part) {
   using Cfg = RowCfg<C, NH, V>;
   constexpr int RL = Cfg::RL, RB = Cfg::RB;
+  constexpr int PS = PadOf<Cfg>::v;
   constexpr int TR = NH / RL;  // threads per row in the register pass
   constexpr int NT = RB * TR;
-  constexpr int SS = row_ss<NH>();
+  constexpr int SS = row_ss<NH, PS>();
   constexpr int S = Comp<C>::S;
   constexpr int NST = Comp<C>::NST;
   constexpr int L = 2 * NH;
@@ -176,22 +192,22 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
         const cpx<float> Xk = xa[u], Xm = xb[u];
         const cpx<float> a = cadd(Xk, cconj(Xm));
         const cpx<float> d = cmul(csub(Xk, cconj(Xm)), cconj(T[pad16(k)]));
-        x[pad16(k)] = {a.x - d.y, a.y + d.x};
+        x[fftr::padp<PS>(k)] = {a.x - d.y, a.y + d.x};
         if (k != 0 && 2 * k != NH) {
           const cpx<float> a2 = cadd(Xm, cconj(Xk));
           const cpx<float> d2 = cmul(csub(Xm, cconj(Xk)), cconj(T[pad16(NH - k)]));
-          x[pad16(NH - k)] = {a2.x - d2.y, a2.y + d2.x};
+          x[fftr::padp<PS>(NH - k)] = {a2.x - d2.y, a2.y + d2.x};
         }
       }
     }
     if (c + 1 < C) gather(c + 1);
     __syncthreads();
-    fftr::lds_passes<NH, +1, 1, RB, SS, NT, 2>(buf, T, tid, typename Cfg::RA{});
+    fftr::lds_passes<NH, +1, 1, RB, SS, NT, 2, PS>(buf, T, tid, typename Cfg::RA{});
     // register pass: last inverse stage (radix RL, span TR)
     {
       const cpx<float>* src = buf + r * SS;
 #pragma unroll
-      for (int j = 0; j < RL; ++j) v[c][j] = src[pad16(i + j * TR)];
+      for (int j = 0; j < RL; ++j) v[c][j] = src[fftr::padp<PS>(i + j * TR)];
 #pragma unroll
       for (int j = 1; j < RL; ++j) v[c][j] = cmul(v[c][j], rtw[j]);
       Dft<RL, +1>::run(v[c]);
@@ -276,10 +292,10 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
     {
       cpx<float>* dst = buf + r * SS;
 #pragma unroll
-      for (int j = 0; j < RL; ++j) dst[pad16(i * RL + j)] = v[c][j];
+      for (int j = 0; j < RL; ++j) dst[fftr::padp<PS>(i * RL + j)] = v[c][j];
     }
     __syncthreads();
-    fftr::lds_passes<NH, -1, RL, RB, SS, NT, 2>(buf, T, tid,
+    fftr::lds_passes<NH, -1, RL, RB, SS, NT, 2, PS>(buf, T, tid,
                                                 typename fftr::Rev<typename Cfg::RA, RList<>>::type{});
     // unpack X[k] = (Z[k] + conj Z[NH-k]) / 2 - i T[k] (Z[k] - conj Z[NH-k]) / 2
     // at the sampled frequencies and store them
@@ -288,8 +304,8 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
       cpx<float>* ydst = Y + (int64_t)c * cstride + r0 + rg;
       for (int j = tid / RB; j < nlast; j += QS) {
         const int k = lk[j];
-        const cpx<float> Zk = z[pad16(k == NH ? 0 : k)];
-        const cpx<float> Zc = cconj(z[pad16(k == 0 ? 0 : NH - k)]);
+        const cpx<float> Zk = z[fftr::padp<PS>(k == NH ? 0 : k)];
+        const cpx<float> Zc = cconj(z[fftr::padp<PS>(k == 0 ? 0 : NH - k)]);
         const cpx<float> sm = cadd(Zk, Zc);
         const cpx<float> wd = cmul(T[pad16(k)], csub(Zk, Zc));
         ydst[(int64_t)j * rows] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
