@@ -210,6 +210,8 @@ def main():
                     help="last-axis transform of every solve (auto = the pruned FFT)")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",
                     help="bf16x3: split-bf16 MFMA partial DFT (implies --transform dft)")
+    ap.add_argument("--schedule", choices=["grid", "persistent"], default="grid",
+                    help="workgroup schedule of the iteration kernels")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -234,6 +236,7 @@ def main():
     SOLVE_KW["transform"] = {"auto": mor.TRANSFORM_AUTO, "fft": mor.TRANSFORM_FFT,
                              "dft": mor.TRANSFORM_DFT}[args.transform]
     SOLVE_KW["precision"] = mor.PREC_BF16X3 if args.precision == "bf16x3" else mor.PREC_FP32
+    SOLVE_KW["schedule"] = mor.SCHED_PERSISTENT if args.schedule == "persistent" else mor.SCHED_GRID
     dft = args.transform == "dft" or args.precision == "bf16x3"
     if args.precision == "bf16x3":
         TOL = 1e-5  # split-bf16 products set a residual floor near 1e-6
@@ -351,7 +354,7 @@ def main():
             "tol": TOL,
             "start": start,
             "fields": "FP32, FP64 residual and stress sums",
-            "transform": args.transform, "precision": args.precision,
+            "transform": args.transform, "precision": args.precision, "schedule": args.schedule,
         },
         "roofline": roof,
         "kernels": {k: {"ms": v["ms"], "launches": v["launches"],

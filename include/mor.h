@@ -131,6 +131,12 @@ typedef struct {
 enum { MOR_PREC_FP32 = 0,     /* FP32 transforms and fields (default)            */
        MOR_PREC_BF16X3 = 1 }; /* split-bf16 partial DFT on MFMA, FP32 accumulate */
 enum { MOR_TRANSFORM_AUTO = 0, MOR_TRANSFORM_FFT = 1, MOR_TRANSFORM_DFT = 2 };
+/* Work schedule of the iteration kernels (same results):
+ *   MOR_SCHED_GRID        one workgroup per (RVE, tile); converged RVEs' workgroups exit at once
+ *   MOR_SCHED_PERSISTENT  a grid sized to the device's residency walks a device-built queue of
+ *                         the still-iterating RVEs' tiles (specialised row/column kernels; other
+ *                         kernels keep the grid schedule) */
+enum { MOR_SCHED_GRID = 0, MOR_SCHED_PERSISTENT = 1 };
 
 typedef struct {
   int32_t max_iter;     /* 0 -> 10000                                            */
@@ -145,7 +151,7 @@ typedef struct {
                               eps0 = macro strain                                */
   void* stream;         /* hipStream_t, NULL = null stream                       */
   int32_t use_graph;    /* replay the iteration chunk from a captured hipGraph   */
-  int32_t pad_;
+  int32_t schedule;     /* MOR_SCHED_*: how workgroups map to (RVE, tile) work   */
 } mor_solve_opts;
 
 typedef struct {

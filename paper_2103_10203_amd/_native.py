@@ -62,7 +62,7 @@ class mor_phase(ct.Structure):
 class mor_solve_opts(ct.Structure):
     _fields_ = [("max_iter", ct.c_int32), ("precision", ct.c_int32), ("transform", ct.c_int32),
                 ("check_every", ct.c_int32), ("warm_start", ct.c_void_p), ("stream", ct.c_void_p),
-                ("use_graph", ct.c_int32), ("pad_", ct.c_int32)]
+                ("use_graph", ct.c_int32), ("schedule", ct.c_int32)]
 
 
 class mor_outputs(ct.Structure):
@@ -254,10 +254,15 @@ class SolveResult:
     coeffs: object = None
 
 
-def _opts(max_iter, check_every, warm_start, stream, precision=PREC_FP32, transform=TRANSFORM_AUTO, use_graph=0):
+SCHED_GRID = 0
+SCHED_PERSISTENT = 1
+
+
+def _opts(max_iter, check_every, warm_start, stream, precision=PREC_FP32, transform=TRANSFORM_AUTO, use_graph=0,
+          schedule=SCHED_GRID):
     ws = ct.c_void_p(warm_start.data_ptr()) if warm_start is not None else ct.c_void_p(None)
     return mor_solve_opts(int(max_iter), int(precision), int(transform), int(check_every), ws,
-                          _stream_ptr(stream), int(use_graph), 0)
+                          _stream_ptr(stream), int(use_graph), int(schedule))
 
 
 def _outputs(B, S, eff_rows, want_fields, want_coeffs, nfield_pts, C, ncoef_total):
@@ -284,7 +289,7 @@ def _outputs(B, S, eff_rows, want_fields, want_coeffs, nfield_pts, C, ncoef_tota
 def solve(plan: Plan, macro_strain, phases, tol: float, max_iter: int = 0, warm_start=None, stream=None,
           want_fields: bool = False, want_coeffs: bool = False, check_every: int = 0,
           precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO, use_graph: int = 0,
-          allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
+          schedule: int = SCHED_GRID, allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
     """mor_solve for B macro strains on one plan; macro_strain [B][ncomp]."""
     eb = np.ascontiguousarray(np.atleast_2d(macro_strain), dtype=np.float64)
     B, C = eb.shape
@@ -293,7 +298,7 @@ def solve(plan: Plan, macro_strain, phases, tol: float, max_iter: int = 0, warm_
     S = plan.nstress
     out, eff, its, res, strain, stress, coeffs = _outputs(B, S, B, want_fields, want_coeffs, B * plan.N, C,
                                                           B * C * plan.n_coeff)
-    opts = _opts(max_iter, check_every, warm_start, stream, precision, transform, use_graph)
+    opts = _opts(max_iter, check_every, warm_start, stream, precision, transform, use_graph, schedule)
     st = _check(lib.mor_solve(plan.handle, _np_ptr(eb), B, _phases(phases), float(tol), ct.byref(opts),
                               ct.byref(out)), allow)
     if strain is not None:
@@ -306,7 +311,7 @@ def solve(plan: Plan, macro_strain, phases, tol: float, max_iter: int = 0, warm_
 
 def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int = 0, warm_start=None, stream=None,
                 want_fields: bool = False, want_coeffs: bool = False, check_every: int = 0, use_graph: int = 0,
-                precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO,
+                precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO, schedule: int = SCHED_GRID,
                 allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
     """mor_solve_multi: RVE b uses plans[plan_of[b]]; outputs packed per RVE."""
     eb = np.ascontiguousarray(np.atleast_2d(macro_strain), dtype=np.float64)
@@ -317,7 +322,7 @@ def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int 
     npts = int(sum(plans[i].N for i in po))
     ncoef = int(sum(plans[i].n_coeff for i in po)) * C
     out, eff, its, res, strain, stress, coeffs = _outputs(B, S, B, want_fields, want_coeffs, npts, C, ncoef)
-    opts = _opts(max_iter, check_every, warm_start, stream, precision, transform, use_graph)
+    opts = _opts(max_iter, check_every, warm_start, stream, precision, transform, use_graph, schedule)
     st = _check(lib.mor_solve_multi(handles, len(plans), _np_ptr(po), _np_ptr(eb), B, _phases(phases), float(tol),
                                     ct.byref(opts), ct.byref(out)), allow)
     return SolveResult(st, eff, its, res, strain, stress, coeffs)
@@ -325,14 +330,14 @@ def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int 
 
 def solve_path(plan: Plan, macro_strains, phases, tol: float, state, max_iter: int = 0, stream=None,
                want_fields: bool = False, check_every: int = 0, use_graph: int = 0,
-               precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO,
+               precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO, schedule: int = SCHED_GRID,
                allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
     """mor_solve_path: macro_strains [steps][ncomp]; state: torch float32 cuda [nstate][N] (in/out)."""
     eb = np.ascontiguousarray(np.atleast_2d(macro_strains), dtype=np.float64)
     steps, C = eb.shape
     S = plan.nstress
     out, eff, its, res, strain, stress, coeffs = _outputs(steps, S, steps, want_fields, False, plan.N, C, 0)
-    opts = _opts(max_iter, check_every, None, stream, precision, transform, use_graph)
+    opts = _opts(max_iter, check_every, None, stream, precision, transform, use_graph, schedule)
     st = _check(lib.mor_solve_path(plan.handle, _np_ptr(eb), steps, _phases(phases), float(tol), ct.byref(opts),
                                    ct.c_void_p(state.data_ptr()), ct.byref(out)), allow)
     if strain is not None:

@@ -123,6 +123,8 @@ struct Group {
   int rb = 1, cb = 1, xb = 1;
   int rvar = 0;  // row-kernel variant
   int cvar = 0;  // column-kernel variant
+  int gidx = 0;  // position of the group (active count slot)
+  int* d_alist = nullptr;  // this group's segment of the active list
   bool fast_row = false, fast_col = false;
   int* d_list = nullptr;
 };
@@ -272,6 +274,9 @@ struct SolveCtx {
   bool dft = false;        // last-axis transform as MFMA GEMMs instead of the row FFT
   int dft_prec = DFT_F32;  // DFT_F32 or DFT_X3 (split bf16)
   float* d_dfte = nullptr; // DFT path: real field per RVE [C][N] (strain, then polarisation)
+  bool persist = false;    // persistent schedule of the specialised row/column kernels
+  int* d_alist = nullptr;  // [B] active RVEs per group (group segments as in the lists)
+  int* d_nact = nullptr;   // [groups] active count per group
 };
 
 // Asynchronous upload from a host copy kept alive until the solve ends.
@@ -414,6 +419,122 @@ void go_col_fast(SolveCtx& cx, Group& g, const cpx<float>* warm) {
   }
 }
 
+// Persistent grid size: a multiple of the workgroups resident at once on the
+// device, capped by the number of items.
+int persist_grid(const void* fn, int nt, size_t lds, int64_t items) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  int per = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(fn);
+    if (it != cache.end()) per = it->second;
+  }
+  if (per == 0) {
+    int nb = 0, dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nt, lds) != hipSuccess || nb < 1) nb = 1;
+    // four workgroups per resident slot: the queue keeps the dispatcher fed
+    // while workgroups of the previous round drain
+    per = std::max(1, 4 * nb * std::max(ncu, 1));
+    std::lock_guard<std::mutex> lk(mu);
+    cache[fn] = per;
+  }
+  return (int)std::max<int64_t>(1, std::min<int64_t>(per, items));
+}
+
+template <int C, int NH, int V, int MAT>
+void go_row_persist_v(SolveCtx& cx, Group& g, int rows) {
+  if constexpr (V < RowVar<C, NH>::count) {
+    using Cfg = RowCfg<C, NH, V>;
+    const int ntiles = (rows + Cfg::RB - 1) / Cfg::RB;
+    auto fn = k_row_persist<C, NH, V, MAT>;
+    const int grid = persist_grid((const void*)fn, row_threads<C, NH, V>(), row_lds_bytes<C, NH, V>(),
+                                  (int64_t)ntiles * g.rves.size());
+    fn<<<grid, row_threads<C, NH, V>(), row_lds_bytes<C, NH, V>(), cx.st>>>(
+        cx.d_plans, g.d_alist, cx.d_nact + g.gidx, ntiles, cx.d_st, cx.d_yl, cx.off, cx.mat, cx.d_jstate);
+  }
+}
+
+template <int C, int NH, int MAT>
+void go_row_persist(SolveCtx& cx, Group& g, int rows) {
+  switch (g.rvar) {
+    case 0: go_row_persist_v<C, NH, 0, MAT>(cx, g, rows); break;
+    case 1: go_row_persist_v<C, NH, 1, MAT>(cx, g, rows); break;
+    case 2: go_row_persist_v<C, NH, 2, MAT>(cx, g, rows); break;
+    case 3: go_row_persist_v<C, NH, 3, MAT>(cx, g, rows); break;
+    case 4: go_row_persist_v<C, NH, 4, MAT>(cx, g, rows); break;
+    case 5: go_row_persist_v<C, NH, 5, MAT>(cx, g, rows); break;
+    case 6: go_row_persist_v<C, NH, 6, MAT>(cx, g, rows); break;
+    case 7: go_row_persist_v<C, NH, 7, MAT>(cx, g, rows); break;
+    default: go_row_persist_v<C, NH, 8, MAT>(cx, g, rows); break;
+  }
+}
+
+template <int C, int MAT>
+void row_persist(SolveCtx& cx, Group& g) {
+  const int nlen = C == 3 ? g.n1 : g.n2;
+  const int rows = C == 3 ? g.n0 : g.n0 * g.n1;
+  if constexpr (C == 3) {
+    switch (nlen / 2) {
+      case 32: go_row_persist<3, 32, MAT>(cx, g, rows); break;
+      case 64: go_row_persist<3, 64, MAT>(cx, g, rows); break;
+      case 128: go_row_persist<3, 128, MAT>(cx, g, rows); break;
+      case 192: go_row_persist<3, 192, MAT>(cx, g, rows); break;
+      default: go_row_persist<3, 256, MAT>(cx, g, rows); break;
+    }
+  } else {
+    switch (nlen / 2) {
+      case 32: go_row_persist<6, 32, MAT>(cx, g, rows); break;
+      case 64: go_row_persist<6, 64, MAT>(cx, g, rows); break;
+      default: go_row_persist<6, 128, MAT>(cx, g, rows); break;
+    }
+  }
+}
+
+template <int C, int N0, int V>
+void go_col_persist_v(SolveCtx& cx, Group& g) {
+  if constexpr (V < ColVar<C, N0>::count) {
+    using Cfg = ColCfg<C, N0, V>;
+    const int ntiles = (g.ncol_max + Cfg::CB - 1) / Cfg::CB;
+    auto fn = k_col_persist<C, N0, V>;
+    const int grid = persist_grid((const void*)fn, col_threads<C, N0, V>(), col_lds_bytes<C, N0, V>(),
+                                  (int64_t)ntiles * g.rves.size());
+    fn<<<grid, col_threads<C, N0, V>(), col_lds_bytes<C, N0, V>(), cx.st>>>(
+        cx.d_plans, g.d_alist, cx.d_nact + g.gidx, ntiles, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef, cx.off,
+        cx.d_part, cx.mat);
+  }
+}
+
+template <int C, int N0>
+void go_col_persist(SolveCtx& cx, Group& g) {
+  switch (g.cvar) {
+    case 0: go_col_persist_v<C, N0, 0>(cx, g); break;
+    case 1: go_col_persist_v<C, N0, 1>(cx, g); break;
+    case 2: go_col_persist_v<C, N0, 2>(cx, g); break;
+    case 3: go_col_persist_v<C, N0, 3>(cx, g); break;
+    case 4: go_col_persist_v<C, N0, 4>(cx, g); break;
+    default: go_col_persist_v<C, N0, 5>(cx, g); break;
+  }
+}
+
+template <int C>
+void col_persist(SolveCtx& cx, Group& g) {
+  if constexpr (C == 3) {
+    switch (g.n0) {
+      case 64: go_col_persist<3, 64>(cx, g); break;
+      case 128: go_col_persist<3, 128>(cx, g); break;
+      case 256: go_col_persist<3, 256>(cx, g); break;
+      case 384: go_col_persist<3, 384>(cx, g); break;
+      default: go_col_persist<3, 512>(cx, g); break;
+    }
+  } else {
+    if (g.n0 == 64) go_col_persist<6, 64>(cx, g);
+    else go_col_persist<6, 128>(cx, g);
+  }
+}
+
 template <int C, int MODE>
 void col_fast(SolveCtx& cx, Group& g, const cpx<float>* warm) {
   if constexpr (C == 3) {
@@ -491,9 +612,17 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
   const size_t shr = (size_t)(nh + nh + 1 + 2 * C * g.rb * (nh + 1)) * sizeof(cpx<float>);
   dim3 gr((rows + g.rb - 1) / g.rb, (unsigned)g.rves.size());
   hipEvent_t a{};
+  const bool pers = cx.persist && !cx.dft;
+  if (pers) {
+    // queue of this iteration: the group's still-iterating RVEs
+    k_active_list<<<1, 1024, 0, cx.st>>>(g.d_list, (int)g.rves.size(), cx.d_st, g.d_alist, cx.d_nact + g.gidx);
+    MOR_LAUNCH_CHECK("active_list");
+  }
   ev_begin(cx, PK_ROW, &a);
   if (cx.dft)
     launch_dft_stage<C, MAT>(cx, g, rows, nlen);
+  else if (g.fast_row && pers)
+    row_persist<C, MAT>(cx, g);
   else if (g.fast_row)
     row_fast<C, MODE_ITER, MAT>(cx, g, nullptr, nullptr);
   else
@@ -512,7 +641,9 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
   const size_t shc = (size_t)(g.n0 + 2 * C * g.cb * g.n0) * sizeof(cpx<float>);
   dim3 gc((g.ncol_max + g.cb - 1) / g.cb, (unsigned)g.rves.size());
   ev_begin(cx, PK_COL, &a);
-  if (g.fast_col)
+  if (g.fast_col && pers)
+    col_persist<C>(cx, g);
+  else if (g.fast_col)
     col_fast<C, MODE_ITER>(cx, g, nullptr);
   else
     k_col<C, MODE_ITER><<<gc, 256, shc, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef,
@@ -631,6 +762,7 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   cx.ncoef_h.resize(B);
   // transform of the last axis: the row FFT (default, and AUTO: measured
   // faster on every size), or the MFMA partial DFT
+  cx.persist = opts && opts->schedule == MOR_SCHED_PERSISTENT;
   if (opts && (opts->transform == MOR_TRANSFORM_DFT || opts->precision == MOR_PREC_BF16X3)) {
     cx.dft = true;
     cx.dft_prec = opts->precision == MOR_PREC_BF16X3 ? DFT_X3 : DFT_F32;
@@ -727,6 +859,14 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   if ((s = upload(cx, d_lists, lists)) != MOR_OK) return s;
   if ((s = upload(cx, cx.d_nblk, nblk_list)) != MOR_OK) return s;
   for (size_t gi = 0; gi < cx.groups.size(); ++gi) cx.groups[gi].d_list = d_lists + lstart[gi];
+  if (cx.persist) {
+    if ((s = ws.get("alist", lists.size(), &cx.d_alist)) != MOR_OK) return s;
+    if ((s = ws.get("nact", cx.groups.size(), &cx.d_nact)) != MOR_OK) return s;
+    for (size_t gi = 0; gi < cx.groups.size(); ++gi) {
+      cx.groups[gi].gidx = (int)gi;
+      cx.groups[gi].d_alist = cx.d_alist + lstart[gi];
+    }
+  }
   // nblk is indexed by group position in k_sig_reduce: shift per group
   // (k_sig_reduce receives the group's list; its nblk pointer is offset below)
   // states
@@ -952,6 +1092,10 @@ mor_status check_common(const double* ebar, int64_t B, int C, const mor_phase* p
     }
     if (opts->transform < MOR_TRANSFORM_AUTO || opts->transform > MOR_TRANSFORM_DFT) {
       mor_set_error("unknown transform");
+      return MOR_E_INVALID_ARG;
+    }
+    if (opts->schedule != MOR_SCHED_GRID && opts->schedule != MOR_SCHED_PERSISTENT) {
+      mor_set_error("unknown schedule");
       return MOR_E_INVALID_ARG;
     }
     if (opts->precision == MOR_PREC_BF16X3 && opts->transform == MOR_TRANSFORM_FFT) {

@@ -101,11 +101,21 @@ constexpr size_t row_lds_bytes() {
          sizeof(cpx<float>);
 }
 
+// threadIdx.x, re-read per work item of a persistent loop behind an empty asm
+// statement, so that thread-index arithmetic is not hoisted out of the loop
+// (hoisting keeps it live across the whole item and doubles the registers).
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// One row block (tile) of one RVE: the work of one workgroup.
 template <int C, int NH, int V, int MODE, int MAT>
-__global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
-    const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
-    cpx<float>* __restrict__ Yl, Offs off, MatDev mat, float* __restrict__ jstate, float* __restrict__ out_eps,
-    float* __restrict__ out_sig, double* __restrict__ sig_part) {
+__device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, const int b, const int tile,
+                                         RveState* __restrict__ st, cpx<float>* __restrict__ Yl, const Offs& off,
+                                         const MatDev& mat, float* __restrict__ jstate, float* __restrict__ out_eps,
+                                         float* __restrict__ out_sig, double* __restrict__ sig_part, const int tid) {
   using Cfg = RowCfg<C, NH, V>;
   constexpr int RL = Cfg::RL, RB = Cfg::RB;
   constexpr int PS = PadOf<Cfg>::v;
@@ -121,12 +131,10 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ int lk[NH + 1];    // last-axis frequency of spectrum entry j
   __shared__ int kpos[NH + 1];  // entry j of last-axis frequency k, -1 if not sampled
-  const int tid = threadIdx.x;
-  const int b = rve_list[blockIdx.y];
   if (MODE == MODE_ITER && !st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
   const int rows = P.rows;
-  const int r0 = blockIdx.x * RB;
+  const int r0 = tile * RB;
   if (r0 >= rows) return;
   const int nr = min(RB, rows - r0);
   // T[t] = exp(-2 pi i t / L): the real-FFT twiddles are T[k], the length-NH
@@ -279,7 +287,7 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       double w = block_sum_d(acc[s], red);
-      if (tid == 0) sig_part[(off.part[b] + blockIdx.x) * S + s] = w;
+      if (tid == 0) sig_part[(off.part[b] + tile) * S + s] = w;
     }
     return;
   }
@@ -312,6 +320,34 @@ __global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
       }
     }
     if (c + 1 < C) __syncthreads();
+  }
+}
+
+// Grid schedule: workgroup (tile, list position).
+template <int C, int NH, int V, int MODE, int MAT>
+__global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
+    const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
+    cpx<float>* __restrict__ Yl, Offs off, MatDev mat, float* __restrict__ jstate, float* __restrict__ out_eps,
+    float* __restrict__ out_sig, double* __restrict__ sig_part) {
+  row_tile<C, NH, V, MODE, MAT>(plans, rve_list[blockIdx.y], blockIdx.x, st, Yl, off, mat, jstate, out_eps, out_sig,
+                                sig_part, threadIdx.x);
+}
+
+// Persistent schedule: a fixed grid walks the (active RVE, tile) items of
+// the current iteration; item q is tile q % ntiles of RVE alist[q / ntiles].
+// Every workgroup leaves the loop once the items are exhausted.
+template <int C, int NH, int V, int MAT>
+__global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_persist(
+    const PlanDev* __restrict__ plans, const int* __restrict__ alist, const int* __restrict__ nact, int ntiles,
+    RveState* __restrict__ st, cpx<float>* __restrict__ Yl, Offs off, MatDev mat, float* __restrict__ jstate) {
+  const int nitems = *nact * ntiles;
+#pragma unroll 1
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const int b = __builtin_amdgcn_readfirstlane(alist[q / ntiles]);
+    const int tile = __builtin_amdgcn_readfirstlane(q % ntiles);
+    row_tile<C, NH, V, MODE_ITER, MAT>(plans, b, tile, st, Yl, off, mat, jstate, nullptr, nullptr, nullptr,
+                                       opaque_tid());
+    __syncthreads();  // the next item reuses the LDS buffers
   }
 }
 
@@ -362,11 +398,13 @@ constexpr size_t col_lds_bytes() {
   return (size_t)(pad16(N0 - 1) + 1 + 2 * C * ColCfg<C, N0, V>::CB * col_ss<N0>()) * sizeof(cpx<float>);
 }
 
+// One block of columns (tile) of one RVE.
 template <int C, int N0, int V, int MODE>
-__global__ __launch_bounds__((col_threads<C, N0, V>())) void k_col_fast(
-    const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
-    const double* __restrict__ ebar, cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
-    const cpx<float>* __restrict__ warm, Offs off, double* __restrict__ part, MatDev mat) {
+__device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, const int b, const int tile,
+                                         RveState* __restrict__ st, const double* __restrict__ ebar,
+                                         cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
+                                         const cpx<float>* __restrict__ warm, const Offs& off,
+                                         double* __restrict__ part, const MatDev& mat, const int tid) {
   using Cfg = ColCfg<C, N0, V>;
   constexpr int RF = Cfg::RF, CB = Cfg::CB;
   constexpr int TS = N0 / RF;
@@ -376,12 +414,10 @@ __global__ __launch_bounds__((col_threads<C, N0, V>())) void k_col_fast(
   static_assert(NT % 64 == 0, "workgroups are whole wavefronts");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ int coff[CB + 1];
-  const int tid = threadIdx.x;
-  const int b = rve_list[blockIdx.y];
   if (MODE == MODE_ITER && !st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
   const int ncol = P.ncol;
-  const int j0 = blockIdx.x * CB;
+  const int j0 = tile * CB;
   if (j0 >= ncol) return;
   const int ncb = min(CB, ncol - j0);
   cpx<float>* tw = reinterpret_cast<cpx<float>*>(smem_raw);
@@ -523,8 +559,59 @@ __global__ __launch_bounds__((col_threads<C, N0, V>())) void k_col_fast(
   if (MODE == MODE_ITER) {
     __shared__ double red[16];
     const double tot = block_sum_d(dsum, red);
-    if (tid == 0) part[off.part[b] + blockIdx.x] = tot;
+    if (tid == 0) part[off.part[b] + tile] = tot;
   }
+}
+
+template <int C, int N0, int V, int MODE>
+__global__ __launch_bounds__((col_threads<C, N0, V>())) void k_col_fast(
+    const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
+    const double* __restrict__ ebar, cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
+    const cpx<float>* __restrict__ warm, Offs off, double* __restrict__ part, MatDev mat) {
+  col_tile<C, N0, V, MODE>(plans, rve_list[blockIdx.y], blockIdx.x, st, ebar, Yc, coef, warm, off, part, mat,
+                           threadIdx.x);
+}
+
+template <int C, int N0, int V>
+__global__ __launch_bounds__((col_threads<C, N0, V>())) void k_col_persist(
+    const PlanDev* __restrict__ plans, const int* __restrict__ alist, const int* __restrict__ nact, int ntiles,
+    RveState* __restrict__ st, const double* __restrict__ ebar, cpx<float>* __restrict__ Yc,
+    cpx<float>* __restrict__ coef, Offs off, double* __restrict__ part, MatDev mat) {
+  const int nitems = *nact * ntiles;
+#pragma unroll 1
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const int b = __builtin_amdgcn_readfirstlane(alist[q / ntiles]);
+    const int tile = __builtin_amdgcn_readfirstlane(q % ntiles);
+    col_tile<C, N0, V, MODE_ITER>(plans, b, tile, st, ebar, Yc, coef, nullptr, off, part, mat, opaque_tid());
+    __syncthreads();
+  }
+}
+
+// Active list of a group for the persistent schedule: the RVEs of `list`
+// (in list order) that are still iterating, and their count.
+__global__ __launch_bounds__(1024) void k_active_list(const int* __restrict__ list, int nrv,
+                                                      const RveState* __restrict__ st, int* __restrict__ alist,
+                                                      int* __restrict__ nact) {
+  __shared__ int wsum[16];
+  int base = 0;
+  const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+  for (int c0 = 0; c0 < nrv; c0 += 1024) {
+    const int i = c0 + threadIdx.x;
+    const int b = i < nrv ? list[i] : 0;
+    const bool on = i < nrv && st[b].active;
+    const unsigned long long bal = __ballot(on);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wid] = __popcll(bal);
+    __syncthreads();
+    int off = base;
+    for (int w = 0; w < wid; ++w) off += wsum[w];
+    if (on) alist[off + before] = b;
+    int tot = 0;
+    for (int w = 0; w < 16; ++w) tot += wsum[w];
+    __syncthreads();
+    base += tot;
+  }
+  if (threadIdx.x == 0) *nact = base;
 }
 
 }  // namespace mor_k
