@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <random>
 #include <string>
 #include <vector>
@@ -111,11 +113,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
   }
 }
 
-// ------------------------------------------------------------------ BF16 MFMA GEMM
-// Inference only: C = act(X W + b), X FP32 [M][K] (rounded to bf16 on load),
-// W bf16 [K][N], FP32 accumulation with v_mfma_f32_32x32x8_bf16 (gfx950
-// supports the 1k variant).  Workgroup = 4 wavefronts, tile 64 (m) x 64 (n),
-// each wave computes one 32x32 block; K step 8 per MFMA, 32 per LDS stage.
+// ------------------------------------------------------------------ bf16 helpers
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -126,64 +124,115 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
   return (unsigned short)((u + r) >> 16);
 }
 
-template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm_bf16(int M, int N, int K, const float* __restrict__ X, int ldx,
-                                                   const unsigned short* __restrict__ W, int ldw,
-                                                   float* __restrict__ C, int ldc, const float* __restrict__ bias) {
-  constexpr int KS = 32;
-  __shared__ unsigned short Xs[64][KS + 8];  // [m][k]
-  __shared__ unsigned short Ws[64][KS + 8];  // [n][k] (transposed for the B operand)
-  const int tid = threadIdx.x;
-  const int wave = tid / 64, lane = tid % 64;
-  const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  f32x16 acc;
+// ------------------------------------------------------------------ BF16 MFMA GEMM (inference)
+// C[m][n] = act(sum_k A[m][k] Bt[n][k] + bias[n]) with A bf16 [M][Kp] and Bt
+// bf16 [N][Kp] (K padded with zeros to a multiple of 32), FP32 accumulation
+// on v_mfma_f32_32x32x8_bf16.  Workgroup = 4 wavefronts on a 128 x 128
+// output tile (2 x 2 wavefronts of 64 x 64, each 2 x 2 MFMA blocks); K is
+// staged 32 at a time through LDS, the next stage's global loads issued
+// before the current stage's MFMAs.  Output FP32 or bf16.
+constexpr int MM_T = 128, MM_K = 32, MM_LD = MM_K + 8;
+
+template <int EPI, bool OUT_BF16>
+__global__ __launch_bounds__(256) void k_mm_bf16(int M, int N, int Kp, const unsigned short* __restrict__ A,
+                                                 const unsigned short* __restrict__ Bt,
+                                                 const float* __restrict__ bias, void* __restrict__ Cout, int ldc) {
+  __shared__ __attribute__((aligned(16))) unsigned short As[MM_T][MM_LD];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[MM_T][MM_LD];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int wm = (wave / 2) * 64, wn = (wave % 2) * 64;
+  const int m0 = blockIdx.y * MM_T, n0 = blockIdx.x * MM_T;
+  // staging: thread t moves 16 bf16 (two 16-byte vectors) of A and of B:
+  // row t / 2, k half (t % 2) * 16
+  const int srow = tid / 2, sk = (tid % 2) * 16;
+  const bool a_ok = m0 + srow < M, b_ok = n0 + srow < N;
+  const uint4* ag = reinterpret_cast<const uint4*>(A + (int64_t)(m0 + srow) * Kp + sk);
+  const uint4* bg = reinterpret_cast<const uint4*>(Bt + (int64_t)(n0 + srow) * Kp + sk);
+  uint4 ra[2], rb[2];
+  const uint4 z = {0u, 0u, 0u, 0u};
+  auto fetch = [&](int k0) {
+    const int o = k0 / 8;  // uint4 = 8 bf16
+    ra[0] = a_ok ? ag[o] : z;
+    ra[1] = a_ok ? ag[o + 1] : z;
+    rb[0] = b_ok ? bg[o] : z;
+    rb[1] = b_ok ? bg[o + 1] : z;
+  };
+  f32x16 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  for (int k0 = 0; k0 < K; k0 += KS) {
-    for (int t = tid; t < 64 * KS; t += 256) {
-      const int mm = t / KS, kk = t % KS;
-      const int gm = m0 + mm, gk = k0 + kk;
-      float v = (gm < M && gk < K) ? X[(int64_t)gm * ldx + gk] : 0.f;
-      Xs[mm][kk] = f2bf(v);
-    }
-    for (int t = tid; t < 64 * KS; t += 256) {
-      const int nn = t % 64, kk = t / 64;
-      const int gk = k0 + kk, gn = n0 + nn;
-      Ws[nn][kk] = (gk < K && gn < N) ? W[(int64_t)gk * ldw + gn] : (unsigned short)0;
-    }
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+  fetch(0);
+  for (int k0 = 0; k0 < Kp; k0 += MM_K) {
+    __syncthreads();  // previous stage's fragment reads are done
+    *reinterpret_cast<uint4*>(&As[srow][sk]) = ra[0];
+    *reinterpret_cast<uint4*>(&As[srow][sk + 8]) = ra[1];
+    *reinterpret_cast<uint4*>(&Bs[srow][sk]) = rb[0];
+    *reinterpret_cast<uint4*>(&Bs[srow][sk + 8]) = rb[1];
     __syncthreads();
+    if (k0 + MM_K < Kp) fetch(k0 + MM_K);
+    const int r = lane % 32, kq = (lane / 32) * 4;
 #pragma unroll
-    for (int ks = 0; ks < KS; ks += 8) {
-      bf16x4 a, b;
-      const int r = lane % 32, kq = (lane / 32) * 4;
+    for (int ks = 0; ks < MM_K; ks += 8) {
+      bf16x4 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = (short)Xs[wm + r][ks + kq + i];
-        b[i] = (short)Ws[wn + r][ks + kq + i];
+      for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const bf16x4*>(&As[wm + i * 32 + r][ks + kq]);
+        b[i] = *reinterpret_cast<const bf16x4*>(&Bs[wn + i * 32 + r][ks + kq]);
       }
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    __syncthreads();
-  }
-  // D layout (32x32): lane -> column n = lane % 32; element i -> row
-  // (i / 4) * 8 + (lane / 32) * 4 + (i % 4)
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int row = (i / 4) * 8 + (lane / 32) * 4 + (i % 4);
-    const int gm = m0 + wm + row, gn = n0 + wn + lane % 32;
-    if (gm < M && gn < N) {
-      float v = acc[i];
-      if (EPI == EPI_BIAS) v += bias[gn];
-      if (EPI == EPI_BIAS_RELU) v = fmaxf(v + bias[gn], 0.f);
-      C[(int64_t)gm * ldc + gn] = v;
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
+  // D layout (32x32 block): lane -> column lane % 32; element e -> row
+  // (e / 4) * 8 + (lane / 32) * 4 + e % 4
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int gn = n0 + wn + j * 32 + lane % 32;
+      if (gn >= N) continue;
+      const float bb = (EPI == EPI_BIAS || EPI == EPI_BIAS_RELU) ? bias[gn] : 0.f;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int gm = m0 + wm + i * 32 + (e / 4) * 8 + (lane / 32) * 4 + e % 4;
+        if (gm >= M) continue;
+        float v = acc[i][j][e] + bb;
+        if (EPI == EPI_BIAS_RELU) v = fmaxf(v, 0.f);
+        if (OUT_BF16)
+          reinterpret_cast<unsigned short*>(Cout)[(int64_t)gm * ldc + gn] = f2bf(v);
+        else
+          reinterpret_cast<float*>(Cout)[(int64_t)gm * ldc + gn] = v;
+      }
+    }
 }
 
-__global__ void k_to_bf16(const float* __restrict__ src, unsigned short* __restrict__ dst, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = f2bf(src[i]);
+__global__ void k_fill_u16(unsigned short* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// dst[r][k] = bf16(src[r][k]) for k < K, zero for K <= k < Kp (row-major).
+__global__ void k_rows_to_bf16(const float* __restrict__ src, int rows, int K, int Kp, unsigned short* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * Kp) return;
+  const int64_t r = i / Kp;
+  const int k = (int)(i - r * Kp);
+  dst[i] = k < K ? f2bf(src[r * K + k]) : (unsigned short)0;
+}
+
+// Transposed bf16 weights: dst[n][k] = bf16(W[k][n]) (W row-major [K][N]),
+// zero for K <= k < Kp.
+__global__ void k_weight_t_bf16(const float* __restrict__ W, int K, int N, int Kp, unsigned short* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)N * Kp) return;
+  const int64_t n = i / Kp;
+  const int k = (int)(i - n * Kp);
+  dst[i] = k < K ? f2bf(W[(int64_t)k * N + n]) : (unsigned short)0;
 }
 
 // ------------------------------------------------------------------ loss, bias grads, Adam
@@ -316,7 +365,8 @@ __global__ void k_warm_features(const PlanSlots* __restrict__ ps, const int* __r
 // its slot's representative contributes its conjugate, and only when the
 // representative itself is not stored.
 __global__ void k_warm_targets(const PlanSlots* __restrict__ ps, const int* __restrict__ plan_of,
-                               const int64_t* __restrict__ coef_base, int B, int S, const cpx<float>* __restrict__ co,
+                               const int64_t* __restrict__ coef_base, int per_rve, int B, int S,
+                               const cpx<float>* __restrict__ co,
                                BornPar bp, float* __restrict__ T) {
   const int b = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -339,7 +389,7 @@ __global__ void k_warm_targets(const PlanSlots* __restrict__ ps, const int* __re
   float* t = T + (int64_t)b * (18 * S) + (int64_t)s * 18;
   for (int k = 0; k < 3; ++k) {
     for (int c = 0; c < 3; ++c) {
-      cpx<float> v = co[coef_base[b] + ((int64_t)k * 3 + c) * P.ncoef + e];
+      cpx<float> v = co[coef_base[b] * per_rve + ((int64_t)k * 3 + c) * P.ncoef + e];
       if (conj) v.y = -v.y;
       t[(c * 3 + k) * 2] = v.x * invN - bt[c][k].x;
       t[(c * 3 + k) * 2 + 1] = v.y * invN - bt[c][k].y;
@@ -351,7 +401,8 @@ __global__ void k_warm_targets(const PlanSlots* __restrict__ ps, const int* __re
 // (conjugated for partner coefficients), Y taken as zero for slots s >= S;
 // zero at xi = 0 (the solver sets the mean).
 __global__ void k_warm_apply(const PlanSlots* __restrict__ ps, const int* __restrict__ plan_of,
-                             const int64_t* __restrict__ coef_base, int B, int S, const float* __restrict__ Y,
+                             const int64_t* __restrict__ coef_base, int per_rve, int B, int S,
+                             const float* __restrict__ Y,
                              const double* __restrict__ ebar, BornPar bp, cpx<float>* __restrict__ warm) {
   const int b = blockIdx.y;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -382,7 +433,7 @@ __global__ void k_warm_apply(const PlanSlots* __restrict__ ps, const int* __rest
       }
     }
   }
-  for (int c = 0; c < 3; ++c) warm[coef_base[b] + (int64_t)c * P.ncoef + e] = out[c];
+  for (int c = 0; c < 3; ++c) warm[coef_base[b] * per_rve + (int64_t)c * P.ncoef + e] = out[c];
 }
 
 }  // namespace
@@ -395,8 +446,16 @@ struct mor_mlp {
   float* g = nullptr;
   float* m = nullptr;
   float* v = nullptr;
-  unsigned short* wbf = nullptr;  // bf16 copies of W1, W2, W3
+  unsigned short* wbf = nullptr;  // bf16 transposed, K-padded copies of W1, W2, W3
   bool bf_valid = false;
+  unsigned short* abf = nullptr;  // bf16 activations for inference: X | H1 | H2
+  int64_t abf_cap = 0;            // rows the bf16 activation buffer holds
+  int kp_in() const { return (in + 31) / 32 * 32; }
+  int kp_hid() const { return (hid + 31) / 32 * 32; }
+  int64_t wt1() const { return 0; }
+  int64_t wt2() const { return (int64_t)hid * kp_in(); }
+  int64_t wt3() const { return wt2() + (int64_t)hid * kp_hid(); }
+  int64_t wt_end() const { return wt3() + (int64_t)out * kp_hid(); }
   int64_t step = 0;
   // activation workspace
   int64_t cap_b = 0;
@@ -499,21 +558,55 @@ std::vector<PlanSlots> slot_views(const mor_plan_t* plans, int64_t nplans) {
   return v;
 }
 
-// Device copies of plan views, plan_of and per-RVE coefficient bases.
+// Device copies of plan views, plan_of and per-RVE coefficient bases (in
+// units of one component's coefficients), cached per (device, stream): a call
+// with the same plans (by uid) and plan_of reuses them without any copy.
+// A rebuild first drains the stream, since queued kernels may still read the
+// old tables.
 struct SlotArgs {
+  std::unique_lock<std::mutex> hold;  // the stream's cache, until the launches are queued
+  const PlanSlots* ps = nullptr;
+  const int* po = nullptr;
+  const int64_t* base = nullptr;
+  int maxcoef = 0;
+  double* ebar = nullptr;  // device macro strains (warm_apply)
+};
+
+struct SlotCache {
+  std::mutex mu;
+  std::vector<uint64_t> uids;
+  std::vector<int64_t> plan_of;
   PlanSlots* ps = nullptr;
   int* po = nullptr;
   int64_t* base = nullptr;
+  size_t cap_p = 0, cap_b = 0;
   int maxcoef = 0;
-  ~SlotArgs() {
-    (void)hipFree(ps);
-    (void)hipFree(po);
-    (void)hipFree(base);
-  }
+  std::vector<PlanSlots> h_ps;
+  std::vector<int> h_po;
+  std::vector<int64_t> h_base;
+  double* ebar = nullptr;    // device
+  double* h_ebar = nullptr;  // pinned staging of the macro strains
+  size_t cap_e = 0;
+  hipEvent_t ebar_done = nullptr;
 };
 
-mor_status slot_args(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of, int64_t B, int per_rve,
-                     hipStream_t st, SlotArgs& a) {
+std::mutex g_slot_mu;
+std::map<std::pair<int, void*>, SlotCache*> g_slot_cache;
+
+SlotCache* slot_cache(hipStream_t st) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_slot_mu);
+  auto key = std::make_pair(dev, (void*)st);
+  auto it = g_slot_cache.find(key);
+  if (it != g_slot_cache.end()) return it->second;
+  SlotCache* c = new SlotCache();
+  g_slot_cache[key] = c;
+  return c;
+}
+
+mor_status slot_args(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of, int64_t B, hipStream_t st,
+                     SlotArgs& a) {
   if (!plans || nplans < 1 || !plan_of || B < 1) {
     mor_set_error("warm: invalid plans / plan_of / B");
     return MOR_E_INVALID_ARG;
@@ -524,28 +617,90 @@ mor_status slot_args(const mor_plan_t* plans, int64_t nplans, const int64_t* pla
       return plans[i] ? MOR_E_UNSUPPORTED : MOR_E_INVALID_ARG;
     }
   }
-  std::vector<PlanSlots> v = slot_views(plans, nplans);
-  std::vector<int> po(B);
-  std::vector<int64_t> base(B);
-  int64_t off = 0;
-  for (int64_t b = 0; b < B; ++b) {
+  for (int64_t b = 0; b < B; ++b)
     if (plan_of[b] < 0 || plan_of[b] >= nplans) {
       mor_set_error("warm: plan_of out of range");
       return MOR_E_INVALID_ARG;
     }
-    po[b] = (int)plan_of[b];
-    base[b] = off;
-    off += (int64_t)per_rve * v[po[b]].ncoef;
-    a.maxcoef = std::max(a.maxcoef, v[po[b]].ncoef);
+  SlotCache* c = slot_cache(st);
+  a.hold = std::unique_lock<std::mutex>(c->mu);
+  bool same = (int64_t)c->uids.size() == nplans && (int64_t)c->plan_of.size() == B;
+  for (int64_t i = 0; same && i < nplans; ++i) same = c->uids[i] == plans[i]->uid;
+  if (same) same = std::equal(plan_of, plan_of + B, c->plan_of.begin());
+  if (!same) {
+    MOR_HIP_TRY(hipStreamSynchronize(st));
+    c->uids.resize(nplans);
+    for (int64_t i = 0; i < nplans; ++i) c->uids[i] = plans[i]->uid;
+    c->plan_of.assign(plan_of, plan_of + B);
+    c->h_ps = slot_views(plans, nplans);
+    c->h_po.resize(B);
+    c->h_base.resize(B);
+    int64_t off = 0;
+    c->maxcoef = 0;
+    for (int64_t b = 0; b < B; ++b) {
+      c->h_po[b] = (int)plan_of[b];
+      c->h_base[b] = off;
+      off += c->h_ps[c->h_po[b]].ncoef;
+      c->maxcoef = std::max(c->maxcoef, c->h_ps[c->h_po[b]].ncoef);
+    }
+    if (c->cap_p < (size_t)nplans) {
+      (void)hipFree(c->ps);
+      c->ps = nullptr;
+      c->cap_p = 0;
+      MOR_HIP_TRY(hipMalloc((void**)&c->ps, nplans * sizeof(PlanSlots)));
+      c->cap_p = nplans;
+    }
+    if (c->cap_b < (size_t)B) {
+      (void)hipFree(c->po);
+      (void)hipFree(c->base);
+      c->po = nullptr;
+      c->base = nullptr;
+      c->cap_b = 0;
+      MOR_HIP_TRY(hipMalloc((void**)&c->po, B * sizeof(int)));
+      MOR_HIP_TRY(hipMalloc((void**)&c->base, B * sizeof(int64_t)));
+      c->cap_b = B;
+    }
+    MOR_HIP_TRY(hipMemcpyAsync(c->ps, c->h_ps.data(), nplans * sizeof(PlanSlots), hipMemcpyHostToDevice, st));
+    MOR_HIP_TRY(hipMemcpyAsync(c->po, c->h_po.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+    MOR_HIP_TRY(hipMemcpyAsync(c->base, c->h_base.data(), B * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    // the host vectors stay alive (and unchanged) until the next rebuild,
+    // which drains the stream first
   }
-  MOR_HIP_TRY(hipMalloc((void**)&a.ps, v.size() * sizeof(PlanSlots)));
-  MOR_HIP_TRY(hipMalloc((void**)&a.po, B * sizeof(int)));
-  MOR_HIP_TRY(hipMalloc((void**)&a.base, B * sizeof(int64_t)));
-  MOR_HIP_TRY(hipMemcpy(a.ps, v.data(), v.size() * sizeof(PlanSlots), hipMemcpyHostToDevice));
-  MOR_HIP_TRY(hipMemcpy(a.po, po.data(), B * sizeof(int), hipMemcpyHostToDevice));
-  MOR_HIP_TRY(hipMemcpy(a.base, base.data(), B * sizeof(int64_t), hipMemcpyHostToDevice));
-  (void)st;
+  a.ps = c->ps;
+  a.po = c->po;
+  a.base = c->base;
+  a.maxcoef = c->maxcoef;
   return MOR_OK;
+}
+
+// Macro strains of warm_apply, staged through pinned memory; the staging
+// buffer is reused once the previous upload has completed.  Called with the
+// stream's cache held (after slot_args).
+mor_status upload_ebar(hipStream_t st, const double* host, int64_t n, SlotArgs& a) {
+  SlotCache* c = slot_cache(st);
+  if (c->ebar_done) MOR_HIP_TRY(hipEventSynchronize(c->ebar_done));
+  if (c->cap_e < (size_t)n) {
+    MOR_HIP_TRY(hipStreamSynchronize(st));
+    (void)hipFree(c->ebar);
+    (void)hipHostFree(c->h_ebar);
+    c->ebar = nullptr;
+    c->h_ebar = nullptr;
+    c->cap_e = 0;
+    MOR_HIP_TRY(hipMalloc((void**)&c->ebar, n * sizeof(double)));
+    MOR_HIP_TRY(hipHostMalloc((void**)&c->h_ebar, n * sizeof(double), hipHostMallocDefault));
+    c->cap_e = n;
+  }
+  if (!c->ebar_done) MOR_HIP_TRY(hipEventCreateWithFlags(&c->ebar_done, hipEventDisableTiming));
+  std::memcpy(c->h_ebar, host, n * sizeof(double));
+  MOR_HIP_TRY(hipMemcpyAsync(c->ebar, c->h_ebar, n * sizeof(double), hipMemcpyHostToDevice, st));
+  MOR_HIP_TRY(hipEventRecord(c->ebar_done, st));
+  a.ebar = c->ebar;
+  return MOR_OK;
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
 }
 
 }  // namespace
@@ -566,7 +721,7 @@ extern "C" mor_status mor_mlp_create(int32_t in_dim, int32_t hidden, int32_t out
       hipMalloc((void**)&net->g, np * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&net->m, np * sizeof(float)) != hipSuccess ||
       hipMalloc((void**)&net->v, np * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&net->wbf, (net->off_b3() + 0) * sizeof(unsigned short)) != hipSuccess) {
+      hipMalloc((void**)&net->wbf, net->wt_end() * sizeof(unsigned short)) != hipSuccess) {
     (void)hipGetLastError();
     mor_mlp_destroy(net);
     mor_set_error("mor_mlp_create: allocation failed");
@@ -598,6 +753,7 @@ extern "C" mor_status mor_mlp_destroy(mor_mlp_t net) {
   (void)hipFree(net->g);
   (void)hipFree(net->m);
   (void)hipFree(net->v);
+  (void)hipFree(net->abf);
   (void)hipFree(net->wbf);
   (void)hipFree(net->ws);
   (void)hipFree(net->part);
@@ -650,23 +806,50 @@ extern "C" mor_status mor_mlp_forward(mor_mlp_t net, const float* X, int64_t B, 
   if (precision == MOR_MLP_FP32) {
     forward_fp32(net, st, X, (int)B, a, Y);
   } else if (precision == MOR_MLP_BF16) {
-    // BF16 inference: weights rounded once per parameter update
+    // BF16 inference: transposed, K-padded bf16 weights refreshed once per
+    // parameter update; activations stay bf16 between the layers
+    const int kpi = net->kp_in(), kph = net->kp_hid();
     if (!net->bf_valid) {
-      const int64_t nw = net->off_b3();
-      k_to_bf16<<<(unsigned)((nw + 255) / 256), 256, 0, st>>>(net->p, net->wbf, nw);
-      MOR_LAUNCH_CHECK("to_bf16");
+      const int64_t n1 = (int64_t)net->hid * kpi, n2 = (int64_t)net->hid * kph, n3 = (int64_t)net->out * kph;
+      k_weight_t_bf16<<<(unsigned)((n1 + 255) / 256), 256, 0, st>>>(net->p + net->off_W1(), net->in, net->hid, kpi,
+                                                                   net->wbf + net->wt1());
+      k_weight_t_bf16<<<(unsigned)((n2 + 255) / 256), 256, 0, st>>>(net->p + net->off_W2(), net->hid, net->hid, kph,
+                                                                   net->wbf + net->wt2());
+      k_weight_t_bf16<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(net->p + net->off_W3(), net->hid, net->out, kph,
+                                                                   net->wbf + net->wt3());
+      MOR_LAUNCH_CHECK("weights to bf16");
       net->bf_valid = true;
     }
+    if (net->abf_cap < B) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(net->abf);
+      net->abf = nullptr;
+      net->abf_cap = 0;
+      if (hipMalloc((void**)&net->abf, (size_t)B * (kpi + 2 * kph) * sizeof(unsigned short)) != hipSuccess) {
+        (void)hipGetLastError();
+        mor_set_error("mor_mlp_forward: allocation failed");
+        return MOR_E_OUT_OF_MEMORY;
+      }
+      net->abf_cap = B;
+      // the K padding of H1 and H2 is never written by the GEMMs: zero it once
+      const int64_t nb = (int64_t)B * (kpi + 2 * kph);
+      k_fill_u16<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(net->abf, nb);
+    }
+    unsigned short* xb = net->abf;
+    unsigned short* h1 = xb + (size_t)B * kpi;
+    unsigned short* h2 = h1 + (size_t)B * kph;
     const float* P = net->p;
     const unsigned short* W = net->wbf;
-    dim3 g1((net->hid + 63) / 64, (unsigned)((B + 63) / 64));
-    k_gemm_bf16<EPI_BIAS_RELU><<<g1, 256, 0, st>>>((int)B, net->hid, net->in, X, net->in, W + net->off_W1(), net->hid,
-                                                   a.H1, net->hid, P + net->off_b1());
-    k_gemm_bf16<EPI_BIAS_RELU><<<g1, 256, 0, st>>>((int)B, net->hid, net->hid, a.H1, net->hid, W + net->off_W2(),
-                                                   net->hid, a.H2, net->hid, P + net->off_b2());
-    dim3 g3((net->out + 63) / 64, (unsigned)((B + 63) / 64));
-    k_gemm_bf16<EPI_BIAS><<<g3, 256, 0, st>>>((int)B, net->out, net->hid, a.H2, net->hid, W + net->off_W3(), net->out,
-                                              Y, net->out, P + net->off_b3());
+    k_rows_to_bf16<<<(unsigned)((B * kpi + 255) / 256), 256, 0, st>>>(X, (int)B, net->in, kpi, xb);
+    const unsigned gm = (unsigned)((B + MM_T - 1) / MM_T);
+    dim3 g1((net->hid + MM_T - 1) / MM_T, gm);
+    k_mm_bf16<EPI_BIAS_RELU, true><<<g1, 256, 0, st>>>((int)B, net->hid, kpi, xb, W + net->wt1(), P + net->off_b1(),
+                                                       h1, kph);
+    k_mm_bf16<EPI_BIAS_RELU, true><<<g1, 256, 0, st>>>((int)B, net->hid, kph, h1, W + net->wt2(), P + net->off_b2(),
+                                                       h2, kph);
+    dim3 g3((net->out + MM_T - 1) / MM_T, gm);
+    k_mm_bf16<EPI_BIAS, false><<<g3, 256, 0, st>>>((int)B, net->out, kph, h2, W + net->wt3(), P + net->off_b3(), Y,
+                                                  net->out);
   } else {
     mor_set_error("mor_mlp_forward: precision must be MOR_MLP_FP32 or MOR_MLP_BF16");
     return MOR_E_INVALID_ARG;
@@ -742,12 +925,11 @@ extern "C" mor_status mor_warm_features(const mor_plan_t* plans, int64_t nplans,
   }
   hipStream_t st = (hipStream_t)stream;
   SlotArgs a;
-  mor_status s = slot_args(plans, nplans, plan_of, B, 1, st, a);
+  mor_status s = slot_args(plans, nplans, plan_of, B, st, a);
   if (s != MOR_OK) return s;
   dim3 grid((nslots + 255) / 256, (unsigned)B);
   k_warm_features<<<grid, 256, 0, st>>>(a.ps, a.po, (int)B, nslots, X);
   MOR_LAUNCH_CHECK("warm_features");
-  MOR_HIP_TRY(hipStreamSynchronize(st));
   return MOR_OK;
 }
 
@@ -761,13 +943,14 @@ extern "C" mor_status mor_warm_targets(const mor_plan_t* plans, int64_t nplans, 
   }
   hipStream_t st = (hipStream_t)stream;
   SlotArgs a;
-  mor_status s = slot_args(plans, nplans, plan_of, B, 9, st, a);  // 3 unit cases x 3 components
+  mor_status s = slot_args(plans, nplans, plan_of, B, st, a);
   if (s != MOR_OK) return s;
-  MOR_HIP_TRY(hipMemsetAsync(T, 0, (size_t)B * 18 * nslots * sizeof(float), st));
+  const int64_t nt = B * 18 * (int64_t)nslots;
+  k_fill_f32<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(T, nt);
   dim3 grid((a.maxcoef + 255) / 256, (unsigned)B);
-  k_warm_targets<<<grid, 256, 0, st>>>(a.ps, a.po, a.base, (int)B, nslots, (const cpx<float>*)coeffs, bp, T);
+  // 3 unit cases x 3 components per RVE
+  k_warm_targets<<<grid, 256, 0, st>>>(a.ps, a.po, a.base, 9, (int)B, nslots, (const cpx<float>*)coeffs, bp, T);
   MOR_LAUNCH_CHECK("warm_targets");
-  MOR_HIP_TRY(hipStreamSynchronize(st));
   return MOR_OK;
 }
 
@@ -781,19 +964,11 @@ extern "C" mor_status mor_warm_apply(const mor_plan_t* plans, int64_t nplans, co
   }
   hipStream_t st = (hipStream_t)stream;
   SlotArgs a;
-  mor_status s = slot_args(plans, nplans, plan_of, B, 3, st, a);
+  mor_status s = slot_args(plans, nplans, plan_of, B, st, a);
   if (s != MOR_OK) return s;
-  double* deb = nullptr;
-  MOR_HIP_TRY(hipMalloc((void**)&deb, B * 3 * sizeof(double)));
-  MOR_HIP_TRY(hipMemcpy(deb, macro_strain, B * 3 * sizeof(double), hipMemcpyHostToDevice));
+  if ((s = upload_ebar(st, macro_strain, B * 3, a)) != MOR_OK) return s;
   dim3 grid((a.maxcoef + 255) / 256, (unsigned)B);
-  k_warm_apply<<<grid, 256, 0, st>>>(a.ps, a.po, a.base, (int)B, nslots, Y, deb, bp, (cpx<float>*)warm);
-  hipError_t le = hipGetLastError();
-  (void)hipStreamSynchronize(st);
-  (void)hipFree(deb);
-  if (le != hipSuccess) {
-    mor_set_error(std::string("launch warm_apply: ") + hipGetErrorString(le));
-    return MOR_E_DEVICE;
-  }
+  k_warm_apply<<<grid, 256, 0, st>>>(a.ps, a.po, a.base, 3, (int)B, nslots, Y, a.ebar, bp, (cpx<float>*)warm);
+  MOR_LAUNCH_CHECK("warm_apply");
   return MOR_OK;
 }

@@ -70,6 +70,7 @@ struct PlanDev {
 };
 
 struct mor_plan {
+  uint64_t uid = 0;  // unique per plan in the process (caches key on it, not on the address)
   int ndim = 0;
   int n[3] = {1, 1, 1};
   int64_t N = 0, M = 0, M_actual = 0, count = 0;

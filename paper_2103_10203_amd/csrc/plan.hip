@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -811,7 +812,9 @@ extern "C" mor_status mor_plan_create(const mor_grid* grid, const uint8_t* phase
       return MOR_E_INVALID_ARG;
     }
   }
+  static std::atomic<uint64_t> next_uid{0};
   mor_plan* P = new mor_plan();
+  P->uid = ++next_uid;
   P->ndim = grid->ndim;
   for (int a = 0; a < grid->ndim; ++a) P->n[a] = (int)grid->n[a];
   P->N = N;

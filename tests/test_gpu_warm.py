@@ -193,3 +193,20 @@ def test_trained_network_gain_small_grid():
     assert hot.iterations.mean() < cold.iterations.mean()
     rel = np.max(np.abs(hot.eff_stress - cold.eff_stress)) / np.max(np.abs(cold.eff_stress))
     assert rel < 2e-5
+
+
+def test_bf16_inference_real_shape():
+    """The tiled BF16 MFMA inference at the warm-start network's real shape
+    (4097 -> 512 -> 512 -> 18432, batch 1024 plus a ragged batch) against the
+    FP32 path."""
+    import torch
+    mor = _mor()
+    S = 1024
+    net = mor.MLP(4 * S + 1, 512, 18 * S, seed=11)
+    rng = np.random.default_rng(8)
+    for B in (1024, 37):
+        X = torch.tensor((rng.normal(size=(B, 4 * S + 1)) * 0.1).astype(np.float32), device="cuda")
+        y32 = net.forward(X, mor.MLP_FP32)
+        y16 = net.forward(X, mor.MLP_BF16)
+        rel = float(torch.linalg.norm(y16 - y32) / torch.linalg.norm(y32))
+        assert rel < 2e-2, (B, rel)
