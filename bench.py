@@ -205,7 +205,8 @@ def main():
     ap.add_argument("--train", type=int, default=20000,
                     help="training microstructures of the warm-start network (0: cold start only)")
     ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--nslots", type=int, default=1024)
+    ap.add_argument("--nslots", type=int, default=256,
+                    help="network slots (ranked conjugate pairs); the Born prior covers every pair")
     ap.add_argument("--transform", choices=["auto", "fft", "dft"], default="auto",
                     help="last-axis transform of every solve (auto = the pruned FFT)")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",

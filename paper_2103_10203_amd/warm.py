@@ -28,7 +28,7 @@ UNIT = np.eye(3)
 
 @dataclass
 class WarmConfig:
-    nslots: int = 1024
+    nslots: int = 256
     hidden: int = 512
     seed: int = 0
     epochs: int = 60
