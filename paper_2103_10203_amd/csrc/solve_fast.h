@@ -364,9 +364,9 @@ struct ColVar {
 template <> struct ColCfg<3, 64, 0>  { static constexpr int RF = 8,  CB = 8; using FA = RList<8>; };
 template <> struct ColCfg<3, 64, 1>  { static constexpr int RF = 4,  CB = 4; using FA = RList<4, 4>; };
 template <> struct ColVar<3, 64> { static constexpr int count = 2; };
-template <> struct ColCfg<3, 128, 0> { static constexpr int RF = 4,  CB = 2; using FA = RList<8, 4>; };
+template <> struct ColCfg<3, 128, 0> { static constexpr int RF = 8,  CB = 4; using FA = RList<4, 4>; };
 template <> struct ColCfg<3, 128, 1> { static constexpr int RF = 16, CB = 8; using FA = RList<8>; };
-template <> struct ColCfg<3, 128, 2> { static constexpr int RF = 8,  CB = 4; using FA = RList<4, 4>; };
+template <> struct ColCfg<3, 128, 2> { static constexpr int RF = 4,  CB = 2; using FA = RList<8, 4>; };
 template <> struct ColVar<3, 128> { static constexpr int count = 3; };
 template <> struct ColCfg<3, 256, 0> { static constexpr int RF = 8,  CB = 2; using FA = RList<8, 4>; };
 template <> struct ColCfg<3, 256, 1> { static constexpr int RF = 4,  CB = 1; using FA = RList<8, 8>; };
@@ -395,7 +395,7 @@ constexpr int col_ss() {
 }
 template <int C, int N0, int V>
 constexpr size_t col_lds_bytes() {
-  return (size_t)(pad16(N0 - 1) + 1 + 2 * C * ColCfg<C, N0, V>::CB * col_ss<N0>()) * sizeof(cpx<float>);
+  return (size_t)(pad16(N0 - 1) + 1 + C * ColCfg<C, N0, V>::CB * col_ss<N0>()) * sizeof(cpx<float>);
 }
 
 // One block of columns (tile) of one RVE.
@@ -421,10 +421,10 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
   if (j0 >= ncol) return;
   const int ncb = min(CB, ncol - j0);
   cpx<float>* tw = reinterpret_cast<cpx<float>*>(smem_raw);
-  cpx<float>* fbuf = tw + pad16(N0 - 1) + 1;  // forward result tau^
-  cpx<float>* ibuf = fbuf + NSEQ * SS;         // new coefficients / inverse transform
+  // one buffer: the forward result tau^, then (after the Green step has read
+  // it) the new coefficients and the inverse transform
+  cpx<float>* buf = tw + pad16(N0 - 1) + 1;
   for (int t = tid; t < N0; t += NT) tw[pad16(t)] = P.tw0[t];
-  for (int t = tid; t < NSEQ * SS; t += NT) ibuf[t] = {0.f, 0.f};
   if (tid <= CB) coff[tid] = P.col_off[j0 + min(tid, ncb)];
   // prefetch this thread's first pattern entry (its loads overlap the FFT)
   const int ncoef = P.ncoef;
@@ -457,22 +457,31 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
 #pragma unroll
     for (int j = 0; j < RF; ++j) v[j] = col_live ? yline[i + j * TS] : cpx<float>{0.f, 0.f};
     Dft<RF, -1>::run(v);
-    cpx<float>* dst = fbuf + s * SS;
+    cpx<float>* dst = buf + s * SS;
 #pragma unroll
     for (int j = 0; j < RF; ++j) dst[pad16(i * RF + j)] = v[j];
     __syncthreads();
-    fftr::lds_passes<N0, -1, RF, NSEQ, SS, NT, 1>(fbuf, tw, tid, typename Cfg::FA{});
+    fftr::lds_passes<N0, -1, RF, NSEQ, SS, NT, 1>(buf, tw, tid, typename Cfg::FA{});
   } else {
     __syncthreads();
   }
-  // step c): Green operator on the block's pattern entries
+  // step c): Green operator on the block's pattern entries.  A thread
+  // handles at most EPT entries; their results stay in registers until the
+  // buffer has been read by every thread and cleared.
+  constexpr int EPT = (CB * N0 + NT - 1) / NT;
   const float invN = P.inv_N;
   double dsum = 0.0;
-  for (int e = ebeg + tid; e < eend; e += NT) {
+  cpx<float> res[EPT][C];
+  int rpos[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    rpos[u] = -1;
+    const int e = ebeg + tid + u * NT;
+    if (e >= eend) continue;
     int jj = 0;
     while (jj + 1 < ncb && e >= coff[jj + 1]) ++jj;
     const int j = j0 + jj;
-    const bool first = e == ebeg + tid;
+    const bool first = u == 0;
     const int k0 = first ? pk0 : P.coef_k0[e];
     const uint8_t fl = first ? pfl : P.coef_flag[e];
     float nr_[C], ni_[C];
@@ -489,7 +498,7 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
       float tr_[C], ti_[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const cpx<float> w = fbuf[(c * CB + jj) * SS + pad16(k0)];
+        const cpx<float> w = buf[(c * CB + jj) * SS + pad16(k0)];
         tr_[c] = w.x;
         ti_[c] = w.y;
       }
@@ -538,15 +547,25 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       co[(int64_t)c * ncoef + e] = {nr_[c], ni_[c]};
-      ibuf[(c * CB + jj) * SS + pad16(k0)] = {nr_[c] * invN, ni_[c] * invN};
+      res[u][c] = {nr_[c] * invN, ni_[c] * invN};
     }
+    rpos[u] = jj * SS + pad16(k0);
   }
+  __syncthreads();  // every read of tau^ is done
+  for (int t = tid; t < NSEQ * SS; t += NT) buf[t] = {0.f, 0.f};
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < EPT; ++u)
+    if (rpos[u] >= 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) buf[c * CB * SS + rpos[u]] = res[u][c];
+    }
   __syncthreads();
   // step d), axis 0: inverse passes, the last one straight to global memory
-  fftr::lds_passes<N0, +1, 1, NSEQ, SS, NT, 1>(ibuf, tw, tid, typename fftr::Rev<typename Cfg::FA, RList<>>::type{});
+  fftr::lds_passes<N0, +1, 1, NSEQ, SS, NT, 1>(buf, tw, tid, typename fftr::Rev<typename Cfg::FA, RList<>>::type{});
   {
     cpx<float> v[RF];
-    const cpx<float>* src = ibuf + s * SS;
+    const cpx<float>* src = buf + s * SS;
 #pragma unroll
     for (int j = 0; j < RF; ++j) v[j] = src[pad16(i + j * TS)];
     fftr::pass_twiddle<N0, RF, TS, +1>(v, i, tw);

@@ -1,0 +1,124 @@
+"""Expected values of the full-size GPU tests, written from the FP64 oracle.
+
+This script calls only the oracle (``oracle/``) and the seeded generators
+(``synth/``); nothing here comes from the HIP path.  Each fixture states the
+workload recipe and the passage of the paper it exercises.  Usage:
+
+    python tests/golden/make_golden.py [c2_j2_512] [c3_stiffness] [c4_128]
+"""
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle import material, pattern, solver  # noqa: E402
+
+LM, MM = synth.phase_lame(synth.MATRIX_E, synth.MATRIX_NU)
+LI, MI = synth.phase_lame(synth.FIBRE_E, synth.FIBRE_NU)
+PH = (material.Phase(LM, MM), material.Phase(LI, MI))
+PH_J2 = (material.Phase(LM, MM, sigma_y0=0.25, H=1.0, plastic=True), material.Phase(LI, MI))
+NSAMPLE = 256
+
+
+def sample_points(shape, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(int(np.prod(shape)), size=NSAMPLE, replace=False))
+
+
+def c2_geometry():
+    return synth.rsa_fibres(512, 512, 20.0, 40.0, seed=2103, target_vf=0.40).g
+
+
+def c3_geometries():
+    out = []
+    for n, seed in ((128, 31), (256, 32), (384, 33)):
+        out.append(synth.rsa_fibres(n, n, n / 32, n / 16, seed=seed, target_vf=0.35).g)
+    return out
+
+
+def c4_geometry():
+    return synth.rsa_spheres(128, 128, 128, 8.0, 14.0, seed=7, target_vf=0.25).g
+
+
+def c4_macro():
+    return synth.macro_strains(1, 6, 1e-3, seed=4)[0]
+
+
+def make_c2():
+    """Elasto-plastic load path (Sec. 2 J2 model, Sec. 5.2 load stepping):
+    512^2 fibres, 20 equal steps to eps_11 = 2 %, M = 1, 5, 20 % of N."""
+    g = c2_geometry()
+    pts = sample_points(g.shape, 77)
+    res = {"recipe": "synth.rsa_fibres(512, 512, 20, 40, seed=2103, target_vf=0.40); J2 matrix sigma_y0 0.25 GPa, "
+                     "H 1 GPa; 20 equal steps to eps_11 = 0.02; oracle tol 1e-9",
+           "cite": "Sec. 2 (J2 plasticity), Sec. 4 steps a-d, Sec. 5.2 (load steps)",
+           "vf": float(g.mean()), "sample_points": pts.tolist(), "cases": {}}
+    for R in (0.01, 0.05, 0.20):
+        M = int(math.ceil(R * g.size))
+        p = pattern.build_pattern(g, M)
+        t = time.perf_counter()
+        steps = solver.solve_path(g, PH_J2, solver.macro_tensor([0.02, 0.0, 0.0], 2), 20, mask=p.mask(), tol=1e-9)
+        sig = [solver.tensor_comps(s.sigma_bar, 2, with_s33=True).tolist() for s in steps]
+        alpha = steps[-1].alpha.reshape(-1)
+        res["cases"][str(M)] = {"R": R, "M": M, "sigma_bar": sig, "alpha_sample": alpha[pts].tolist(),
+                                "alpha_mean": float(alpha.mean()), "alpha_max": float(alpha.max())}
+        print(f"c2 M={M}: {time.perf_counter() - t:.0f} s", flush=True)
+    return res
+
+
+def make_c3():
+    """Effective stiffness of the three microstructures of the uneven batch
+    (Sec. 4 reduced scheme, linear elastic): sigma_bar = C_eff eps_bar for any
+    macro strain, from three unit-strain solves."""
+    res = {"recipe": "synth.rsa_fibres(n, n, n/32, n/16, seed, target_vf=0.35) for (n, seed) in "
+                     "((128, 31), (256, 32), (384, 33)); M = ceil(0.05 N); oracle tol 1e-11",
+           "cite": "Sec. 4 steps a-d (linear in the macro strain for Hooke phases)", "grids": []}
+    for g in c3_geometries():
+        M = int(math.ceil(0.05 * g.size))
+        p = pattern.build_pattern(g, M)
+        cols = []
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = 1.0
+            r = solver.solve(g, PH, solver.macro_tensor(e, 2), mask=p.mask(), tol=1e-11)
+            cols.append(solver.tensor_comps(r.sigma_bar, 2, with_s33=True))
+        res["grids"].append({"n": g.shape[0], "M": M, "C_eff": np.stack(cols, axis=1).tolist()})
+        print(f"c3 n={g.shape[0]} done", flush=True)
+    return res
+
+
+def make_c4():
+    """3D 128^3 spheres, M = 2 % (Sec. 4 reduced scheme in 3D)."""
+    g = c4_geometry()
+    eb = c4_macro()
+    M = int(math.ceil(0.02 * g.size))
+    p = pattern.build_pattern(g, M)
+    t = time.perf_counter()
+    r = solver.solve(g, PH, solver.macro_tensor(eb, 3), mask=p.mask(), tol=1e-9)
+    pts = sample_points(g.shape, 78)
+    eps = solver.tensor_comps(r.eps, 3).reshape(-1, 6)
+    print(f"c4: {time.perf_counter() - t:.0f} s, {r.iterations} iterations", flush=True)
+    return {"recipe": "synth.rsa_spheres(128, 128, 128, 8, 14, seed=7, target_vf=0.25); macro strain "
+                      "synth.macro_strains(1, 6, 1e-3, seed=4); M = ceil(0.02 N); oracle tol 1e-9",
+            "cite": "Sec. 4 steps a-d, 3D", "vf": float(g.mean()), "M": M, "macro_strain": eb.tolist(),
+            "sigma_bar": solver.tensor_comps(r.sigma_bar, 3, with_s33=True).tolist(),
+            "sample_points": pts.tolist(), "eps_sample": eps[pts].tolist()}
+
+
+MAKERS = {"c2_j2_512": make_c2, "c3_stiffness": make_c3, "c4_128": make_c4}
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(MAKERS)
+    for name in names:
+        data = MAKERS[name]()
+        with open(os.path.join(HERE, name + ".json"), "w") as fh:
+            json.dump(data, fh, indent=1)
+        print("wrote", name, flush=True)

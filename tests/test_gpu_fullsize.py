@@ -1,0 +1,100 @@
+"""Parity at the full sizes of the configured workloads, against expected
+values that `tests/golden/make_golden.py` wrote from the FP64 oracle:
+
+* the 4096-RVE uneven batch (128², 256², 384², one launch): every effective
+  stress against the oracle's effective stiffness of its microstructure
+  (the reduced scheme is linear in the macro strain for Hooke phases);
+* 128³ spheres at M = 2 %: effective stress and sampled strains, for the FFT
+  path, the FP32-MFMA DFT and the bf16x3 DFT;
+* 512² J2 fibres, 20 load steps to 2 %, M = 1, 5, 20 %: effective stress per
+  step and the accumulated plastic strain at sampled points.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests.golden.make_golden import c2_geometry, c3_geometries, c4_geometry, c4_macro
+from tests.gpu_common import native_phases
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"{name}.json not generated (python tests/golden/make_golden.py {name})")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_c3_uneven_batch_4096_against_effective_stiffness():
+    import paper_2103_10203_amd as mor
+    G = _golden("c3_stiffness")
+    gs = c3_geometries()
+    plans = [mor.Plan(g, grid["M"]) for g, grid in zip(gs, G["grids"])]
+    B = 4096
+    po = np.arange(B) % 3  # round robin: 1366 / 1365 / 1365
+    ebs = synth.macro_strains(B, 3, 5e-3, seed=2026)
+    out = mor.solve_multi(plans, po, ebs, native_phases(), 1e-6)
+    assert out.status == mor.MOR_OK
+    C = [np.array(grid["C_eff"]) for grid in G["grids"]]
+    want = np.stack([C[po[b]] @ ebs[b] for b in range(B)])
+    err = np.max(np.abs(out.eff_stress - want)) / np.max(np.abs(want))
+    assert err < 1e-5, err
+
+
+@pytest.mark.parametrize("path", ["fft", "dft_fp32", "dft_bf16x3"])
+def test_c4_128cube(path):
+    import paper_2103_10203_amd as mor
+    G = _golden("c4_128")
+    g = c4_geometry()
+    assert abs(float(g.mean()) - G["vf"]) < 1e-12
+    plan = mor.Plan(g, G["M"])
+    eb = np.array([c4_macro()])
+    kw = {"fft": {}, "dft_fp32": {"transform": mor.TRANSFORM_DFT},
+          "dft_bf16x3": {"precision": mor.PREC_BF16X3}}[path]
+    tol = 1e-5 if path == "dft_bf16x3" else 1e-6
+    out = mor.solve(plan, eb, native_phases(), tol, want_fields=True, **kw)
+    assert out.status == mor.MOR_OK
+    want = np.array(G["sigma_bar"])
+    err = np.max(np.abs(out.eff_stress[0] - want)) / np.max(np.abs(want))
+    assert err < (1e-4 if path == "dft_bf16x3" else 1e-5), err
+    pts = np.array(G["sample_points"])
+    eps = out.strain[0].reshape(6, -1)[:, pts].T.cpu().numpy()
+    assert _rel_l2(eps, G["eps_sample"]) < 1e-4
+
+
+@pytest.mark.parametrize("R", [0.01, 0.05, 0.20])
+def test_c2_j2_512_load_path(R):
+    import torch
+    import paper_2103_10203_amd as mor
+    G = _golden("c2_j2_512")
+    g = c2_geometry()
+    assert abs(float(g.mean()) - G["vf"]) < 1e-12
+    M = int(math.ceil(R * g.size))
+    case = G["cases"][str(M)]
+    plan = mor.Plan(g, M)
+    path = np.stack([[0.02 * (k + 1) / 20, 0.0, 0.0] for k in range(20)])
+    state = torch.zeros(5 * g.size, dtype=torch.float32, device="cuda")
+    out = mor.solve_path(plan, path, native_phases(j2=True), 1e-6, state)
+    assert out.status == mor.MOR_OK
+    want = np.array(case["sigma_bar"])
+    for k in range(20):
+        err = np.max(np.abs(out.eff_stress[k] - want[k])) / np.max(np.abs(want[k]))
+        assert err < 1e-4, (k, err)
+    pts = np.array(G["sample_points"])
+    alpha = state.view(5, -1)[4].double().cpu().numpy()
+    assert case["alpha_max"] > 0.0
+    assert _rel_l2(alpha[pts], case["alpha_sample"]) < 1e-3
+    assert abs(alpha.mean() - case["alpha_mean"]) < 1e-3 * case["alpha_mean"]
