@@ -14,10 +14,14 @@ the Born-prior-only rate, the plain single-RVE rates (cold and learned), the
 iteration statistics of each start, the training cost, and the effective
 stress difference between learned and cold starts.
 
-Prints one JSON line (rank 0).  It also reports the per-kernel roofline of the
-dominant kernel (HIP events around its launches inside the timed region,
-algorithmic bytes counted by the kernels), the plan-construction cost, and the
-FP64 CPU oracle on a bounded sample of the same workload.
+The timed steps record no per-kernel events (events around every launch
+cost about 9 % of the step); --graph 1 replays each chunk of iterations from a
+hipGraph (measured equal to eager launches).  Prints one JSON
+line (rank 0).  It also reports the per-kernel roofline of the dominant kernel
+(HIP events around each of its launches on the solve stream, in an eager
+repetition of the same steps right after the timed ones; algorithmic bytes
+counted from the plans and iteration counts), the plan-construction cost, and
+the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -121,31 +125,42 @@ def measured_traffic(kernel):
     return None
 
 
-SOLVE_KW = {}  # transform / precision of every solve (command line)
+SOLVE_KW = {}  # transform / precision / schedule of every solve (command line)
+BATCH_KW = {}  # options of the batched solves only
 
 
 def timed_batched(mor, plans, plan_of, ebs, ph, steps, warmup, warm_fn=None):
     """Batched solves of the whole workload; warm_fn (if given) builds the warm
-    start inside the timed region (features, network, scatter)."""
+    start inside the timed region (features, network, scatter).
+
+    The throughput is timed without per-kernel events (optionally with
+    hipGraph replay of the iteration chunks); the per-kernel durations of the
+    roofline come from a repetition of the same steps, launched eagerly with
+    HIP events around every kernel on the solve stream."""
     import torch
 
-    def step():
+    def step(**kw):
         w = warm_fn() if warm_fn else None
-        return mor.solve_multi(plans, plan_of, ebs, ph, TOL, warm_start=w, **SOLVE_KW)
+        return mor.solve_multi(plans, plan_of, ebs, ph, TOL, warm_start=w, **SOLVE_KW, **kw)
 
     for _ in range(warmup):
-        step()
-    mor.profile_reset()
-    mor.profile_enable(True)
+        step(**BATCH_KW)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = None
     for _ in range(steps):
-        out = step()
+        out = step(**BATCH_KW)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    mor.profile_enable(False)
     assert out.status == mor.MOR_OK, out.status
+    # profiled repetition: eager launches, events around each kernel
+    mor.profile_reset()
+    mor.profile_enable(True)
+    for _ in range(steps):
+        prof = step(use_graph=0)
+    torch.cuda.synchronize()
+    mor.profile_enable(False)
+    assert np.array_equal(prof.iterations, out.iterations)
     kern = {k: mor.profile_query(k) for k in ("row", "col", "final", "init")}
     return out, elapsed, kern
 
@@ -211,6 +226,8 @@ def main():
                     help="last-axis transform of every solve (auto = the pruned FFT)")
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32",
                     help="bf16x3: split-bf16 MFMA partial DFT (implies --transform dft)")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="1: replay each chunk of iterations of the batched solves from a hipGraph")
     ap.add_argument("--schedule", choices=["grid", "persistent"], default="grid",
                     help="workgroup schedule of the iteration kernels")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -238,6 +255,7 @@ def main():
                              "dft": mor.TRANSFORM_DFT}[args.transform]
     SOLVE_KW["precision"] = mor.PREC_BF16X3 if args.precision == "bf16x3" else mor.PREC_FP32
     SOLVE_KW["schedule"] = mor.SCHED_PERSISTENT if args.schedule == "persistent" else mor.SCHED_GRID
+    BATCH_KW["use_graph"] = args.graph
     dft = args.transform == "dft" or args.precision == "bf16x3"
     if args.precision == "bf16x3":
         TOL = 1e-5  # split-bf16 products set a residual floor near 1e-6
@@ -291,6 +309,7 @@ def main():
     achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9 if kd["ms"] > 0 else 0.0
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+            "timing": "HIP events around every launch of the kernel in an eager repetition of the timed steps",
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_us": kd["ms"] * 1e3 / max(kd["launches"], 1), "launches": kd["launches"]}
     if dft:
@@ -356,6 +375,7 @@ def main():
             "start": start,
             "fields": "FP32, FP64 residual and stress sums",
             "transform": args.transform, "precision": args.precision, "schedule": args.schedule,
+            "hipgraph": bool(args.graph),
         },
         "roofline": roof,
         "kernels": {k: {"ms": v["ms"], "launches": v["launches"],
