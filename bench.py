@@ -210,6 +210,60 @@ def train_network(mor, ph, ntrain, nslots, epochs, log):
     return net, info
 
 
+def other_configs(mor, ph):
+    """Throughput of the other configured workloads (one timed call each,
+    after one untimed call): the 4096-RVE uneven batch, 3D 128^3 with the FFT
+    and the split-bf16 MFMA DFT, and the 512^2 J2 load path."""
+    import torch
+
+    def timed(fn, reps=1):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, r
+
+    res = {}
+    gs = [synth.rsa_fibres(n, n, n / 32, n / 16, seed=seed, target_vf=0.35).g
+          for n, seed in ((128, 31), (256, 32), (384, 33))]
+    plans = [mor.Plan(g, int(math.ceil(0.05 * g.size))) for g in gs]
+    B = 4096
+    po = np.arange(B) % 3
+    ebs = synth.macro_strains(B, 3, 5e-3, seed=2026)
+    el, out = timed(lambda: mor.solve_multi(plans, po, ebs, ph, TOL), 2)
+    res["uneven_4096"] = {"workload": "4096 RVEs round robin over 128², 256², 384² fibre RVEs (vf 0.35), M = 5 %, "
+                                      "one mor_solve_multi call, residual 1e-6",
+                          "solves_per_s": B / el, "ms": el * 1e3, "mean_iterations": float(out.iterations.mean())}
+    del plans
+    g3 = synth.rsa_spheres(128, 128, 128, 8.0, 14.0, seed=7, target_vf=0.25).g
+    p3 = mor.Plan(g3, int(math.ceil(0.02 * g3.size)))
+    e3 = synth.macro_strains(8, 6, 1e-3, seed=3)
+    for name, kw, tol in (("fft", {}, 1e-6), ("dft_bf16x3", {"precision": mor.PREC_BF16X3}, 1e-5)):
+        el, out = timed(lambda: mor.solve(p3, e3, ph, tol, **kw))
+        res[f"cube128_{name}"] = {"workload": "128³ spheres (vf 0.25), M = 2 %, 8 macro strains in one call, "
+                                              f"residual {tol:g}",
+                                  "solves_per_s": 8 / el, "ms": el * 1e3,
+                                  "mean_iterations": float(out.iterations.mean())}
+    del p3
+    g2 = synth.rsa_fibres(512, 512, 20.0, 40.0, seed=2103, target_vf=0.40).g
+    p2 = mor.Plan(g2, int(math.ceil(0.05 * g2.size)))
+    path = np.stack([[0.02 * (k + 1) / 20, 0.0, 0.0] for k in range(20)])
+    lm, mm = synth.phase_lame(synth.MATRIX_E, synth.MATRIX_NU)
+    li, mi = synth.phase_lame(synth.FIBRE_E, synth.FIBRE_NU)
+    j2 = [mor.Phase(lm, mm, 0.25, 1.0, True), mor.Phase(li, mi)]
+
+    def run_path():
+        state = torch.zeros(5 * g2.size, dtype=torch.float32, device="cuda")
+        return mor.solve_path(p2, path, j2, TOL, state)
+
+    el, out = timed(run_path)
+    res["j2_512_path"] = {"workload": "512² J2 fibres (vf 0.4), M = 5 %, 20 load steps to 2 %, residual 1e-6",
+                          "ms_per_path": el * 1e3, "iterations": int(out.iterations.sum())}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +284,8 @@ def main():
                     help="1: replay each chunk of iterations of the batched solves from a hipGraph")
     ap.add_argument("--schedule", choices=["grid", "persistent"], default="grid",
                     help="workgroup schedule of the iteration kernels")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the timings of the other configured workloads")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -406,6 +462,8 @@ def main():
     if learned:
         line["training"] = learned["train"]
         line["eff_stress_rel_diff_learned_vs_cold"] = learned["eff_stress_rel_diff_vs_cold"]
+    if not args.no_other_configs:
+        line["other_configs"] = other_configs(mor, ph)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(gs, ebs, args.cpu_budget)
     print(json.dumps(line), flush=True)
