@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <map>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -544,11 +546,67 @@ bool size_ok(int64_t n) {
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
-  hipError_t alloc(size_t n) { return hipMalloc((void**)&p, std::max<size_t>(n, 1) * sizeof(T)); }
+  hipError_t alloc(struct PlanScratch& sc, size_t n);
 };
+
+// Temporaries of plan construction come from a per-device pool of device
+// blocks that are kept for reuse (plan construction is called once per
+// microstructure, often thousands of times; hipMalloc/hipFree pairs dominated
+// its cost).  A PlanScratch hands out blocks for one construction and gives
+// them back when it ends, after draining the stream.
+struct ScratchPool {
+  std::mutex mu;
+  std::multimap<size_t, void*> free;  // size -> block
+};
+
+ScratchPool& scratch_pool(int dev) {
+  static std::mutex mu;
+  static std::map<int, ScratchPool*> pools;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = pools.find(dev);
+  if (it != pools.end()) return *it->second;
+  ScratchPool* p = new ScratchPool();
+  pools[dev] = p;
+  return *p;
+}
+
+struct PlanScratch {
+  hipStream_t st;
+  int dev = 0;
+  std::vector<std::pair<size_t, void*>> held;
+  explicit PlanScratch(hipStream_t s) : st(s) { (void)hipGetDevice(&dev); }
+  hipError_t get(void** out, size_t bytes) {
+    bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    ScratchPool& pool = scratch_pool(dev);
+    {
+      std::lock_guard<std::mutex> lk(pool.mu);
+      auto it = pool.free.lower_bound(bytes);
+      if (it != pool.free.end() && it->first <= 4 * bytes) {
+        held.push_back(*it);
+        *out = it->second;
+        pool.free.erase(it);
+        return hipSuccess;
+      }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return e;
+    held.push_back({bytes, p});
+    *out = p;
+    return hipSuccess;
+  }
+  ~PlanScratch() {
+    (void)hipStreamSynchronize(st);  // queued kernels may still use the blocks
+    ScratchPool& pool = scratch_pool(dev);
+    std::lock_guard<std::mutex> lk(pool.mu);
+    for (auto& h : held) pool.free.insert(h);
+  }
+};
+
+template <typename T>
+hipError_t DevBuf<T>::alloc(PlanScratch& sc, size_t n) {
+  return sc.get((void**)&p, std::max<size_t>(n, 1) * sizeof(T));
+}
 
 }  // namespace
 
@@ -570,6 +628,7 @@ static void plan_free(mor_plan* p) {
 }
 
 static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t st) {
+  PlanScratch sc(st);  // declared first: released last, after the stream has drained
   const int nd = P->ndim;
   const int64_t N = P->N;
   Dims d{nd, P->n[0], P->n[1], nd == 3 ? P->n[2] : 1};
@@ -582,9 +641,9 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   DevBuf<cpx<double>> S;
   DevBuf<cpx<double>> tw64;
   DevBuf<unsigned long long> cnt;
-  MOR_HIP_TRY(S.alloc(N));
-  MOR_HIP_TRY(tw64.alloc(1024));
-  MOR_HIP_TRY(cnt.alloc(1));
+  MOR_HIP_TRY(S.alloc(sc, N));
+  MOR_HIP_TRY(tw64.alloc(sc, 1024));
+  MOR_HIP_TRY(cnt.alloc(sc, 1));
   MOR_HIP_TRY(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), st));
   k_g_to_cplx<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(P->d_g, S.p, N, cnt.p);
   MOR_LAUNCH_CHECK("g_to_cplx");
@@ -612,8 +671,8 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   while (npow2 < nreps) npow2 <<= 1;
   DevBuf<SortEl> el;
   DevBuf<unsigned int> nout;
-  MOR_HIP_TRY(el.alloc(npow2));
-  MOR_HIP_TRY(nout.alloc(1));
+  MOR_HIP_TRY(el.alloc(sc, npow2));
+  MOR_HIP_TRY(nout.alloc(sc, 1));
   MOR_HIP_TRY(hipMemsetAsync(nout.p, 0, sizeof(unsigned int), st));
   k_keys<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(S.p, d, N, cnt.p, el.p, nout.p);
   MOR_LAUNCH_CHECK("keys");
@@ -641,12 +700,12 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   // 4. selection
   DevBuf<uint8_t> mask;
   DevBuf<int64_t> mact;
-  MOR_HIP_TRY(mask.alloc(N));
-  MOR_HIP_TRY(mact.alloc(2));
+  MOR_HIP_TRY(mask.alloc(sc, N));
+  MOR_HIP_TRY(mact.alloc(sc, 2));
   MOR_HIP_TRY(hipMemsetAsync(mask.p, 0, N, st));
   MOR_HIP_TRY(hipMalloc((void**)&P->d_rank, (P->M + 1) * sizeof(int64_t)));
   DevBuf<int> pairof;
-  MOR_HIP_TRY(pairof.alloc(N));
+  MOR_HIP_TRY(pairof.alloc(sc, N));
   MOR_HIP_TRY(hipMemsetAsync(pairof.p, 0, N * sizeof(int), st));
   k_select<<<1, 1024, 0, st>>>(el.p, nreps, d, P->M, mask.p, P->d_rank, mact.p, pairof.p);
   MOR_LAUNCH_CHECK("select");
@@ -671,7 +730,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   {
     const int nchunk = (int)((N + kCompactChunk - 1) / kCompactChunk);
     DevBuf<int> ccount;
-    MOR_HIP_TRY(ccount.alloc(nchunk));
+    MOR_HIP_TRY(ccount.alloc(sc, nchunk));
     k_compact_count<<<nchunk, 256, 0, st>>>(mask.p, N, ccount.p);
     k_compact_scan<<<1, 1024, 0, st>>>(ccount.p, nchunk);
     k_compact_scatter<<<nchunk, 256, 0, st>>>(mask.p, N, ccount.p, P->d_sorted);
@@ -682,12 +741,12 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   const int nkh = nlen / 2 + 1;
   const int ncolall = nd == 2 ? nkh : nkh * P->n[1];
   DevBuf<int> cntc, lastcnt, colidx, col_kh, lastidx, meta;
-  MOR_HIP_TRY(cntc.alloc(ncolall));
-  MOR_HIP_TRY(lastcnt.alloc(nkh));
-  MOR_HIP_TRY(colidx.alloc(ncolall));
-  MOR_HIP_TRY(col_kh.alloc(ncolall));
-  MOR_HIP_TRY(lastidx.alloc(nkh));
-  MOR_HIP_TRY(meta.alloc(4));
+  MOR_HIP_TRY(cntc.alloc(sc, ncolall));
+  MOR_HIP_TRY(lastcnt.alloc(sc, nkh));
+  MOR_HIP_TRY(colidx.alloc(sc, ncolall));
+  MOR_HIP_TRY(col_kh.alloc(sc, ncolall));
+  MOR_HIP_TRY(lastidx.alloc(sc, nkh));
+  MOR_HIP_TRY(meta.alloc(sc, 4));
   MOR_HIP_TRY(hipMemsetAsync(lastcnt.p, 0, nkh * sizeof(int), st));
   // integer layout: col_k | col_last | col_off | last_k | last_off | coef_k0
   const int64_t cap_col = ncolall, cap_last = nkh, cap_coef = P->M_actual;
