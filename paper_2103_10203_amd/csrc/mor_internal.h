@@ -6,6 +6,8 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/mor.h"
 #include "fft_lds.h"
@@ -71,6 +73,7 @@ struct PlanDev {
 
 struct mor_plan {
   uint64_t uid = 0;  // unique per plan in the process (caches key on it, not on the address)
+  std::vector<std::pair<size_t, void*>> blocks;  // device blocks owned by the plan (pooled)
   int ndim = 0;
   int n[3] = {1, 1, 1};
   int64_t N = 0, M = 0, M_actual = 0, count = 0;

@@ -608,22 +608,45 @@ hipError_t DevBuf<T>::alloc(PlanScratch& sc, size_t n) {
   return sc.get((void**)&p, std::max<size_t>(n, 1) * sizeof(T));
 }
 
+// A device block owned by the plan, from the same pool; plan_free gives the
+// plan's blocks back once the device has drained.
+template <typename T>
+hipError_t plan_alloc(mor_plan* P, T** out, size_t bytes) {
+  bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+  ScratchPool& pool = scratch_pool(P->device);
+  {
+    std::lock_guard<std::mutex> lk(pool.mu);
+    auto it = pool.free.lower_bound(bytes);
+    if (it != pool.free.end() && it->first <= 4 * bytes) {
+      P->blocks.push_back(*it);
+      *out = (T*)it->second;
+      pool.free.erase(it);
+      return hipSuccess;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return e;
+  P->blocks.push_back({bytes, p});
+  *out = (T*)p;
+  return hipSuccess;
+}
+
 }  // namespace
 
 static void plan_free(mor_plan* p) {
   if (!p) return;
-  (void)hipFree(p->d_g);
-  (void)hipFree(p->d_sorted);
-  (void)hipFree(p->d_rank);
-  (void)hipFree(p->d_coef_lin);
-  (void)hipFree(p->d_ints);
-  (void)hipFree(p->d_coef_n);
-  (void)hipFree(p->d_coef_flag);
-  (void)hipFree(p->d_tw);
-  (void)hipFree(p->d_dev);
-  (void)hipFree(p->d_slot_rep);
-  (void)hipFree(p->d_slot_ghat);
-  (void)hipFree(p->d_coef_slot);
+  if (!p->blocks.empty()) {
+    // the blocks go back to the pool: nothing queued may still use them
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != p->device) (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    if (cur != p->device) (void)hipSetDevice(cur);
+    ScratchPool& pool = scratch_pool(p->device);
+    std::lock_guard<std::mutex> lk(pool.mu);
+    for (auto& b : p->blocks) pool.free.insert(b);
+  }
   delete p;
 }
 
@@ -634,7 +657,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   Dims d{nd, P->n[0], P->n[1], nd == 3 ? P->n[2] : 1};
   const int nlen = nd == 2 ? P->n[1] : P->n[2];
 
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_g, N));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_g, N));
   MOR_HIP_TRY(hipMemcpyAsync(P->d_g, phase_map, N, hipMemcpyHostToDevice, st));
 
   // 1. FP64 spectrum
@@ -703,7 +726,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   MOR_HIP_TRY(mask.alloc(sc, N));
   MOR_HIP_TRY(mact.alloc(sc, 2));
   MOR_HIP_TRY(hipMemsetAsync(mask.p, 0, N, st));
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_rank, (P->M + 1) * sizeof(int64_t)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_rank, (P->M + 1) * sizeof(int64_t)));
   DevBuf<int> pairof;
   MOR_HIP_TRY(pairof.alloc(sc, N));
   MOR_HIP_TRY(hipMemsetAsync(pairof.p, 0, N * sizeof(int), st));
@@ -717,8 +740,8 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   P->nslots = hm[1] - 1;
 
   // slot tables of the warm-start network
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_slot_rep, std::max<int64_t>(P->nslots, 1) * sizeof(int64_t)));
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_slot_ghat, std::max<int64_t>(P->nslots, 1) * sizeof(cpx<float>)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_slot_rep, std::max<int64_t>(P->nslots, 1) * sizeof(int64_t)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_slot_ghat, std::max<int64_t>(P->nslots, 1) * sizeof(cpx<float>)));
   if (P->nslots > 0) {
     k_slots<<<(unsigned)((P->nslots + 255) / 256), 256, 0, st>>>(el.p, P->nslots, S.p, cnt.p, P->d_slot_rep,
                                                                  P->d_slot_ghat);
@@ -726,7 +749,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   }
 
   // 5. sorted pattern
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_sorted, P->M_actual * sizeof(int64_t)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_sorted, P->M_actual * sizeof(int64_t)));
   {
     const int nchunk = (int)((N + kCompactChunk - 1) / kCompactChunk);
     DevBuf<int> ccount;
@@ -751,7 +774,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   // integer layout: col_k | col_last | col_off | last_k | last_off | coef_k0
   const int64_t cap_col = ncolall, cap_last = nkh, cap_coef = P->M_actual;
   const int64_t nint = cap_col + cap_col + (cap_col + 1) + cap_last + (cap_last + 1) + cap_coef;
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_ints, nint * sizeof(int32_t)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_ints, nint * sizeof(int32_t)));
   int32_t* col_k = P->d_ints;
   int32_t* col_last = col_k + cap_col;
   int32_t* col_off = col_last + cap_col;
@@ -769,10 +792,10 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   const int ncol = hmeta[0], nlast = hmeta[1], ncoef = hmeta[2];
   k_tab_groups<<<(ncol + 1 + 255) / 256, 256, 0, st>>>(col_kh.p, lastidx.p, ncol, nlast, col_last, last_off);
   MOR_LAUNCH_CHECK("tab_groups");
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_lin, std::max(ncoef, 1) * sizeof(int64_t)));
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_n, std::max(ncoef, 1) * 3 * sizeof(float)));
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_flag, std::max(ncoef, 1)));
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_coef_slot, std::max(ncoef, 1) * sizeof(int)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_lin, std::max(ncoef, 1) * sizeof(int64_t)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_n, std::max(ncoef, 1) * 3 * sizeof(float)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_flag, std::max(ncoef, 1)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_slot, std::max(ncoef, 1) * sizeof(int)));
   k_tab_fill<<<(ncolall + 3) / 4, 256, 0, st>>>(mask.p, d, ncolall, colidx.p, col_off, P->gamma_kind, coef_k0,
                                                     P->d_coef_lin, P->d_coef_n, P->d_coef_flag, pairof.p,
                                                     P->d_coef_slot);
@@ -781,7 +804,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   // twiddles for the solver transforms
   const int n0 = P->n[0], n1 = P->n[1];
   const int ntw = n0 + n1 + nlen / 2 + nlen;
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_tw, ntw * sizeof(cpx<float>)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_tw, ntw * sizeof(cpx<float>)));
   cpx<float>* tw0 = P->d_tw;
   cpx<float>* tw1 = tw0 + n0;
   cpx<float>* twh = tw1 + n1;
@@ -821,7 +844,7 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   fft_make_desc(n0, &v.fd0);
   fft_make_desc(n1, &v.fd1);
   fft_make_desc(nlen / 2, &v.fdh);
-  MOR_HIP_TRY(hipMalloc((void**)&P->d_dev, sizeof(PlanDev)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_dev, sizeof(PlanDev)));
   MOR_HIP_TRY(hipMemcpyAsync(P->d_dev, &v, sizeof(PlanDev), hipMemcpyHostToDevice, st));
   MOR_HIP_TRY(hipStreamSynchronize(st));
   return MOR_OK;
