@@ -535,6 +535,33 @@ void col_persist(SolveCtx& cx, Group& g) {
   }
 }
 
+// 3D axis-1 transform of a group: specialised kernels for n1 = 32/64/128,
+// the generic runtime-radix kernel otherwise.
+bool has_fast_mid(int n1) { return n1 == 32 || n1 == 64 || n1 == 128; }
+
+template <int N1, int DIR>
+void go_mid_fast(SolveCtx& cx, Group& g, int check_active) {
+  dim3 gm((g.n0 + MidCfg<N1>::XB - 1) / MidCfg<N1>::XB, g.nlast_max, (unsigned)g.rves.size());
+  k_mid_fast<6, N1, DIR><<<gm, mid_threads<6, N1>(), mid_lds_bytes<6, N1>(), cx.st>>>(
+      cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, check_active);
+}
+
+template <int DIR>
+void launch_mid(SolveCtx& cx, Group& g, int check_active) {
+  if (has_fast_mid(g.n1)) {
+    switch (g.n1) {
+      case 32: go_mid_fast<32, DIR>(cx, g, check_active); break;
+      case 64: go_mid_fast<64, DIR>(cx, g, check_active); break;
+      default: go_mid_fast<128, DIR>(cx, g, check_active); break;
+    }
+  } else {
+    const size_t shm = (size_t)(g.n1 + 2 * 6 * g.xb * g.n1) * sizeof(cpx<float>);
+    dim3 gm((g.n0 + g.xb - 1) / g.xb, g.nlast_max, (unsigned)g.rves.size());
+    k_mid<6, DIR><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb,
+                                           check_active);
+  }
+}
+
 template <int C, int MODE>
 void col_fast(SolveCtx& cx, Group& g, const cpx<float>* warm) {
   if constexpr (C == 3) {
@@ -565,10 +592,8 @@ mor_status launch_init(SolveCtx& cx, Group& g, const cpx<float>* warm) {
   MOR_LAUNCH_CHECK("col(init)");
   ev_end(cx, PK_INIT, a);
   if (C == 6) {
-    const size_t shm = (size_t)(g.n1 + 2 * C * g.xb * g.n1) * sizeof(cpx<float>);
-    dim3 gm((g.n0 + g.xb - 1) / g.xb, g.nlast_max, (unsigned)g.rves.size());
     ev_begin(cx, PK_MIDI, &a);
-    k_mid<C, +1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 0);
+    launch_mid<+1>(cx, g, 0);
     MOR_LAUNCH_CHECK("mid(inv)");
     ev_end(cx, PK_MIDI, a);
   }
@@ -630,11 +655,9 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
                                                       cx.d_jstate, nullptr, nullptr, nullptr, g.rb);
   MOR_LAUNCH_CHECK("row");
   ev_end(cx, PK_ROW, a);
-  const size_t shm = (size_t)(g.n1 + 2 * C * g.xb * g.n1) * sizeof(cpx<float>);
-  dim3 gm((g.n0 + g.xb - 1) / g.xb, g.nlast_max, (unsigned)g.rves.size());
   if (C == 6) {
     ev_begin(cx, PK_MIDF, &a);
-    k_mid<C, -1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 1);
+    launch_mid<-1>(cx, g, 1);
     MOR_LAUNCH_CHECK("mid(fwd)");
     ev_end(cx, PK_MIDF, a);
   }
@@ -652,7 +675,7 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
   ev_end(cx, PK_COL, a);
   if (C == 6) {
     ev_begin(cx, PK_MIDI, &a);
-    k_mid<C, +1><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, g.xb, 1);
+    launch_mid<+1>(cx, g, 1);
     MOR_LAUNCH_CHECK("mid(inv)");
     ev_end(cx, PK_MIDI, a);
   }
