@@ -130,7 +130,7 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
   static_assert(NT % RB == 0, "row block divides the workgroup");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ int lk[NH + 1];    // last-axis frequency of spectrum entry j
-  __shared__ int kpos[NH + 1];  // entry j of last-axis frequency k, -1 if not sampled
+  __shared__ int kofs[NH + 1];  // j * rows for the entry j of last-axis frequency k, -1 if not sampled
   if (MODE == MODE_ITER && !st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
   const int rows = P.rows;
@@ -143,10 +143,12 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
   cpx<float>* buf = T + row_tw_len<NH>();  // RB sequences, one component
   const int nlast = P.nlast;
   for (int t = tid; t < L; t += NT) T[pad16(t)] = P.rtw[t];
-  for (int t = tid; t <= NH; t += NT) kpos[t] = -1;
+  for (int t = tid; t <= NH; t += NT) kofs[t] = -1;
   for (int t = tid; t < nlast; t += NT) lk[t] = P.last_k[t];
   __syncthreads();
-  for (int t = tid; t < nlast; t += NT) kpos[lk[t]] = t;
+  // nlast * rows < 2^31 for every admissible grid (n <= 1024 per axis), so
+  // the offsets inside one component fit 32 bits
+  for (int t = tid; t < nlast; t += NT) kofs[lk[t]] = t * rows;
   __syncthreads();
   cpx<float>* Y = Yl + off.yl[b];
   const int64_t cstride = (int64_t)nlast * rows;
@@ -174,9 +176,9 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
       xb[u] = {0.f, 0.f};
       if (t < GT && rlive) {
         const int k = t / RB;
-        const int ja = kpos[k], jb = kpos[NH - k];
-        if (ja >= 0) xa[u] = ysrc[(int64_t)ja * rows];
-        if (jb >= 0) xb[u] = ysrc[(int64_t)jb * rows];
+        const int oa = kofs[k], ob = kofs[NH - k];
+        if (oa >= 0) xa[u] = ysrc[oa];
+        if (ob >= 0) xb[u] = ysrc[ob];
       }
     }
   };
@@ -201,11 +203,7 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
         const cpx<float> a = cadd(Xk, cconj(Xm));
         const cpx<float> d = cmul(csub(Xk, cconj(Xm)), cconj(T[pad16(k)]));
         x[fftr::padp<PS>(k)] = {a.x - d.y, a.y + d.x};
-        if (k != 0 && 2 * k != NH) {
-          const cpx<float> a2 = cadd(Xm, cconj(Xk));
-          const cpx<float> d2 = cmul(csub(Xm, cconj(Xk)), cconj(T[pad16(NH - k)]));
-          x[fftr::padp<PS>(NH - k)] = {a2.x - d2.y, a2.y + d2.x};
-        }
+        if (k != 0 && 2 * k != NH) x[fftr::padp<PS>(NH - k)] = {a.x + d.y, d.x - a.y};
       }
     }
     if (c + 1 < C) gather(c + 1);
