@@ -103,6 +103,7 @@ struct MatDev {
   float lam[2], mu[2], sy[2], H[2];
   int32_t plastic[2];
   float lam0, mu0;
+  float dl[2], dm[2];  // lam[p] - lam0 and 2 (mu[p] - mu0), rounded as the device would
   float g_inv_mu0;  // 1/mu0
   float g_k;        // (lam0+mu0)/(mu0 (lam0+2 mu0))
 };

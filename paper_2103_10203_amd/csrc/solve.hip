@@ -328,6 +328,10 @@ MatDev make_mat(const mor_phase* ph) {
   const double mu0 = 0.5 * (ph[0].mu + ph[1].mu);
   m.lam0 = (float)lam0;
   m.mu0 = (float)mu0;
+  for (int p = 0; p < 2; ++p) {
+    m.dl[p] = m.lam[p] - m.lam0;
+    m.dm[p] = 2.f * (m.mu[p] - m.mu0);
+  }
   m.g_inv_mu0 = (float)(1.0 / mu0);
   m.g_k = (float)((lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0)));
   return m;

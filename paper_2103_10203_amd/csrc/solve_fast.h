@@ -101,6 +101,21 @@ constexpr size_t row_lds_bytes() {
          sizeof(cpx<float>);
 }
 
+// Raw buffer access to one strain component of an RVE (wave-uniform base,
+// byte size below 2^31).  A buffer load whose offset lies at or beyond the
+// resource's size is range-checked by the hardware: it touches no memory and
+// returns zero.  kOutOfRange is such an offset for every resource built here.
+constexpr uint32_t kOutOfRange = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t comp_rsrc(const cpx<float>* base, uint32_t bytes) {
+  // stride 0 (raw buffer); the fourth word selects 32-bit data for the gfx9 family
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<cpx<float>*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ cpx<float> load_or_zero(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off) {
+  typedef int i32x2 __attribute__((ext_vector_type(2)));
+  const i32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)byte_off, 0, 0);
+  return {__int_as_float(v.x), __int_as_float(v.y)};
+}
+
 // threadIdx.x, re-read per work item of a persistent loop behind an empty asm
 // statement, so that thread-index arithmetic is not hoisted out of the loop
 // (hoisting keeps it live across the whole item and doubles the registers).
@@ -130,7 +145,8 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
   static_assert(NT % RB == 0, "row block divides the workgroup");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ int lk[NH + 1];    // last-axis frequency of spectrum entry j
-  __shared__ int kofs[NH + 1];  // j * rows for the entry j of last-axis frequency k, -1 if not sampled
+  __shared__ uint32_t kofs[NH + 1];  // byte offset j * rows * 8 of the entry j of last-axis frequency k,
+                                    // kOutOfRange if k is not sampled
   if (MODE == MODE_ITER && !st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
   const int rows = P.rows;
@@ -143,12 +159,13 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
   cpx<float>* buf = T + row_tw_len<NH>();  // RB sequences, one component
   const int nlast = P.nlast;
   for (int t = tid; t < L; t += NT) T[pad16(t)] = P.rtw[t];
-  for (int t = tid; t <= NH; t += NT) kofs[t] = -1;
+  for (int t = tid; t <= NH; t += NT) kofs[t] = kOutOfRange;
   for (int t = tid; t < nlast; t += NT) lk[t] = P.last_k[t];
   __syncthreads();
-  // nlast * rows < 2^31 for every admissible grid (n <= 1024 per axis), so
-  // the offsets inside one component fit 32 bits
-  for (int t = tid; t < nlast; t += NT) kofs[lk[t]] = t * rows;
+  // one component spans nlast * rows * 8 < 2^31 bytes for every grid this
+  // kernel is built for (nlast <= NH + 1 <= 257 with rows <= 1024 in 2D,
+  // nlast <= 129 with rows <= 1024^2 in 3D)
+  for (int t = tid; t < nlast; t += NT) kofs[lk[t]] = (uint32_t)t * (uint32_t)rows * 8u;
   __syncthreads();
   cpx<float>* Y = Yl + off.yl[b];
   const int64_t cstride = (int64_t)nlast * rows;
@@ -167,18 +184,20 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
   constexpr int GT = KH * RB;             // gather items per component
   constexpr int GU = (GT + NT - 1) / NT;  // items per thread
   cpx<float> xa[GU], xb[GU];
+  // Unsampled frequencies read zero through the buffer range check, so the
+  // gather has no branches.  Rows past the end of the RVE (rg >= nr) read
+  // entries of the next frequency or zero; their results are never stored.
+  const uint32_t rowb = (uint32_t)(r0 + rg) * 8u;
+  const uint32_t cbytes = (uint32_t)cstride * 8u;
   auto gather = [&](int c) {
-    const cpx<float>* ysrc = Y + (int64_t)c * cstride + r0 + rg;
+    const __amdgpu_buffer_rsrc_t rs = comp_rsrc(Y + (int64_t)c * cstride, cbytes);
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
       const int t = tid + u * NT;  // t % RB == rg
-      xa[u] = {0.f, 0.f};
-      xb[u] = {0.f, 0.f};
-      if (t < GT && rlive) {
+      if (GT % NT == 0 || t < GT) {
         const int k = t / RB;
-        const int oa = kofs[k], ob = kofs[NH - k];
-        if (oa >= 0) xa[u] = ysrc[oa];
-        if (ob >= 0) xb[u] = ysrc[ob];
+        xa[u] = load_or_zero(rs, kofs[k] + rowb);
+        xb[u] = load_or_zero(rs, kofs[NH - k] + rowb);
       }
     }
   };

@@ -47,12 +47,15 @@ template <int C, int MAT>
 __device__ __forceinline__ void constitutive(const float* e, int ph, const MatDev& m, const float* stin, float* tau,
                                              float* sig, float* stout) {
   constexpr int ND = Comp<C>::NDIAG;
-  float tr = 0.f;
+  float tr = e[0];
 #pragma unroll
-  for (int i = 0; i < ND; ++i) tr += e[i];
+  for (int i = 1; i < ND; ++i) tr += e[i];
+  // phase 0 or 1 (checked at plan creation): selects, not indexed loads of
+  // the parameter block, and the phase differences are loop invariants
+  const bool p1 = ph != 0;
   if (MAT == MAT_HOOKE) {
-    const float lam = m.lam[ph], mu = m.mu[ph];
-    const float dl = lam - m.lam0, dm = 2.f * (mu - m.mu0);
+    const float lam = p1 ? m.lam[1] : m.lam[0], mu = p1 ? m.mu[1] : m.mu[0];
+    const float dl = p1 ? m.dl[1] : m.dl[0], dm = p1 ? m.dm[1] : m.dm[0];
 #pragma unroll
     for (int i = 0; i < C; ++i) tau[i] = (i < ND ? dl * tr : 0.f) + dm * e[i];
     if (sig) {
@@ -72,7 +75,7 @@ __device__ __forceinline__ void constitutive(const float* e, int ph, const MatDe
       for (int i = 0; i < 6; ++i) { E[i] = e[i]; EP[i] = stin[i]; }
       alpha = stin[6];
     }
-    const float lam = m.lam[ph], mu = m.mu[ph];
+    const float lam = p1 ? m.lam[1] : m.lam[0], mu = p1 ? m.mu[1] : m.mu[0];
     float ee[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) ee[i] = E[i] - EP[i];
@@ -85,11 +88,11 @@ __device__ __forceinline__ void constitutive(const float* e, int ph, const MatDe
     }
     const float ns = sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2] + 2.f * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
     const float q = 1.22474487139158905f * ns;
-    const float H = m.H[ph];
-    const float f = q - (m.sy[ph] + H * alpha);
+    const float H = p1 ? m.H[1] : m.H[0];
+    const float f = q - ((p1 ? m.sy[1] : m.sy[0]) + H * alpha);
     float sg[6];
     float dg = 0.f, fac = 0.f;
-    if (m.plastic[ph] && f > 0.f) {
+    if ((p1 ? m.plastic[1] : m.plastic[0]) && f > 0.f) {
       dg = f / (3.f * mu + H);
       fac = 1.22474487139158905f * dg / ns;
     }
