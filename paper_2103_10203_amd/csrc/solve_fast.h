@@ -431,6 +431,8 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
   static_assert(NT % 64 == 0, "workgroups are whole wavefronts");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ int coff[CB + 1];
+  __shared__ double cwt[CB];  // Parseval weight of each column of the block (1 or 2)
+  __shared__ uint32_t pmask[CB][N0 / 32];  // pattern frequencies k0 of each column of the block
   if (MODE == MODE_ITER && !st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
   const int ncol = P.ncol;
@@ -443,6 +445,11 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
   cpx<float>* buf = tw + pad16(N0 - 1) + 1;
   for (int t = tid; t < N0; t += NT) tw[pad16(t)] = P.tw0[t];
   if (tid <= CB) coff[tid] = P.col_off[j0 + min(tid, ncb)];
+  for (int t = tid; t < CB * (N0 / 32); t += NT) (&pmask[0][0])[t] = 0u;
+  if (MODE == MODE_ITER && tid < ncb) {
+    const int kl = P.last_k[P.col_last[j0 + tid]];
+    cwt[tid] = (kl == 0 || 2 * kl == P.nlen) ? 1.0 : 2.0;
+  }
   // prefetch this thread's first pattern entry (its loads overlap the FFT)
   const int ncoef = P.ncoef;
   cpx<float>* co = coef + off.coef[b];
@@ -483,21 +490,19 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
     __syncthreads();
   }
   // step c): Green operator on the block's pattern entries.  A thread
-  // handles at most EPT entries; their results stay in registers until the
-  // buffer has been read by every thread and cleared.
+  // handles at most EPT entries.  Only the thread of an entry reads its
+  // positions of tau^, so it overwrites them in place with the new
+  // coefficients; the positions outside the pattern are cleared afterwards
+  // (the entries mark theirs in pmask).
   constexpr int EPT = (CB * N0 + NT - 1) / NT;
   const float invN = P.inv_N;
   double dsum = 0.0;
-  cpx<float> res[EPT][C];
-  int rpos[EPT];
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
-    rpos[u] = -1;
     const int e = ebeg + tid + u * NT;
     if (e >= eend) continue;
     int jj = 0;
     while (jj + 1 < ncb && e >= coff[jj + 1]) ++jj;
-    const int j = j0 + jj;
     const bool first = u == 0;
     const int k0 = first ? pk0 : P.coef_k0[e];
     const uint8_t fl = first ? pfl : P.coef_flag[e];
@@ -550,8 +555,7 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
       }
     }
     if (MODE == MODE_ITER) {
-      const int kl = P.last_k[P.col_last[j]];
-      const double wcol = (kl == 0 || 2 * kl == P.nlen) ? 1.0 : 2.0;
+      const double wcol = cwt[jj];
       double d2 = 0.0;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
@@ -561,22 +565,21 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
       }
       dsum += wcol * d2;
     }
+    const int pos = jj * SS + pad16(k0);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       co[(int64_t)c * ncoef + e] = {nr_[c], ni_[c]};
-      res[u][c] = {nr_[c] * invN, ni_[c] * invN};
+      buf[c * CB * SS + pos] = {nr_[c] * invN, ni_[c] * invN};
     }
-    rpos[u] = jj * SS + pad16(k0);
+    atomicOr(&pmask[jj][k0 >> 5], 1u << (k0 & 31));
   }
-  __syncthreads();  // every read of tau^ is done
-  for (int t = tid; t < NSEQ * SS; t += NT) buf[t] = {0.f, 0.f};
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < EPT; ++u)
-    if (rpos[u] >= 0) {
-#pragma unroll
-      for (int c = 0; c < C; ++c) buf[c * CB * SS + rpos[u]] = res[u][c];
-    }
+  __syncthreads();  // the pattern marks are complete
+  // clear the other positions of every sequence (pad slots are never read)
+  for (int t = tid; t < NSEQ * N0; t += NT) {
+    const int sq = t / N0, k = t % N0;
+    const int jj = sq % CB;
+    if (!((pmask[jj][k >> 5] >> (k & 31)) & 1u)) buf[sq * SS + pad16(k)] = {0.f, 0.f};
+  }
   __syncthreads();
   // step d), axis 0: inverse passes, the last one straight to global memory
   fftr::lds_passes<N0, +1, 1, NSEQ, SS, NT, 1>(buf, tw, tid, typename fftr::Rev<typename Cfg::FA, RList<>>::type{});
