@@ -685,8 +685,8 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
   }
   // the stop decision comes last: every stage of this iteration has run
   const int nrv = (int)g.rves.size();
-  k_converge<<<(nrv + 255) / 256, 256, 0, cx.st>>>(cx.d_plans, g.d_list, nrv, cx.d_st, cx.d_part, cx.off, g.cb,
-                                                   cx.d_active);
+  k_converge<<<(nrv + kConvergeRvesPerBlock - 1) / kConvergeRvesPerBlock, 256, 0, cx.st>>>(
+      cx.d_plans, g.d_list, nrv, cx.d_st, cx.d_part, cx.off, g.cb, cx.d_active);
   MOR_LAUNCH_CHECK("converge");
   return MOR_OK;
 }

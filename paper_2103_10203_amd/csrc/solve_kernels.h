@@ -534,20 +534,27 @@ __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, 
   }
 }
 
-// Convergence decision after a column pass (one thread per RVE): FP64 sum of
-// the column blocks' squared coefficient changes in a fixed order, Parseval
-// residual r = sqrt(sum) / (N ||eps_bar||_F), and the stop rules.
-__global__ void k_converge(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, int nrve,
-                           RveState* __restrict__ st, const double* __restrict__ part, Offs off, int cb,
-                           unsigned int* __restrict__ active_count) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrve) return;
+// Convergence decision after a column pass (one wavefront per RVE, 4 per
+// workgroup): FP64 sum of the column blocks' squared coefficient changes in a
+// fixed order (lane-strided partial sums, then a butterfly over the lanes),
+// Parseval residual r = sqrt(sum) / (N ||eps_bar||_F), and the stop rules.
+constexpr int kConvergeRvesPerBlock = 4;
+__global__ __launch_bounds__(256) void k_converge(const PlanDev* __restrict__ plans,
+                                                  const int* __restrict__ rve_list, int nrve,
+                                                  RveState* __restrict__ st, const double* __restrict__ part,
+                                                  Offs off, int cb, unsigned int* __restrict__ active_count) {
+  const int i = blockIdx.x * kConvergeRvesPerBlock + (int)(threadIdx.x >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  if (i >= nrve) return;  // uniform over the wavefront
   const int b = rve_list[i];
   RveState& S = st[b];
   if (!S.active) return;
   const int nblk = (plans[S.plan].ncol + cb - 1) / cb;
   double sum = 0.0;
-  for (int q = 0; q < nblk; ++q) sum += part[off.part[b] + q];
+  for (int q = lane; q < nblk; q += 64) sum += part[off.part[b] + q];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if (lane != 0) return;
   const double r = sqrt(sum) / S.denom;
   const int it = S.iters + 1;
   S.iters = it;
