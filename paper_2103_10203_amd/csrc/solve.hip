@@ -412,14 +412,15 @@ void go_col_fast_v(SolveCtx& cx, Group& g, const cpx<float>* warm) {
 
 template <int C, int N0, int MODE>
 void go_col_fast(SolveCtx& cx, Group& g, const cpx<float>* warm) {
-  static_assert(ColVar<C, N0>::count <= 6, "dispatch covers six variants");
+  static_assert(ColVar<C, N0>::count <= 7, "dispatch covers seven variants");
   switch (g.cvar) {
     case 0: go_col_fast_v<C, N0, 0, MODE>(cx, g, warm); break;
     case 1: go_col_fast_v<C, N0, 1, MODE>(cx, g, warm); break;
     case 2: go_col_fast_v<C, N0, 2, MODE>(cx, g, warm); break;
     case 3: go_col_fast_v<C, N0, 3, MODE>(cx, g, warm); break;
     case 4: go_col_fast_v<C, N0, 4, MODE>(cx, g, warm); break;
-    default: go_col_fast_v<C, N0, 5, MODE>(cx, g, warm); break;
+    case 5: go_col_fast_v<C, N0, 5, MODE>(cx, g, warm); break;
+    default: go_col_fast_v<C, N0, 6, MODE>(cx, g, warm); break;
   }
 }
 
@@ -519,7 +520,8 @@ void go_col_persist(SolveCtx& cx, Group& g) {
     case 2: go_col_persist_v<C, N0, 2>(cx, g); break;
     case 3: go_col_persist_v<C, N0, 3>(cx, g); break;
     case 4: go_col_persist_v<C, N0, 4>(cx, g); break;
-    default: go_col_persist_v<C, N0, 5>(cx, g); break;
+    case 5: go_col_persist_v<C, N0, 5>(cx, g); break;
+    default: go_col_persist_v<C, N0, 6>(cx, g); break;
   }
 }
 

@@ -385,13 +385,14 @@ template <> struct ColCfg<3, 128, 0> { static constexpr int RF = 8,  CB = 4; usi
 template <> struct ColCfg<3, 128, 1> { static constexpr int RF = 16, CB = 8; using FA = RList<8>; };
 template <> struct ColCfg<3, 128, 2> { static constexpr int RF = 4,  CB = 2; using FA = RList<8, 4>; };
 template <> struct ColVar<3, 128> { static constexpr int count = 3; };
-template <> struct ColCfg<3, 256, 0> { static constexpr int RF = 8,  CB = 2; using FA = RList<8, 4>; };
+template <> struct ColCfg<3, 256, 0> { static constexpr int RF = 8,  CB = 2, W = 7; using FA = RList<8, 4>; };
 template <> struct ColCfg<3, 256, 1> { static constexpr int RF = 4,  CB = 1; using FA = RList<8, 8>; };
 template <> struct ColCfg<3, 256, 2> { static constexpr int RF = 16, CB = 4; using FA = RList<16>; };
 template <> struct ColCfg<3, 256, 3> { static constexpr int RF = 8,  CB = 4; using FA = RList<8, 4>; };
 template <> struct ColCfg<3, 256, 4> { static constexpr int RF = 8,  CB = 2; using FA = RList<4, 8>; };
 template <> struct ColCfg<3, 256, 5> { static constexpr int RF = 16, CB = 8; using FA = RList<16>; };
-template <> struct ColVar<3, 256> { static constexpr int count = 6; };
+template <> struct ColCfg<3, 256, 6> { static constexpr int RF = 8,  CB = 2, W = 8; using FA = RList<8, 4>; };
+template <> struct ColVar<3, 256> { static constexpr int count = 7; };
 template <> struct ColCfg<3, 384, 0> { static constexpr int RF = 6,  CB = 1; using FA = RList<8, 8>; };
 template <> struct ColCfg<3, 512, 0> { static constexpr int RF = 8,  CB = 1; using FA = RList<8, 8>; };
 template <> struct ColCfg<3, 512, 1> { static constexpr int RF = 16, CB = 4; using FA = RList<8, 4>; };
@@ -401,6 +402,18 @@ template <> struct ColCfg<6, 64, 0>  { static constexpr int RF = 8,  CB = 4; usi
 template <> struct ColCfg<6, 128, 0> { static constexpr int RF = 16, CB = 4; using FA = RList<8>; };
 template <> struct ColCfg<6, 128, 1> { static constexpr int RF = 8,  CB = 2; using FA = RList<4, 4>; };
 template <> struct ColVar<6, 128> { static constexpr int count = 2; };
+
+// Minimum waves per SIMD a variant asks the register allocator for (1: no
+// constraint; set where it fits the registers without spills and measured
+// faster).
+template <typename Cfg, typename = void>
+struct WavesOf {
+  static constexpr int v = 1;
+};
+template <typename Cfg>
+struct WavesOf<Cfg, decltype((void)Cfg::W)> {
+  static constexpr int v = Cfg::W;
+};
 
 template <int C, int N0, int V>
 constexpr int col_threads() {
@@ -603,7 +616,7 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
 }
 
 template <int C, int N0, int V, int MODE>
-__global__ __launch_bounds__((col_threads<C, N0, V>())) void k_col_fast(
+__global__ __launch_bounds__((col_threads<C, N0, V>())) __attribute__((amdgpu_waves_per_eu(WavesOf<ColCfg<C, N0, V>>::v))) void k_col_fast(
     const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
     const double* __restrict__ ebar, cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
     const cpx<float>* __restrict__ warm, Offs off, double* __restrict__ part, MatDev mat) {
