@@ -378,10 +378,10 @@ template <int C, int N0>
 struct ColVar {
   static constexpr int count = 1;
 };
-template <> struct ColCfg<3, 64, 0>  { static constexpr int RF = 8,  CB = 8; using FA = RList<8>; };
+template <> struct ColCfg<3, 64, 0>  { static constexpr int RF = 8,  CB = 8, W = 8; using FA = RList<8>; };
 template <> struct ColCfg<3, 64, 1>  { static constexpr int RF = 4,  CB = 4; using FA = RList<4, 4>; };
 template <> struct ColVar<3, 64> { static constexpr int count = 2; };
-template <> struct ColCfg<3, 128, 0> { static constexpr int RF = 8,  CB = 4; using FA = RList<4, 4>; };
+template <> struct ColCfg<3, 128, 0> { static constexpr int RF = 8,  CB = 4, W = 8; using FA = RList<4, 4>; };
 template <> struct ColCfg<3, 128, 1> { static constexpr int RF = 16, CB = 8; using FA = RList<8>; };
 template <> struct ColCfg<3, 128, 2> { static constexpr int RF = 4,  CB = 2; using FA = RList<8, 4>; };
 template <> struct ColVar<3, 128> { static constexpr int count = 3; };
@@ -398,7 +398,7 @@ template <> struct ColCfg<3, 512, 0> { static constexpr int RF = 8,  CB = 1; usi
 template <> struct ColCfg<3, 512, 1> { static constexpr int RF = 16, CB = 4; using FA = RList<8, 4>; };
 template <> struct ColCfg<3, 512, 2> { static constexpr int RF = 8,  CB = 2; using FA = RList<8, 8>; };
 template <> struct ColVar<3, 512> { static constexpr int count = 3; };
-template <> struct ColCfg<6, 64, 0>  { static constexpr int RF = 8,  CB = 4; using FA = RList<8>; };
+template <> struct ColCfg<6, 64, 0>  { static constexpr int RF = 8,  CB = 4, W = 6; using FA = RList<8>; };
 template <> struct ColCfg<6, 128, 0> { static constexpr int RF = 16, CB = 4; using FA = RList<8>; };
 template <> struct ColCfg<6, 128, 1> { static constexpr int RF = 8,  CB = 2; using FA = RList<4, 4>; };
 template <> struct ColVar<6, 128> { static constexpr int count = 2; };
