@@ -111,6 +111,23 @@ def solve_source_hash():
     return h.hexdigest()[:16]
 
 
+VALU_FILE = os.path.join(ROOT, "profiles", "solve_256x256_m3277_b1024_valu_issue.txt")
+
+
+def measured_valu_issue(kernel):
+    """Fraction of the chip's VALU issue slots `kernel` used (rocprofv3 SQ
+    counters, committed summary), or None when the kernel sources changed."""
+    if not os.path.exists(VALU_FILE):
+        return None
+    want = solve_source_hash()
+    with open(VALU_FILE) as fh:
+        for line in fh:
+            f = line.split()
+            if len(f) == 6 and f[0] == "valu" and f[1] == kernel and f[5] == want:
+                return float(f[2])
+    return None
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
     summary (copy-calibrated), or None when the kernel sources changed since."""
@@ -367,7 +384,10 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
             "timing": "HIP events around every launch of the kernel in an eager repetition of the timed steps",
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "avg_launch_us": kd["ms"] * 1e3 / max(kd["launches"], 1), "launches": kd["launches"]}
+            "avg_launch_us": kd["ms"] * 1e3 / max(kd["launches"], 1), "launches": kd["launches"],
+            "valu_issue_frac": measured_valu_issue(dom),
+            "valu_note": "share of the 1024 SIMDs' VALU issue slots the kernel used (rocprofv3 SQ_INSTS_VALU, "
+                         "SQ_BUSY_CYCLES); near 1 means arithmetic issue, not HBM, bounds it"}
     if dft:
         # the last-axis stage is two dense GEMMs: 8 C rows nlast L flops per RVE-iteration
         fl = sum(8.0 * p.ncomp * (p.N // p.shape[-1]) * p.info["n_last"] * p.shape[-1] * it

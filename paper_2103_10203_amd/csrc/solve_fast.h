@@ -110,10 +110,16 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t comp_rsrc(const cpx<float>* ba
   // stride 0 (raw buffer); the fourth word selects 32-bit data for the gfx9 family
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<cpx<float>*>(base), (short)0, (int)bytes, 0x00020000);
 }
+typedef int i32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ cpx<float> load_or_zero(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off) {
-  typedef int i32x2 __attribute__((ext_vector_type(2)));
   const i32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)byte_off, 0, 0);
   return {__int_as_float(v.x), __int_as_float(v.y)};
+}
+__device__ __forceinline__ void store_c(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off, cpx<float> a) {
+  i32x2 v;
+  v.x = __float_as_int(a.x);
+  v.y = __float_as_int(a.y);
+  __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)byte_off, 0, 0);
 }
 
 // threadIdx.x, re-read per work item of a persistent loop behind an empty asm
@@ -326,14 +332,14 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
     // at the sampled frequencies and store them
     if (rlive) {
       const cpx<float>* z = buf + rg * SS;
-      cpx<float>* ydst = Y + (int64_t)c * cstride + r0 + rg;
+      const __amdgpu_buffer_rsrc_t rs = comp_rsrc(Y + (int64_t)c * cstride, cbytes);
       for (int j = tid / RB; j < nlast; j += QS) {
         const int k = lk[j];
         const cpx<float> Zk = z[fftr::padp<PS>(k == NH ? 0 : k)];
         const cpx<float> Zc = cconj(z[fftr::padp<PS>(k == 0 ? 0 : NH - k)]);
         const cpx<float> sm = cadd(Zk, Zc);
         const cpx<float> wd = cmul(T[pad16(k)], csub(Zk, Zc));
-        ydst[(int64_t)j * rows] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
+        store_c(rs, (uint32_t)j * (uint32_t)rows * 8u + rowb, {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)});
       }
     }
     if (c + 1 < C) __syncthreads();
