@@ -184,8 +184,9 @@ __device__ __forceinline__ void pass_twiddle(cpx<float>* v, int k, const cpx<flo
 }
 
 // One in-place Stockham pass over NS sequences (base + s*SS, positions
-// padded by padp<PS>) by NT threads.
-template <int N, int R, int P, int SIGN, int NS, int SS, int NT, int TWS, int PS = 4>
+// padded by padp<PS>) by NT threads.  TW = false skips the pass twiddles (the
+// producer of the pass's input has applied them).
+template <int N, int R, int P, int SIGN, int NS, int SS, int NT, int TWS, int PS = 4, bool TW = true>
 __device__ __forceinline__ void lds_pass(cpx<float>* buf, const cpx<float>* tw, int tid) {
   constexpr int NB = N / R;
   constexpr int TOTAL = NS * NB;
@@ -200,7 +201,7 @@ __device__ __forceinline__ void lds_pass(cpx<float>* buf, const cpx<float>* tw, 
       const cpx<float>* src = buf + s * SS;
 #pragma unroll
       for (int j = 0; j < R; ++j) v[q][j] = src[padp<PS>(i + j * NB)];
-      pass_twiddle<N, R, P, SIGN, TWS>(v[q], k, tw);
+      if constexpr (TW) pass_twiddle<N, R, P, SIGN, TWS>(v[q], k, tw);
       Dft<R, SIGN>::run(v[q]);
     }
   }
@@ -232,6 +233,16 @@ __device__ __forceinline__ void lds_passes(cpx<float>* buf, const cpx<float>* tw
   lds_pass<N, R, P, SIGN, NS, SS, NT, TWS, PS>(buf, tw, tid);
   lds_passes<N, SIGN, P * R, NS, SS, NT, TWS, PS>(buf, tw, tid, RList<Rest...>{});
 }
+
+// Single radix of a one-element list (0 otherwise).
+template <typename A>
+struct Single {
+  static constexpr int v = 0;
+};
+template <int R>
+struct Single<RList<R>> {
+  static constexpr int v = R;
+};
 
 template <int... Rs>
 struct Prod;

@@ -62,9 +62,9 @@ template <> struct RowVar<3, 256> { static constexpr int count = 5; };
 template <> struct RowCfg<6, 32, 0>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
 template <> struct RowCfg<6, 32, 1>  { static constexpr int RL = 8, RB = 16; using RA = RList<4>; };
 template <> struct RowVar<6, 32> { static constexpr int count = 2; };
-template <> struct RowCfg<6, 64, 0>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
+template <> struct RowCfg<6, 64, 0>  { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4>; };
 template <> struct RowCfg<6, 64, 1>  { static constexpr int RL = 8, RB = 8;  using RA = RList<8>; };
-template <> struct RowCfg<6, 64, 2>  { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4>; };
+template <> struct RowCfg<6, 64, 2>  { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4>; };
 template <> struct RowVar<6, 64> { static constexpr int count = 3; };
 template <> struct RowCfg<6, 128, 0> { static constexpr int RL = 4, RB = 4;  using RA = RList<8, 4>; };
 template <> struct RowCfg<6, 128, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<16>; };
@@ -320,14 +320,29 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
   for (int c = 0; c < C; ++c) {
     // register pass: first forward stage (radix RL, span 1)
     Dft<RL, -1>::run(v[c]);
+    // With one LDS pass (radix R2 = NH / RL, span RL), output j of this
+    // thread lands at input j2 = i of that pass's butterfly k = j, whose
+    // twiddle w^{i j} (w = exp(-2 pi i / NH)) is the conjugate of the inverse
+    // register pass's rtw[j]: apply it here from registers and run the LDS
+    // pass without twiddles.
+    constexpr int R2 = fftr::Single<typename Cfg::RA>::v;
+    constexpr bool kPreTwiddle = R2 * RL == NH;
+    if constexpr (kPreTwiddle) {
+#pragma unroll
+      for (int j = 1; j < RL; ++j) v[c][j] = cmul(v[c][j], cconj(rtw[j]));
+    }
     {
       cpx<float>* dst = buf + r * SS;
 #pragma unroll
       for (int j = 0; j < RL; ++j) dst[fftr::padp<PS>(i * RL + j)] = v[c][j];
     }
     __syncthreads();
-    fftr::lds_passes<NH, -1, RL, RB, SS, NT, 2, PS>(buf, T, tid,
-                                                typename fftr::Rev<typename Cfg::RA, RList<>>::type{});
+    if constexpr (kPreTwiddle) {
+      fftr::lds_pass<NH, R2, RL, -1, RB, SS, NT, 2, PS, false>(buf, T, tid);
+    } else {
+      fftr::lds_passes<NH, -1, RL, RB, SS, NT, 2, PS>(buf, T, tid,
+                                                  typename fftr::Rev<typename Cfg::RA, RList<>>::type{});
+    }
     // unpack X[k] = (Z[k] + conj Z[NH-k]) / 2 - i T[k] (Z[k] - conj Z[NH-k]) / 2
     // at the sampled frequencies and store them
     if (rlive) {
