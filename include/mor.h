@@ -128,8 +128,16 @@ typedef struct {
   int32_t pad_;
 } mor_phase;
 
-enum { MOR_PREC_FP32 = 0,     /* FP32 transforms and fields (default)            */
-       MOR_PREC_BF16X3 = 1 }; /* split-bf16 partial DFT on MFMA, FP32 accumulate */
+/* Arithmetic of the iteration (the residual and the grid mean of sigma are
+ * FP64 sums in every mode):
+ *   MOR_PREC_FP32    FP32 transforms and fields (default; specialised kernels)
+ *   MOR_PREC_BF16X3  split-bf16 partial DFT on MFMA, FP32 accumulate
+ *   MOR_PREC_FP64    FP64 transforms, Green operator and Hooke law (generic
+ *                    kernels; Hooke phases, FFT transform and grid schedule
+ *                    only, else MOR_E_UNSUPPORTED).  For tolerances below what
+ *                    FP32 reaches (the paper's examples stop at 1e-8); field
+ *                    and coefficient outputs are rounded to FP32. */
+enum { MOR_PREC_FP32 = 0, MOR_PREC_BF16X3 = 1, MOR_PREC_FP64 = 2 };
 enum { MOR_TRANSFORM_AUTO = 0, MOR_TRANSFORM_FFT = 1, MOR_TRANSFORM_DFT = 2 };
 /* Work schedule of the iteration kernels (same results):
  *   MOR_SCHED_GRID        one workgroup per (RVE, tile); converged RVEs' workgroups exit at once

@@ -7,7 +7,7 @@ script (``build.py``) and the thin ctypes binding (``_native``).
 from ._native import (  # noqa: F401
     Phase, Plan, SolveResult, MorError, solve, solve_multi, solve_path,
     profile_enable, profile_reset, profile_query, version, lib,
-    GAMMA_ROTATED, GAMMA_CONTINUOUS, PREC_FP32, PREC_BF16X3,
+    GAMMA_ROTATED, GAMMA_CONTINUOUS, PREC_FP32, PREC_BF16X3, PREC_FP64,
     TRANSFORM_AUTO, TRANSFORM_FFT, TRANSFORM_DFT,
     MOR_OK, MOR_E_INVALID_ARG, MOR_E_NOT_CONVERGED, MOR_E_NONFINITE, MOR_E_UNSUPPORTED,
     MLP, MLP_FP32, MLP_BF16, warm_features, warm_targets, warm_apply,

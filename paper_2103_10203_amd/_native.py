@@ -29,6 +29,7 @@ GAMMA_ROTATED = 0
 GAMMA_CONTINUOUS = 1
 PREC_FP32 = 0
 PREC_BF16X3 = 1
+PREC_FP64 = 2
 TRANSFORM_AUTO = 0
 TRANSFORM_FFT = 1
 TRANSFORM_DFT = 2

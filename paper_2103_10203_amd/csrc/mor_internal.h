@@ -68,6 +68,12 @@ struct PlanDev {
   const cpx<float>* tw1;     // [n1]        exp(-2 pi i t/n1) (3D)
   const cpx<float>* twh;     // [nlen/2]    exp(-2 pi i t/(nlen/2))
   const cpx<float>* rtw;     // [nlen]      exp(-2 pi i t/nlen)
+  // FP64 copies for the FP64 solve path (same definitions, not rounded)
+  const double* coef_n64;    // [ncoef][3]
+  const cpx<double>* tw0_64;
+  const cpx<double>* tw1_64;
+  const cpx<double>* twh_64;
+  const cpx<double>* rtw_64;
   FftDesc fd0, fd1, fdh;
 };
 
@@ -88,6 +94,8 @@ struct mor_plan {
   float* d_coef_n = nullptr;
   uint8_t* d_coef_flag = nullptr;
   cpx<float>* d_tw = nullptr;    // tw0 | tw1 | twh | rtw
+  double* d_coef_n64 = nullptr;
+  cpx<double>* d_tw64 = nullptr; // FP64 tw0 | tw1 | twh | rtw
   PlanDev* d_dev = nullptr;      // device copy of `dev`
   PlanDev dev{};
   // warm-start network tables: slot s = selected pair s+1 in rank order
@@ -99,6 +107,15 @@ struct mor_plan {
 
 // ---------------------------------------------------------------- solve
 // Per-solve material constants (FP32 copies for the kernels).
+// Hooke phases in FP64 (the FP64 solve path; J2 runs in FP32 only).
+struct MatDev64 {
+  double lam[2], mu[2];
+  double lam0, mu0;
+  double dl[2], dm[2];  // lam[p] - lam0 and 2 (mu[p] - mu0)
+  double g_inv_mu0;     // 1/mu0
+  double g_k;           // (lam0+mu0)/(mu0 (lam0+2 mu0))
+};
+
 struct MatDev {
   float lam[2], mu[2], sy[2], H[2];
   int32_t plastic[2];

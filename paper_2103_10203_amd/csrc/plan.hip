@@ -103,8 +103,10 @@ __global__ void k_twiddle_f64(cpx<double>* tw, int n) {
 }
 
 // The four solver twiddle tables in one launch, packed tw0 [n0] | tw1 [n1] |
-// twh [nh] | rtw [nl], each exp(-2 pi i t / length) rounded from FP64.
-__global__ void k_twiddle4_f32(cpx<float>* tw, int n0, int n1, int nh, int nl) {
+// twh [nh] | rtw [nl], each exp(-2 pi i t / length) evaluated in FP64 (and
+// rounded for the FP32 tables).
+template <typename T>
+__global__ void k_twiddle4(cpx<T>* tw, int n0, int n1, int nh, int nl) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int n;
   int u = t;
@@ -121,7 +123,7 @@ __global__ void k_twiddle4_f32(cpx<float>* tw, int n0, int n1, int nh, int nl) {
   }
   double s, c;
   sincospi(2.0 * (double)u / (double)n, &s, &c);
-  tw[t] = {(float)c, (float)(-s)};
+  tw[t] = {(T)c, (T)(-s)};
 }
 
 __global__ void k_g_to_cplx(const uint8_t* __restrict__ g, cpx<double>* __restrict__ S, int64_t N,
@@ -434,7 +436,8 @@ __global__ void k_tab_groups(const int* __restrict__ col_kh, const int* __restri
 // Pattern entries of each column, rows ascending, with Green directions.
 __device__ void coef_entry(const uint8_t* __restrict__ mask, Dims d, int gamma_kind, const int* k, int64_t lin, int e,
                            int* __restrict__ coef_k0, int64_t* __restrict__ coef_lin, float* __restrict__ coef_n,
-                           uint8_t* __restrict__ flag, const int* __restrict__ pairof, int* __restrict__ coef_slot) {
+                           double* __restrict__ coef_n64, uint8_t* __restrict__ flag, const int* __restrict__ pairof,
+                           int* __restrict__ coef_slot) {
   const int n[3] = {d.n0, d.n1, d.n2};
   coef_k0[e] = k[0];
   coef_lin[e] = lin;
@@ -489,6 +492,9 @@ __device__ void coef_entry(const uint8_t* __restrict__ mask, Dims d, int gamma_k
   coef_n[3 * e + 0] = (float)v[0];
   coef_n[3 * e + 1] = (float)v[1];
   coef_n[3 * e + 2] = (float)v[2];
+  coef_n64[3 * e + 0] = v[0];
+  coef_n64[3 * e + 1] = v[1];
+  coef_n64[3 * e + 2] = v[2];
   flag[e] = f;
 }
 
@@ -499,8 +505,8 @@ __global__ __launch_bounds__(256) void k_tab_fill(const uint8_t* __restrict__ ma
                                                   const int* __restrict__ colidx, const int* __restrict__ col_off,
                                                   int gamma_kind, int* __restrict__ coef_k0,
                                                   int64_t* __restrict__ coef_lin, float* __restrict__ coef_n,
-                                                  uint8_t* __restrict__ flag, const int* __restrict__ pairof,
-                                                  int* __restrict__ coef_slot) {
+                                                  double* __restrict__ coef_n64, uint8_t* __restrict__ flag,
+                                                  const int* __restrict__ pairof, int* __restrict__ coef_slot) {
   const int c = blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (c >= ncolall) return;
@@ -531,7 +537,8 @@ __global__ __launch_bounds__(256) void k_tab_fill(const uint8_t* __restrict__ ma
     const unsigned long long bal = __ballot(sel);
     if (sel) {
       const int pos = __popcll(bal & ((1ull << lane) - 1ull));
-      coef_entry(mask, d, gamma_kind, k, lin, e + pos, coef_k0, coef_lin, coef_n, flag, pairof, coef_slot);
+      coef_entry(mask, d, gamma_kind, k, lin, e + pos, coef_k0, coef_lin, coef_n, coef_n64, flag, pairof,
+                 coef_slot);
     }
     e += __popcll(bal);
   }
@@ -794,11 +801,12 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   MOR_LAUNCH_CHECK("tab_groups");
   MOR_HIP_TRY(plan_alloc(P, &P->d_coef_lin, std::max(ncoef, 1) * sizeof(int64_t)));
   MOR_HIP_TRY(plan_alloc(P, &P->d_coef_n, std::max(ncoef, 1) * 3 * sizeof(float)));
+  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_n64, std::max(ncoef, 1) * 3 * sizeof(double)));
   MOR_HIP_TRY(plan_alloc(P, &P->d_coef_flag, std::max(ncoef, 1)));
   MOR_HIP_TRY(plan_alloc(P, &P->d_coef_slot, std::max(ncoef, 1) * sizeof(int)));
   k_tab_fill<<<(ncolall + 3) / 4, 256, 0, st>>>(mask.p, d, ncolall, colidx.p, col_off, P->gamma_kind, coef_k0,
-                                                    P->d_coef_lin, P->d_coef_n, P->d_coef_flag, pairof.p,
-                                                    P->d_coef_slot);
+                                                    P->d_coef_lin, P->d_coef_n, P->d_coef_n64, P->d_coef_flag,
+                                                    pairof.p, P->d_coef_slot);
   MOR_LAUNCH_CHECK("tab_fill");
 
   // twiddles for the solver transforms
@@ -809,8 +817,11 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   cpx<float>* tw1 = tw0 + n0;
   cpx<float>* twh = tw1 + n1;
   cpx<float>* rtw = twh + nlen / 2;
-  k_twiddle4_f32<<<(ntw + 255) / 256, 256, 0, st>>>(P->d_tw, n0, n1, nlen / 2, nlen);
+  k_twiddle4<float><<<(ntw + 255) / 256, 256, 0, st>>>(P->d_tw, n0, n1, nlen / 2, nlen);
   MOR_LAUNCH_CHECK("twiddle_f32");
+  MOR_HIP_TRY(plan_alloc(P, &P->d_tw64, ntw * sizeof(cpx<double>)));
+  k_twiddle4<double><<<(ntw + 255) / 256, 256, 0, st>>>(P->d_tw64, n0, n1, nlen / 2, nlen);
+  MOR_LAUNCH_CHECK("twiddle_f64");
   (void)tw0;
   (void)tw1;
   (void)twh;
@@ -841,6 +852,11 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   v.tw1 = tw1;
   v.twh = twh;
   v.rtw = rtw;
+  v.coef_n64 = P->d_coef_n64;
+  v.tw0_64 = P->d_tw64;
+  v.tw1_64 = v.tw0_64 + n0;
+  v.twh_64 = v.tw1_64 + n1;
+  v.rtw_64 = v.twh_64 + nlen / 2;
   fft_make_desc(n0, &v.fd0);
   fft_make_desc(n1, &v.fd1);
   fft_make_desc(nlen / 2, &v.fdh);

@@ -106,13 +106,14 @@ Workspace* workspace_for(void* stream) {
 
 // Launch geometry from an LDS budget (bytes).
 constexpr int kLdsBudget = 56 * 1024;
-int rows_per_block(int C, int nlen) {
+// Blocks of the generic kernels within the LDS budget; es = bytes per complex.
+int rows_per_block(int C, int nlen, int es = 8) {
   const int nh = nlen / 2;
-  int rb = (kLdsBudget / 8 - (2 * nh + 1)) / (2 * C * (nh + 1));
+  int rb = (kLdsBudget / es - (2 * nh + 1)) / (2 * C * (nh + 1));
   return std::max(1, rb);
 }
-int cols_per_block(int C, int n0) {
-  int cb = (kLdsBudget / 8 - n0) / (2 * C * n0);
+int cols_per_block(int C, int n0, int es = 8) {
+  int cb = (kLdsBudget / es - n0) / (2 * C * n0);
   return std::max(1, cb);
 }
 
@@ -277,6 +278,11 @@ struct SolveCtx {
   bool persist = false;    // persistent schedule of the specialised row/column kernels
   int* d_alist = nullptr;  // [B] active RVEs per group (group segments as in the lists)
   int* d_nact = nullptr;   // [groups] active count per group
+  bool fp64 = false;       // FP64 fields and coefficients (generic kernels, Hooke phases)
+  MatDev64 mat64{};
+  cpx<double>* yl64() const { return reinterpret_cast<cpx<double>*>(d_yl); }
+  cpx<double>* yc64() const { return reinterpret_cast<cpx<double>*>(d_yc); }
+  cpx<double>* coef64() const { return reinterpret_cast<cpx<double>*>(d_coef); }
 };
 
 // Asynchronous upload from a host copy kept alive until the solve ends.
@@ -337,6 +343,23 @@ MatDev make_mat(const mor_phase* ph) {
   return m;
 }
 
+
+MatDev64 make_mat64(const mor_phase* ph) {
+  MatDev64 m{};
+  for (int p = 0; p < 2; ++p) {
+    m.lam[p] = ph[p].lambda;
+    m.mu[p] = ph[p].mu;
+  }
+  m.lam0 = 0.5 * (ph[0].lambda + ph[1].lambda);
+  m.mu0 = 0.5 * (ph[0].mu + ph[1].mu);
+  for (int p = 0; p < 2; ++p) {
+    m.dl[p] = m.lam[p] - m.lam0;
+    m.dm[p] = 2.0 * (m.mu[p] - m.mu0);
+  }
+  m.g_inv_mu0 = 1.0 / m.mu0;
+  m.g_k = (m.lam0 + m.mu0) / (m.mu0 * (m.lam0 + 2.0 * m.mu0));
+  return m;
+}
 
 void ev_begin(SolveCtx& cx, int kind, hipEvent_t* a) {
   if (!g_prof_on || cx.capturing) return;
@@ -554,12 +577,17 @@ void go_mid_fast(SolveCtx& cx, Group& g, int check_active) {
 
 template <int DIR>
 void launch_mid(SolveCtx& cx, Group& g, int check_active) {
-  if (has_fast_mid(g.n1)) {
+  if (has_fast_mid(g.n1) && !cx.fp64) {
     switch (g.n1) {
       case 32: go_mid_fast<32, DIR>(cx, g, check_active); break;
       case 64: go_mid_fast<64, DIR>(cx, g, check_active); break;
       default: go_mid_fast<128, DIR>(cx, g, check_active); break;
     }
+  } else if (cx.fp64) {
+    const size_t shm = (size_t)(g.n1 + 2 * 6 * g.xb * g.n1) * sizeof(cpx<double>);
+    dim3 gm((g.n0 + g.xb - 1) / g.xb, g.nlast_max, (unsigned)g.rves.size());
+    k_mid<6, DIR, double><<<gm, 256, shm, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.yl64(), cx.yc64(), cx.off,
+                                                   g.xb, check_active);
   } else {
     const size_t shm = (size_t)(g.n1 + 2 * 6 * g.xb * g.n1) * sizeof(cpx<float>);
     dim3 gm((g.n0 + g.xb - 1) / g.xb, g.nlast_max, (unsigned)g.rves.size());
@@ -590,7 +618,10 @@ mor_status launch_init(SolveCtx& cx, Group& g, const cpx<float>* warm) {
   dim3 grid((g.ncol_max + g.cb - 1) / g.cb, (unsigned)g.rves.size());
   hipEvent_t a{};
   ev_begin(cx, PK_INIT, &a);
-  if (g.fast_col)
+  if (cx.fp64)
+    k_col<C, MODE_INIT, double, MatDev64><<<grid, 256, 2 * shc, cx.st>>>(
+        cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.yc64(), cx.coef64(), warm, cx.off, cx.d_part, cx.mat64, g.cb);
+  else if (g.fast_col)
     col_fast<C, MODE_INIT>(cx, g, warm);
   else
     k_col<C, MODE_INIT><<<grid, 256, shc, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.d_yc, cx.d_coef,
@@ -635,6 +666,16 @@ void launch_dft_stage(SolveCtx& cx, Group& g, int rows, int L) {
   else dft_forward<DFT_F32>(cx, g, C, rows);
 }
 
+// Generic row kernel in FP64 (Hooke phases only: setup rejects J2 with FP64).
+template <int C, int MODE, int MAT>
+void launch_row64(SolveCtx& cx, Group& g, dim3 gr, size_t shm, float* eps, float* sig) {
+  if constexpr (MAT == MAT_HOOKE) {
+    k_row<C, MODE, MAT_HOOKE, double, MatDev64><<<gr, 256, shm, cx.st>>>(
+        cx.d_plans, g.d_list, cx.d_st, cx.yl64(), cx.off, cx.mat64, nullptr, eps, sig,
+        MODE == MODE_FINAL ? cx.d_sigpart : nullptr, g.rb);
+  }
+}
+
 template <int C, int MAT>
 mor_status launch_iter(SolveCtx& cx, Group& g) {
   const int nlen = C == 3 ? g.n1 : g.n2;
@@ -652,6 +693,8 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
   ev_begin(cx, PK_ROW, &a);
   if (cx.dft)
     launch_dft_stage<C, MAT>(cx, g, rows, nlen);
+  else if (cx.fp64)
+    launch_row64<C, MODE_ITER, MAT>(cx, g, gr, 2 * shr, nullptr, nullptr);
   else if (g.fast_row && pers)
     row_persist<C, MAT>(cx, g);
   else if (g.fast_row)
@@ -670,7 +713,10 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
   const size_t shc = (size_t)(g.n0 + 2 * C * g.cb * g.n0) * sizeof(cpx<float>);
   dim3 gc((g.ncol_max + g.cb - 1) / g.cb, (unsigned)g.rves.size());
   ev_begin(cx, PK_COL, &a);
-  if (g.fast_col && pers)
+  if (cx.fp64)
+    k_col<C, MODE_ITER, double, MatDev64><<<gc, 256, 2 * shc, cx.st>>>(
+        cx.d_plans, g.d_list, cx.d_st, cx.d_ebar, cx.yc64(), cx.coef64(), nullptr, cx.off, cx.d_part, cx.mat64, g.cb);
+  else if (g.fast_col && pers)
     col_persist<C>(cx, g);
   else if (g.fast_col)
     col_fast<C, MODE_ITER>(cx, g, nullptr);
@@ -708,7 +754,9 @@ mor_status launch_final(SolveCtx& cx, Group& g, float* eps, float* sig) {
     dim3 gp((rows + kDftRb - 1) / kDftRb, (unsigned)g.rves.size());
     k_dft_point<C, MODE_FINAL, MAT><<<gp, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.off, cx.mat, cx.d_dfte,
                                                            cx.d_jstate, eps, sig, cx.d_sigpart, kDftRb);
-  } else if (g.fast_row)
+  } else if (cx.fp64)
+    launch_row64<C, MODE_FINAL, MAT>(cx, g, gr, 2 * shr, eps, sig);
+  else if (g.fast_row)
     row_fast<C, MODE_FINAL, MAT>(cx, g, eps, sig);
   else
     k_row<C, MODE_FINAL, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
@@ -748,6 +796,22 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   cx.NST = cx.ndim == 2 ? 5 : 7;
   cx.mat = make_mat(phase);
   cx.j2 = phase[0].plastic || phase[1].plastic;
+  cx.fp64 = opts && opts->precision == MOR_PREC_FP64;
+  if (cx.fp64) {
+    cx.mat64 = make_mat64(phase);
+    if (cx.j2) {
+      mor_set_error("MOR_PREC_FP64 supports Hooke phases only (J2 runs in FP32)");
+      return MOR_E_UNSUPPORTED;
+    }
+    if (opts->transform == MOR_TRANSFORM_DFT) {
+      mor_set_error("MOR_PREC_FP64 uses the FFT transform (MOR_TRANSFORM_AUTO or MOR_TRANSFORM_FFT)");
+      return MOR_E_UNSUPPORTED;
+    }
+    if (opts->schedule == MOR_SCHED_PERSISTENT) {
+      mor_set_error("MOR_PREC_FP64 runs on the grid schedule only");
+      return MOR_E_UNSUPPORTED;
+    }
+  }
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10000;
   Workspace& ws = *cx.ws;
   mor_status s;
@@ -803,23 +867,24 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
       mor_set_error("the DFT transform needs rows and last-axis length multiples of 64 (length <= 512)");
       return MOR_E_UNSUPPORTED;
     }
-    g.fast_row = has_fast_row(cx.C, nlen / 2);
-    g.fast_col = has_fast_col(cx.C, g.n0);
+    g.fast_row = !cx.fp64 && has_fast_row(cx.C, nlen / 2);
+    g.fast_col = !cx.fp64 && has_fast_col(cx.C, g.n0);
+    const int es = cx.fp64 ? (int)sizeof(cpx<double>) : (int)sizeof(cpx<float>);
     if (cx.dft) {
       g.rb = kDftRb;
     } else if (g.fast_row) {
       g.rvar = std::min(row_variant(cx.C, nlen / 2), row_variants(cx.C, nlen / 2) - 1);
       g.rb = fast_rb(cx.C, nlen / 2, g.rvar);
     } else {
-      g.rb = rows_per_block(cx.C, nlen);
+      g.rb = rows_per_block(cx.C, nlen, es);
     }
     if (g.fast_col) {
       g.cvar = std::min(col_variant(cx.C, g.n0), col_variants(cx.C, g.n0) - 1);
       g.cb = fast_cb(cx.C, g.n0, g.cvar);
     } else {
-      g.cb = cols_per_block(cx.C, g.n0);
+      g.cb = cols_per_block(cx.C, g.n0, es);
     }
-    g.xb = g.ndim == 3 ? cols_per_block(cx.C, g.n1) : 1;
+    g.xb = g.ndim == 3 ? cols_per_block(cx.C, g.n1, es) : 1;
     if (!g.fast_row && !cx.dft) g.rb = std::min(g.rb, rows);
   }
   std::vector<int> gof(B);
@@ -858,13 +923,15 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   cx.off.coef = d_offs + 2 * B;
   cx.off.field = d_offs + 3 * B;
   cx.off.part = d_offs + 4 * B;
-  if ((s = ws.get("yl", (size_t)yl, &cx.d_yl)) != MOR_OK) return s;
+  // counts in FP32 complex elements; FP64 complex takes two
+  const size_t ew = cx.fp64 ? 2 : 1;
+  if ((s = ws.get("yl", (size_t)yl * ew, &cx.d_yl)) != MOR_OK) return s;
   if (cx.ndim == 3) {
-    if ((s = ws.get("yc", (size_t)yc, &cx.d_yc)) != MOR_OK) return s;
+    if ((s = ws.get("yc", (size_t)yc * ew, &cx.d_yc)) != MOR_OK) return s;
   } else {
     cx.d_yc = cx.d_yl;
   }
-  if ((s = ws.get("coef", (size_t)co, &cx.d_coef)) != MOR_OK) return s;
+  if ((s = ws.get("coef", (size_t)co * ew, &cx.d_coef)) != MOR_OK) return s;
   if (cx.dft && (s = ws.get("dfte", (size_t)fo * cx.C, &cx.d_dfte)) != MOR_OK) return s;
   if ((s = ws.get("part", (size_t)pa, &cx.d_part)) != MOR_OK) return s;
   if ((s = ws.get("sigpart", (size_t)pa * cx.S, &cx.d_sigpart)) != MOR_OK) return s;
@@ -1017,6 +1084,12 @@ mor_status run(SolveCtx& cx, const cpx<float>* warm, const mor_solve_opts* opts,
   return MOR_OK;
 }
 
+// FP64 coefficients rounded to the FP32 output layout.
+__global__ void k_round_c64(const cpx<double>* __restrict__ a, cpx<float>* __restrict__ o, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = {(float)a[i].x, (float)a[i].y};
+}
+
 mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<RveState>* states_out) {
   std::vector<RveState> hs(cx.B);
   MOR_HIP_TRY(hipMemcpyAsync(hs.data(), cx.d_st, cx.B * sizeof(RveState), hipMemcpyDeviceToHost, cx.st));
@@ -1026,7 +1099,12 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
   if (out && out->coeffs) {
     int64_t tot = 0;
     for (int64_t b = 0; b < cx.B; ++b) tot += (int64_t)cx.C * cx.ncoef_h[b];
-    MOR_HIP_TRY(hipMemcpyAsync(out->coeffs, cx.d_coef, tot * sizeof(cpx<float>), hipMemcpyDeviceToDevice, cx.st));
+    if (cx.fp64) {
+      k_round_c64<<<(unsigned)((tot + 255) / 256), 256, 0, cx.st>>>(cx.coef64(), (cpx<float>*)out->coeffs, tot);
+      MOR_LAUNCH_CHECK("round coefficients");
+    } else {
+      MOR_HIP_TRY(hipMemcpyAsync(out->coeffs, cx.d_coef, tot * sizeof(cpx<float>), hipMemcpyDeviceToDevice, cx.st));
+    }
   }
   MOR_HIP_TRY(hipStreamSynchronize(cx.st));
   if (g_prof_on) {
@@ -1044,14 +1122,15 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
       const PlanDev& d = cx.plan_dev[b];
       const double it = hs[b].iters;
       const double C = cx.C, L = d.nlen;
-      double row = d.rows * (16.0 * C * d.nlast + L);
+      const double ew = cx.fp64 ? 2.0 : 1.0;  // complex elements of FP64 take twice the bytes
+      double row = d.rows * (16.0 * ew * C * d.nlast + L);
       // DFT path: spectra in/out plus the real field written, read,
       // rewritten and read again between the GEMMs
       if (cx.dft) row += 16.0 * C * d.N;
       if (cx.j2) row += d.rows * L * 4.0 * cx.NST;
-      const double col = d.ncol * 16.0 * C * d.n0 + d.ncoef * (16.0 * C + 17.0);
-      const double mid = cx.ndim == 3 ? d.n0 * 8.0 * C * ((double)d.nlast * d.n1 + d.ncol) : 0.0;
-      double fin = d.rows * (8.0 * C * d.nlast + L);
+      const double col = d.ncol * 16.0 * ew * C * d.n0 + d.ncoef * (16.0 * ew * C + 17.0);
+      const double mid = cx.ndim == 3 ? d.n0 * 8.0 * ew * C * ((double)d.nlast * d.n1 + d.ncol) : 0.0;
+      double fin = d.rows * (8.0 * ew * C * d.nlast + L);
       if (cx.dft) fin += 8.0 * C * d.N;
       if (cx.want_eps) fin += (double)d.N * 4.0 * C;
       if (cx.want_sig) fin += (double)d.N * 4.0 * cx.S;
@@ -1069,7 +1148,7 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
       g_prof[PK_FINAL].items += 1;
       g_prof[PK_FINAL].bytes += fin;
       g_prof[PK_INIT].items += 1;
-      g_prof[PK_INIT].bytes += d.ncol * 8.0 * C * d.n0 + d.ncoef * 25.0;
+      g_prof[PK_INIT].bytes += d.ncol * 8.0 * ew * C * d.n0 + d.ncoef * (8.0 * ew + 17.0);
     }
   }
   cx.events.clear();
@@ -1115,8 +1194,9 @@ mor_status check_common(const double* ebar, int64_t B, int C, const mor_phase* p
       mor_set_error("max_iter and check_every must be >= 0");
       return MOR_E_INVALID_ARG;
     }
-    if (opts->precision != MOR_PREC_FP32 && opts->precision != MOR_PREC_BF16X3) {
-      mor_set_error("precision must be MOR_PREC_FP32 or MOR_PREC_BF16X3");
+    if (opts->precision != MOR_PREC_FP32 && opts->precision != MOR_PREC_BF16X3 &&
+        opts->precision != MOR_PREC_FP64) {
+      mor_set_error("precision must be MOR_PREC_FP32, MOR_PREC_BF16X3 or MOR_PREC_FP64");
       return MOR_E_INVALID_ARG;
     }
     if (opts->transform < MOR_TRANSFORM_AUTO || opts->transform > MOR_TRANSFORM_DFT) {

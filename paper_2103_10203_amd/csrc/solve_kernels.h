@@ -130,44 +130,44 @@ __device__ __forceinline__ void constitutive(const float* e, int ph, const MatDe
 // Green operator of the isotropic reference medium (Sec. 3, eq. Gamma):
 // eps^ = -[(n (x) v + v (x) n)/(2 mu0) - k s n (x) n], v = tau^ n, s = n.v,
 // k = (lam0 + mu0)/(mu0 (lam0 + 2 mu0)).  Applied to real and imaginary parts.
-template <int C>
-__device__ __forceinline__ void green(const float* n, const float* t, float* out, float inv_mu, float kk) {
+template <int C, typename T = float>
+__device__ __forceinline__ void green(const T* n, const T* t, T* out, T inv_mu, T kk) {
   if (C == 3) {
-    float v0 = t[0] * n[0] + t[2] * n[1];
-    float v1 = t[2] * n[0] + t[1] * n[1];
-    float s = n[0] * v0 + n[1] * v1;
-    float ks = kk * s;
+    T v0 = t[0] * n[0] + t[2] * n[1];
+    T v1 = t[2] * n[0] + t[1] * n[1];
+    T s = n[0] * v0 + n[1] * v1;
+    T ks = kk * s;
     out[0] = -(inv_mu * n[0] * v0 - ks * n[0] * n[0]);
     out[1] = -(inv_mu * n[1] * v1 - ks * n[1] * n[1]);
-    out[2] = -(0.5f * inv_mu * (n[0] * v1 + n[1] * v0) - ks * n[0] * n[1]);
+    out[2] = -(T(0.5) * inv_mu * (n[0] * v1 + n[1] * v0) - ks * n[0] * n[1]);
   } else {
     // t: 11,22,33,23,13,12
-    float v0 = t[0] * n[0] + t[5] * n[1] + t[4] * n[2];
-    float v1 = t[5] * n[0] + t[1] * n[1] + t[3] * n[2];
-    float v2 = t[4] * n[0] + t[3] * n[1] + t[2] * n[2];
-    float s = n[0] * v0 + n[1] * v1 + n[2] * v2;
-    float ks = kk * s;
+    T v0 = t[0] * n[0] + t[5] * n[1] + t[4] * n[2];
+    T v1 = t[5] * n[0] + t[1] * n[1] + t[3] * n[2];
+    T v2 = t[4] * n[0] + t[3] * n[1] + t[2] * n[2];
+    T s = n[0] * v0 + n[1] * v1 + n[2] * v2;
+    T ks = kk * s;
     out[0] = -(inv_mu * n[0] * v0 - ks * n[0] * n[0]);
     out[1] = -(inv_mu * n[1] * v1 - ks * n[1] * n[1]);
     out[2] = -(inv_mu * n[2] * v2 - ks * n[2] * n[2]);
-    out[3] = -(0.5f * inv_mu * (n[1] * v2 + n[2] * v1) - ks * n[1] * n[2]);
-    out[4] = -(0.5f * inv_mu * (n[0] * v2 + n[2] * v0) - ks * n[0] * n[2]);
-    out[5] = -(0.5f * inv_mu * (n[0] * v1 + n[1] * v0) - ks * n[0] * n[1]);
+    out[3] = -(T(0.5) * inv_mu * (n[1] * v2 + n[2] * v1) - ks * n[1] * n[2]);
+    out[4] = -(T(0.5) * inv_mu * (n[0] * v2 + n[2] * v0) - ks * n[0] * n[2]);
+    out[5] = -(T(0.5) * inv_mu * (n[0] * v1 + n[1] * v0) - ks * n[0] * n[1]);
   }
 }
 
 // Projection of a strain amplitude onto compatible strains at direction n:
 // P v = Gamma^ : C0 : v = -green(n, C0 : v).  Used on warm starts.
-template <int C>
-__device__ __forceinline__ void project_compatible(const float* n, const float* v, float* out, const MatDev& m) {
+template <int C, typename T = float, typename MT = MatDev>
+__device__ __forceinline__ void project_compatible(const T* n, const T* v, T* out, const MT& m) {
   constexpr int ND = C == 3 ? 2 : 3;
-  float tr = 0.f;
+  T tr = T(0);
 #pragma unroll
   for (int i = 0; i < ND; ++i) tr += v[i];
-  float t[C];
+  T t[C];
 #pragma unroll
-  for (int i = 0; i < C; ++i) t[i] = (i < ND ? m.lam0 * tr : 0.f) + 2.f * m.mu0 * v[i];
-  green<C>(n, t, out, m.g_inv_mu0, m.g_k);
+  for (int i = 0; i < C; ++i) t[i] = (i < ND ? m.lam0 * tr : T(0)) + T(2) * m.mu0 * v[i];
+  green<C, T>(n, t, out, m.g_inv_mu0, m.g_k);
 #pragma unroll
   for (int i = 0; i < C; ++i) out[i] = -out[i];
 }
@@ -191,14 +191,67 @@ __device__ __forceinline__ double block_sum_d(double v, double* lds) {
   return r;
 }
 
+// Hooke law in FP64 (the FP64 path): tau = (lam - lam0) tr(eps) I + 2 (mu - mu0) eps
+// and, if wanted, sigma (with sigma_33 = lam tr(eps) in plane strain).
+template <int C>
+__device__ __forceinline__ void hooke64(const double* e, int ph, const MatDev64& m, double* tau, double* sig) {
+  constexpr int ND = Comp<C>::NDIAG;
+  double tr = e[0];
+#pragma unroll
+  for (int i = 1; i < ND; ++i) tr += e[i];
+  const bool p1 = ph != 0;
+  const double dl = p1 ? m.dl[1] : m.dl[0], dm = p1 ? m.dm[1] : m.dm[0];
+#pragma unroll
+  for (int i = 0; i < C; ++i) tau[i] = (i < ND ? dl * tr : 0.0) + dm * e[i];
+  if (sig) {
+    const double lam = p1 ? m.lam[1] : m.lam[0], mu = p1 ? m.mu[1] : m.mu[0];
+#pragma unroll
+    for (int i = 0; i < C; ++i) sig[i] = (i < ND ? lam * tr : 0.0) + 2.0 * mu * e[i];
+    if (C == 3) sig[3] = lam * tr;
+  }
+}
+
+// Step a) in the precision of the generic kernels: FP32 Hooke/J2, or FP64 Hooke.
+template <int C, int MAT, typename T, typename MT>
+__device__ __forceinline__ void law(const T* e, int ph, const MT& m, const float* stin, T* tau, T* sig, float* stout) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    static_assert(MAT == MAT_HOOKE, "the FP64 path has Hooke phases only");
+    hooke64<C>(e, ph, m, tau, sig);
+  } else {
+    constitutive<C, MAT>(e, ph, m, stin, tau, sig, stout);
+  }
+}
+
+// Plan tables in the precision T of the generic kernels.
+template <typename T>
+struct PT;
+template <>
+struct PT<float> {
+  __device__ static const cpx<float>* tw0(const PlanDev& P) { return P.tw0; }
+  __device__ static const cpx<float>* tw1(const PlanDev& P) { return P.tw1; }
+  __device__ static const cpx<float>* twh(const PlanDev& P) { return P.twh; }
+  __device__ static const cpx<float>* rtw(const PlanDev& P) { return P.rtw; }
+  __device__ static const float* coef_n(const PlanDev& P) { return P.coef_n; }
+  __device__ static float inv_N(const PlanDev& P) { return P.inv_N; }
+};
+template <>
+struct PT<double> {
+  __device__ static const cpx<double>* tw0(const PlanDev& P) { return P.tw0_64; }
+  __device__ static const cpx<double>* tw1(const PlanDev& P) { return P.tw1_64; }
+  __device__ static const cpx<double>* twh(const PlanDev& P) { return P.twh_64; }
+  __device__ static const cpx<double>* rtw(const PlanDev& P) { return P.rtw_64; }
+  __device__ static const double* coef_n(const PlanDev& P) { return P.coef_n64; }
+  __device__ static double inv_N(const PlanDev& P) { return 1.0 / (double)P.N; }
+};
+
 // ------------------------------------------------------------------ row kernel
 // Workgroup = `rb` consecutive rows of one RVE.  MODE_ITER: Yl (F) -> Yl (T).
 // MODE_FINAL: Yl (F) -> strain, stress fields, FP64 stress partial sums,
 // committed J2 state.
-template <int C, int MODE, int MAT>
+template <int C, int MODE, int MAT, typename T = float, typename MT = MatDev>
 __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
-                                             RveState* __restrict__ st, cpx<float>* __restrict__ Yl, Offs off,
-                                             MatDev mat, float* __restrict__ jstate, float* __restrict__ out_eps,
+                                             RveState* __restrict__ st, cpx<T>* __restrict__ Yl, Offs off,
+                                             MT mat, float* __restrict__ jstate, float* __restrict__ out_eps,
                                              float* __restrict__ out_sig, double* __restrict__ sig_part, int rb) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   constexpr int S = Comp<C>::S;
@@ -213,16 +266,16 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
   const int nr = min(rb, rows - r0);
   const int ss = nh + 1;
   const int nseq = C * rb;
-  cpx<float>* twh = reinterpret_cast<cpx<float>*>(smem_raw);
-  cpx<float>* rtw = twh + nh;
-  cpx<float>* A = rtw + nh + 1;
-  cpx<float>* Bf = A + nseq * ss;
-  for (int t = threadIdx.x; t < nh; t += blockDim.x) twh[t] = P.twh[t];
-  for (int t = threadIdx.x; t <= nh; t += blockDim.x) rtw[t] = P.rtw[t];
-  for (int t = threadIdx.x; t < nseq * ss; t += blockDim.x) Bf[t] = {0.f, 0.f};
+  cpx<T>* twh = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* rtw = twh + nh;
+  cpx<T>* A = rtw + nh + 1;
+  cpx<T>* Bf = A + nseq * ss;
+  for (int t = threadIdx.x; t < nh; t += blockDim.x) twh[t] = PT<T>::twh(P)[t];
+  for (int t = threadIdx.x; t <= nh; t += blockDim.x) rtw[t] = PT<T>::rtw(P)[t];
+  for (int t = threadIdx.x; t < nseq * ss; t += blockDim.x) Bf[t] = {T(0), T(0)};
   __syncthreads();
   const int nlast = P.nlast;
-  cpx<float>* Y = Yl + off.yl[b];
+  cpx<T>* Y = Yl + off.yl[b];
   const int64_t cstride = (int64_t)nlast * rows;
   for (int t = threadIdx.x; t < C * nlast * nr; t += blockDim.x) {
     const int r = t % nr;
@@ -234,15 +287,15 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
   // pack the half spectrum X[0..nh] into a length-nh complex sequence
   for (int t = threadIdx.x; t < nseq * nh; t += blockDim.x) {
     const int q = t / nh, k = t - q * nh;
-    const cpx<float> X = Bf[q * ss + k];
-    const cpx<float> Xc = cconj(Bf[q * ss + nh - k]);
-    const cpx<float> a = cadd(X, Xc);
-    const cpx<float> dd = cmul(csub(X, Xc), cconj(rtw[k]));
+    const cpx<T> X = Bf[q * ss + k];
+    const cpx<T> Xc = cconj(Bf[q * ss + nh - k]);
+    const cpx<T> a = cadd(X, Xc);
+    const cpx<T> dd = cmul(csub(X, Xc), cconj(rtw[k]));
     A[q * ss + k] = {a.x - dd.y, a.y + dd.x};
   }
   __syncthreads();
-  cpx<float>* E = fft_stockham<float, +1>(A, Bf, nseq, ss, P.fdh, twh);
-  cpx<float>* O = (E == A) ? Bf : A;
+  cpx<T>* E = fft_stockham<T, +1>(A, Bf, nseq, ss, P.fdh, twh);
+  cpx<T>* O = (E == A) ? Bf : A;
 
   double acc[S];
 #pragma unroll
@@ -251,10 +304,10 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
     const int r = t / nh, k = t - r * nh;
     const int64_t row = r0 + r;
     const uint8_t* grow = P.g + row * P.nlen;
-    float e0[C], e1[C], t0[C], t1[C];
+    T e0[C], e1[C], t0[C], t1[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      const cpx<float> z = E[(c * rb + r) * ss + k];
+      const cpx<T> z = E[(c * rb + r) * ss + k];
       e0[c] = z.x;
       e1[c] = z.y;
     }
@@ -270,12 +323,13 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
           sin1[i] = sp[(int64_t)i * P.N + p0 + 1];
         }
       }
-      constitutive<C, MAT>(e0, g0, mat, sin0, t0, nullptr, nullptr);
-      constitutive<C, MAT>(e1, g1, mat, sin1, t1, nullptr, nullptr);
+      law<C, MAT>(e0, g0, mat, sin0, t0, (T*)nullptr, nullptr);
+      law<C, MAT>(e1, g1, mat, sin1, t1, (T*)nullptr, nullptr);
 #pragma unroll
       for (int c = 0; c < C; ++c) E[(c * rb + r) * ss + k] = {t0[c], t1[c]};
     } else {
-      float s0[S], s1[S], sin0[NST], sin1[NST], so0[NST], so1[NST];
+      T s0[S], s1[S];
+      float sin0[NST], sin1[NST], so0[NST], so1[NST];
       const int64_t p0 = row * P.nlen + 2 * k;
       if (MAT == MAT_J2) {
         float* sp = jstate + off.field[b] * NST;
@@ -285,8 +339,8 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
           sin1[i] = sp[(int64_t)i * P.N + p0 + 1];
         }
       }
-      constitutive<C, MAT>(e0, g0, mat, sin0, t0, s0, so0);
-      constitutive<C, MAT>(e1, g1, mat, sin1, t1, s1, so1);
+      law<C, MAT>(e0, g0, mat, sin0, t0, s0, so0);
+      law<C, MAT>(e1, g1, mat, sin1, t1, s1, so1);
       if (MAT == MAT_J2) {
         float* sp = jstate + off.field[b] * NST;
 #pragma unroll
@@ -299,16 +353,16 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
         float* fe = out_eps + off.field[b] * C;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          fe[(int64_t)c * P.N + p0] = e0[c];
-          fe[(int64_t)c * P.N + p0 + 1] = e1[c];
+          fe[(int64_t)c * P.N + p0] = (float)e0[c];
+          fe[(int64_t)c * P.N + p0 + 1] = (float)e1[c];
         }
       }
       if (out_sig) {
         float* fs = out_sig + off.field[b] * S;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-          fs[(int64_t)s * P.N + p0] = s0[s];
-          fs[(int64_t)s * P.N + p0 + 1] = s1[s];
+          fs[(int64_t)s * P.N + p0] = (float)s0[s];
+          fs[(int64_t)s * P.N + p0 + 1] = (float)s1[s];
         }
       }
 #pragma unroll
@@ -325,18 +379,18 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
     return;
   }
   __syncthreads();
-  cpx<float>* Z = fft_stockham<float, -1>(E, O, nseq, ss, P.fdh, twh);
+  cpx<T>* Z = fft_stockham<T, -1>(E, O, nseq, ss, P.fdh, twh);
   for (int t = threadIdx.x; t < C * nlast * nr; t += blockDim.x) {
     const int r = t % nr;
     const int q = t / nr;
     const int j = q % nlast, c = q / nlast;
     const int k = P.last_k[j];
-    const cpx<float>* z = Z + (c * rb + r) * ss;
-    const cpx<float> Zk = z[k == nh ? 0 : k];
-    const cpx<float> Zc = cconj(z[k == 0 ? 0 : nh - k]);
-    const cpx<float> sm = cadd(Zk, Zc);
-    const cpx<float> wd = cmul(rtw[k], csub(Zk, Zc));
-    Y[c * cstride + (int64_t)j * rows + r0 + r] = {0.5f * (sm.x + wd.y), 0.5f * (sm.y - wd.x)};
+    const cpx<T>* z = Z + (c * rb + r) * ss;
+    const cpx<T> Zk = z[k == nh ? 0 : k];
+    const cpx<T> Zc = cconj(z[k == 0 ? 0 : nh - k]);
+    const cpx<T> sm = cadd(Zk, Zc);
+    const cpx<T> wd = cmul(rtw[k], csub(Zk, Zc));
+    Y[c * cstride + (int64_t)j * rows + r0 + r] = {T(0.5) * (sm.x + wd.y), T(0.5) * (sm.y - wd.x)};
   }
 }
 
@@ -344,12 +398,12 @@ __global__ __launch_bounds__(256) void k_row(const PlanDev* __restrict__ plans, 
 // Workgroup = `cb` consecutive columns of one RVE.  MODE_ITER: forward FFT
 // along axis 0, Green operator on the pattern rows, residual, inverse FFT.
 // MODE_INIT: coefficients from the cold or warm start, inverse FFT only.
-template <int C, int MODE>
+template <int C, int MODE, typename T = float, typename MT = MatDev>
 __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
                                              RveState* __restrict__ st, const double* __restrict__ ebar,
-                                             cpx<float>* __restrict__ Yc, cpx<float>* __restrict__ coef,
+                                             cpx<T>* __restrict__ Yc, cpx<T>* __restrict__ coef,
                                              const cpx<float>* __restrict__ warm, Offs off,
-                                             double* __restrict__ part, MatDev mat, int cb) {
+                                             double* __restrict__ part, MT mat, int cb) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int b = rve_list[blockIdx.y];
   if (MODE == MODE_ITER && !st[b].active) return;
@@ -360,16 +414,16 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
   const int ncb = min(cb, ncol - j0);
   const int n0 = P.n0;
   const int nseq = C * cb;
-  cpx<float>* tw = reinterpret_cast<cpx<float>*>(smem_raw);
-  cpx<float>* A = tw + n0;
-  cpx<float>* Bf = A + nseq * n0;
-  for (int t = threadIdx.x; t < n0; t += blockDim.x) tw[t] = P.tw0[t];
-  cpx<float>* Y = Yc + off.yc[b];
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* A = tw + n0;
+  cpx<T>* Bf = A + nseq * n0;
+  for (int t = threadIdx.x; t < n0; t += blockDim.x) tw[t] = PT<T>::tw0(P)[t];
+  cpx<T>* Y = Yc + off.yc[b];
   const int64_t cstride = (int64_t)ncol * n0;
   const int ncoef = P.ncoef;
-  cpx<float>* co = coef + off.coef[b];
-  cpx<float>* R = A;   // forward result
-  cpx<float>* O = Bf;  // zeroed buffer receiving the new coefficients
+  cpx<T>* co = coef + off.coef[b];
+  cpx<T>* R = A;   // forward result
+  cpx<T>* O = Bf;  // zeroed buffer receiving the new coefficients
   if (MODE == MODE_ITER) {
     for (int t = threadIdx.x; t < C * ncb * n0; t += blockDim.x) {
       const int x = t % n0;
@@ -378,13 +432,12 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
       A[(c * cb + jj) * n0 + x] = Y[c * cstride + (int64_t)(j0 + jj) * n0 + x];
     }
     __syncthreads();
-    R = fft_stockham<float, -1>(A, Bf, nseq, n0, P.fd0, tw);
+    R = fft_stockham<T, -1>(A, Bf, nseq, n0, P.fd0, tw);
     O = (R == A) ? Bf : A;
   }
-  for (int t = threadIdx.x; t < nseq * n0; t += blockDim.x) O[t] = {0.f, 0.f};
+  for (int t = threadIdx.x; t < nseq * n0; t += blockDim.x) O[t] = {T(0), T(0)};
   __syncthreads();
-  const float Nf = (float)P.N;
-  const float invN = P.inv_N;
+    const T invN = PT<T>::inv_N(P);
   double dsum = 0.0;
   for (int jj = 0; jj < ncb; ++jj) {
     const int j = j0 + jj;
@@ -394,49 +447,51 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
     for (int e = P.col_off[j] + threadIdx.x; e < e1; e += blockDim.x) {
       const int k0 = P.coef_k0[e];
       const uint8_t fl = P.coef_flag[e];
-      float nr_[C], ni_[C];
+      T nr_[C], ni_[C];
       if (fl & COEF_ZERO) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          nr_[c] = (float)((double)P.N * ebar[(int64_t)b * C + c]);
-          ni_[c] = 0.f;
+          nr_[c] = (T)((double)P.N * ebar[(int64_t)b * C + c]);
+          ni_[c] = T(0);
         }
       } else if ((fl & COEF_DEAD)) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) nr_[c] = ni_[c] = 0.f;
+        for (int c = 0; c < C; ++c) nr_[c] = ni_[c] = T(0);
       } else if (MODE == MODE_ITER) {
-        float tr_[C], ti_[C];
+        T tr_[C], ti_[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const cpx<float> v = R[(c * cb + jj) * n0 + k0];
+          const cpx<T> v = R[(c * cb + jj) * n0 + k0];
           tr_[c] = v.x;
           ti_[c] = v.y;
         }
-        const float nv[3] = {P.coef_n[3 * e], P.coef_n[3 * e + 1], P.coef_n[3 * e + 2]};
-        green<C>(nv, tr_, nr_, mat.g_inv_mu0, mat.g_k);
-        green<C>(nv, ti_, ni_, mat.g_inv_mu0, mat.g_k);
+        const T* cn = PT<T>::coef_n(P);
+        const T nv[3] = {cn[3 * e], cn[3 * e + 1], cn[3 * e + 2]};
+        green<C, T>(nv, tr_, nr_, mat.g_inv_mu0, mat.g_k);
+        green<C, T>(nv, ti_, ni_, mat.g_inv_mu0, mat.g_k);
       } else {
         if (warm) {
-          float wr[C], wi[C];
+          T wr[C], wi[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) {
             const cpx<float> w = warm[off.coef[b] + (int64_t)c * ncoef + e];
             wr[c] = w.x;
             wi[c] = w.y;
           }
-          const float nv[3] = {P.coef_n[3 * e], P.coef_n[3 * e + 1], P.coef_n[3 * e + 2]};
-          project_compatible<C>(nv, wr, nr_, mat);
-          project_compatible<C>(nv, wi, ni_, mat);
+          const T* cn = PT<T>::coef_n(P);
+        const T nv[3] = {cn[3 * e], cn[3 * e + 1], cn[3 * e + 2]};
+          project_compatible<C, T>(nv, wr, nr_, mat);
+          project_compatible<C, T>(nv, wi, ni_, mat);
         } else {
 #pragma unroll
-          for (int c = 0; c < C; ++c) nr_[c] = ni_[c] = 0.f;
+          for (int c = 0; c < C; ++c) nr_[c] = ni_[c] = T(0);
         }
       }
       if (MODE == MODE_ITER) {
         double d2 = 0.0;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-          const cpx<float> old = co[(int64_t)c * ncoef + e];
+          const cpx<T> old = co[(int64_t)c * ncoef + e];
           const double dr = (double)nr_[c] - (double)old.x, di = (double)ni_[c] - (double)old.y;
           d2 += (double)comp_weight<C>(c) * (dr * dr + di * di);
         }
@@ -449,10 +504,9 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
       }
     }
   }
-  (void)Nf;
   __syncthreads();
-  cpx<float>* other = (O == A) ? Bf : A;
-  cpx<float>* F = fft_stockham<float, +1>(O, other, nseq, n0, P.fd0, tw);
+  cpx<T>* other = (O == A) ? Bf : A;
+  cpx<T>* F = fft_stockham<T, +1>(O, other, nseq, n0, P.fd0, tw);
   for (int t = threadIdx.x; t < C * ncb * n0; t += blockDim.x) {
     const int x = t % n0;
     const int q = t / n0;
@@ -470,10 +524,10 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
 // Workgroup = (RVE, last-axis frequency j2, block of `xb` x0 values).
 // FWD: Yl lines along x1 -> FFT -> Yc at the group's columns.
 // INV: Yc at the group's columns -> zero-filled line -> inverse FFT -> Yl.
-template <int C, int DIR>
+template <int C, int DIR, typename T = float>
 __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
-                                             RveState* __restrict__ st, cpx<float>* __restrict__ Yl,
-                                             cpx<float>* __restrict__ Yc, Offs off, int xb, int check_active) {
+                                             RveState* __restrict__ st, cpx<T>* __restrict__ Yl,
+                                             cpx<T>* __restrict__ Yc, Offs off, int xb, int check_active) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int b = rve_list[blockIdx.z];
   if (check_active && !st[b].active) return;
@@ -485,14 +539,14 @@ __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, 
   if (x00 >= n0) return;
   const int nx = min(xb, n0 - x00);
   const int nseq = C * xb;
-  cpx<float>* tw = reinterpret_cast<cpx<float>*>(smem_raw);
-  cpx<float>* A = tw + n1;
-  cpx<float>* Bf = A + nseq * n1;
-  for (int t = threadIdx.x; t < n1; t += blockDim.x) tw[t] = P.tw1[t];
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* A = tw + n1;
+  cpx<T>* Bf = A + nseq * n1;
+  for (int t = threadIdx.x; t < n1; t += blockDim.x) tw[t] = PT<T>::tw1(P)[t];
   const int rows = P.rows;
   const int nlast = P.nlast, ncol = P.ncol;
-  cpx<float>* L = Yl + off.yl[b];
-  cpx<float>* Cc = Yc + off.yc[b];
+  cpx<T>* L = Yl + off.yl[b];
+  cpx<T>* Cc = Yc + off.yc[b];
   const int64_t lcs = (int64_t)nlast * rows;
   const int64_t ccs = (int64_t)ncol * n0;
   const int ja = P.last_off[j2], jb = P.last_off[j2 + 1];
@@ -505,7 +559,7 @@ __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, 
       A[(c * xb + xi) * n1 + x1] = L[c * lcs + (int64_t)j2 * rows + (int64_t)(x00 + xi) * n1 + x1];
     }
     __syncthreads();
-    cpx<float>* R = fft_stockham<float, -1>(A, Bf, nseq, n1, P.fd1, tw);
+    cpx<T>* R = fft_stockham<T, -1>(A, Bf, nseq, n1, P.fd1, tw);
     for (int t = threadIdx.x; t < C * ng * nx; t += blockDim.x) {
       const int xi = t % nx;
       const int q = t / nx;
@@ -514,7 +568,7 @@ __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, 
       Cc[c * ccs + (int64_t)j * n0 + x00 + xi] = R[(c * xb + xi) * n1 + P.col_k[j]];
     }
   } else {
-    for (int t = threadIdx.x; t < nseq * n1; t += blockDim.x) A[t] = {0.f, 0.f};
+    for (int t = threadIdx.x; t < nseq * n1; t += blockDim.x) A[t] = {T(0), T(0)};
     __syncthreads();
     for (int t = threadIdx.x; t < C * ng * nx; t += blockDim.x) {
       const int xi = t % nx;
@@ -524,7 +578,7 @@ __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, 
       A[(c * xb + xi) * n1 + P.col_k[j]] = Cc[c * ccs + (int64_t)j * n0 + x00 + xi];
     }
     __syncthreads();
-    cpx<float>* R = fft_stockham<float, +1>(A, Bf, nseq, n1, P.fd1, tw);
+    cpx<T>* R = fft_stockham<T, +1>(A, Bf, nseq, n1, P.fd1, tw);
     for (int t = threadIdx.x; t < C * nx * n1; t += blockDim.x) {
       const int x1 = t % n1;
       const int q = t / n1;
