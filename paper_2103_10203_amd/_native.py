@@ -244,6 +244,32 @@ class Plan:
             pass
 
 
+def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, workers: int = 4):
+    """Plans of many microstructures (mor_plan_create each), built from
+    `workers` host threads, each on a HIP stream of its own: a plan is a chain
+    of small launches and one host synchronisation, so several chains overlap
+    on the device.  M: one value or one per grid.  Plans come back in input
+    order and are complete (each construction synchronises its stream)."""
+    from concurrent.futures import ThreadPoolExecutor
+    torch = _torch()
+    grids = list(grids)
+    Ms = [int(M)] * len(grids) if np.isscalar(M) else [int(m) for m in M]
+    if len(Ms) != len(grids):
+        raise ValueError("one M per grid, or a single M")
+    workers = max(1, min(int(workers), len(grids)))
+    streams = [torch.cuda.Stream() for _ in range(workers)]
+    out = [None] * len(grids)
+
+    def work(w):
+        for i in range(w, len(grids), workers):
+            out[i] = Plan(grids[i], Ms[i], gamma_kind, stream=streams[w])
+
+    with ThreadPoolExecutor(workers) as ex:
+        for f in [ex.submit(work, w) for w in range(workers)]:
+            f.result()
+    return out
+
+
 @dataclass
 class SolveResult:
     status: int

@@ -66,3 +66,23 @@ def test_pattern_independent_of_material_and_deterministic():
     a = mor.Plan(g, 3277).pattern()
     b = mor.Plan(g, 3277).pattern()
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_concurrent_plan_construction_matches_sequential():
+    """make_plans (several host threads, one HIP stream each) gives the same
+    plans as one mor_plan_create after another: pattern, rank order and
+    coefficient order, on mixed 2D and 3D grids with one M per grid."""
+    import paper_2103_10203_amd as mor
+    gs = [synth.rsa_fibres(n, n, n / 32, n / 16, seed=300 + n, target_vf=0.35).g for n in (64, 128, 96, 256)]
+    gs += [synth.rsa_spheres(32, 32, 32, r_lo=4.0, r_hi=6.0, seed=5, target_vf=0.2).g]
+    gs = gs * 3
+    Ms = [int(math.ceil(0.05 * g.size)) for g in gs]
+    seq = [mor.Plan(g, M) for g, M in zip(gs, Ms)]
+    par = mor.make_plans(gs, Ms, workers=6)
+    assert len(par) == len(seq)
+    for a, b in zip(seq, par):
+        assert a.info == b.info
+        sa, ra = a.pattern()
+        sb, rb = b.pattern()
+        assert np.array_equal(sa, sb) and np.array_equal(ra, rb)
+        assert np.array_equal(a.coeff_index(), b.coeff_index())
