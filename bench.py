@@ -302,6 +302,8 @@ def main():
                     help="1: replay each chunk of iterations of the batched solves from a hipGraph")
     ap.add_argument("--schedule", choices=["grid", "persistent"], default="grid",
                     help="workgroup schedule of the iteration kernels")
+    ap.add_argument("--plan-threads", type=int, default=PLAN_WORKERS,
+                    help="host threads building the plans (1 under a kernel-tracing profiler)")
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the timings of the other configured workloads")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -353,7 +355,7 @@ def main():
     del seq
     torch.cuda.synchronize()
     t = time.perf_counter()
-    plans = mor.make_plans(gs, M_FREQ, workers=PLAN_WORKERS)
+    plans = mor.make_plans(gs, M_FREQ, workers=args.plan_threads)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t) * 1e3 / B
     plan_of = np.arange(B)
@@ -488,7 +490,7 @@ def main():
         },
         "plan_ms_per_rve": plan_ms,
         "plan_ms_per_rve_one_thread": plan_ms_seq,
-        "plan_threads": PLAN_WORKERS,
+        "plan_threads": args.plan_threads,
         "end_to_end_solves_per_s": 1.0 / (1.0 / value + plan_ms * 1e-3),
         "workload_gen_s": t_gen,
     }

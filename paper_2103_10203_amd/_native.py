@@ -257,6 +257,8 @@ def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, workers: int = 4):
     if len(Ms) != len(grids):
         raise ValueError("one M per grid, or a single M")
     workers = max(1, min(int(workers), len(grids)))
+    if workers == 1:  # in the calling thread, on its current stream
+        return [Plan(g, m, gamma_kind) for g, m in zip(grids, Ms)]
     streams = [torch.cuda.Stream() for _ in range(workers)]
     out = [None] * len(grids)
 
