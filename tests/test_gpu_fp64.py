@@ -131,3 +131,19 @@ def test_fp64_rejects_what_it_does_not_cover():
     with pytest.raises(mor.MorError) as e:
         mor.solve(plan, eb, native_phases(j2=True), 1e-8, precision=mor.PREC_FP64)
     assert e.value.status == mor.MOR_E_UNSUPPORTED
+
+
+def test_fp64_graph_replay_matches_eager():
+    """hipGraph replay of the FP64 iteration chunks gives the eager results
+    bit for bit (several replays per solve, eager solves in between)."""
+    mor = _mor()
+    g = synth.rsa_fibres(64, 64, 3, 5, seed=41, target_vf=0.35).g
+    plan = mor.Plan(g, 205)
+    ebs = synth.macro_strains(5, 3, 2e-3, seed=9)
+    eager = mor.solve(plan, ebs, native_phases(), 1e-10, precision=mor.PREC_FP64, check_every=4)
+    for _ in range(2):
+        graph = mor.solve(plan, ebs, native_phases(), 1e-10, precision=mor.PREC_FP64, check_every=4, use_graph=1)
+        assert np.array_equal(graph.eff_stress, eager.eff_stress)
+        assert np.array_equal(graph.iterations, eager.iterations)
+        again = mor.solve(plan, ebs, native_phases(), 1e-10, precision=mor.PREC_FP64, check_every=4)
+        assert np.array_equal(again.eff_stress, eager.eff_stress)
