@@ -48,11 +48,16 @@ template <> struct RowCfg<3, 128, 4> { static constexpr int RL = 4, RB = 8;  usi
 template <> struct RowCfg<3, 128, 5> { static constexpr int RL = 8, RB = 4;  using RA = RList<16>; };
 template <> struct RowCfg<3, 128, 6> { static constexpr int RL = 8, RB = 16, PS = 5; using RA = RList<16>; };
 template <> struct RowVar<3, 128> { static constexpr int count = 7; };
-template <> struct RowCfg<3, 192, 0> { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4, 3>; };
+template <> struct RowCfg<3, 192, 0> { static constexpr int RL = 6, RB = 16; using RA = RList<8, 4>; };
 template <> struct RowCfg<3, 192, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<8, 3>; };
 template <> struct RowCfg<3, 192, 2> { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4, 3>; };
 template <> struct RowCfg<3, 192, 3> { static constexpr int RL = 4, RB = 8;  using RA = RList<3, 4, 4>; };
-template <> struct RowVar<3, 192> { static constexpr int count = 4; };
+template <> struct RowCfg<3, 192, 4> { static constexpr int RL = 8, RB = 16; using RA = RList<8, 3>; };
+template <> struct RowCfg<3, 192, 5> { static constexpr int RL = 4, RB = 16; using RA = RList<4, 4, 3>; };
+template <> struct RowCfg<3, 192, 6> { static constexpr int RL = 6, RB = 8;  using RA = RList<4, 8>; };
+template <> struct RowCfg<3, 192, 7> { static constexpr int RL = 6, RB = 32; using RA = RList<8, 4>; };
+template <> struct RowCfg<3, 192, 8> { static constexpr int RL = 6, RB = 8;  using RA = RList<8, 4>; };
+template <> struct RowVar<3, 192> { static constexpr int count = 9; };
 template <> struct RowCfg<3, 256, 0> { static constexpr int RL = 8, RB = 8;  using RA = RList<4, 8>; };
 template <> struct RowCfg<3, 256, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<16, 2>; };
 template <> struct RowCfg<3, 256, 2> { static constexpr int RL = 8, RB = 16; using RA = RList<4, 8>; };
@@ -415,6 +420,11 @@ template <> struct ColCfg<3, 256, 5> { static constexpr int RF = 16, CB = 8; usi
 template <> struct ColCfg<3, 256, 6> { static constexpr int RF = 8,  CB = 2, W = 8; using FA = RList<8, 4>; };
 template <> struct ColVar<3, 256> { static constexpr int count = 7; };
 template <> struct ColCfg<3, 384, 0> { static constexpr int RF = 6,  CB = 1; using FA = RList<8, 8>; };
+template <> struct ColCfg<3, 384, 1> { static constexpr int RF = 6,  CB = 2; using FA = RList<8, 8>; };
+template <> struct ColCfg<3, 384, 2> { static constexpr int RF = 8,  CB = 4; using FA = RList<8, 6>; };
+template <> struct ColCfg<3, 384, 3> { static constexpr int RF = 16, CB = 8; using FA = RList<8, 3>; };
+template <> struct ColCfg<3, 384, 4> { static constexpr int RF = 6,  CB = 4; using FA = RList<8, 8>; };
+template <> struct ColVar<3, 384> { static constexpr int count = 5; };
 template <> struct ColCfg<3, 512, 0> { static constexpr int RF = 8,  CB = 1; using FA = RList<8, 8>; };
 template <> struct ColCfg<3, 512, 1> { static constexpr int RF = 16, CB = 4; using FA = RList<8, 4>; };
 template <> struct ColCfg<3, 512, 2> { static constexpr int RF = 8,  CB = 2; using FA = RList<8, 8>; };

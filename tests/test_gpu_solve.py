@@ -279,7 +279,7 @@ def test_row_kernel_variants_3d(shape):
         mor.tune_set(3, L, keep)
 
 
-@pytest.mark.parametrize("shape", [(64, 64), (128, 128), (256, 256), (512, 64), (128, 16, 16)])
+@pytest.mark.parametrize("shape", [(64, 64), (128, 128), (256, 256), (384, 96), (512, 64), (128, 16, 16)])
 def test_col_kernel_variants(shape):
     """Every column-kernel variant (axis-0 FFT factorisation, columns per
     workgroup) against the FP64 oracle."""
