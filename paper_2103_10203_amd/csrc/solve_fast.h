@@ -29,9 +29,9 @@ template <int C, int NH>
 struct RowVar {
   static constexpr int count = 1;
 };
-template <> struct RowCfg<3, 32, 0>  { static constexpr int RL = 4, RB = 32; using RA = RList<8>; };
+template <> struct RowCfg<3, 32, 0>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
 template <> struct RowCfg<3, 32, 1>  { static constexpr int RL = 8, RB = 32; using RA = RList<4>; };
-template <> struct RowCfg<3, 32, 2>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
+template <> struct RowCfg<3, 32, 2>  { static constexpr int RL = 4, RB = 32; using RA = RList<8>; };
 template <> struct RowVar<3, 32> { static constexpr int count = 3; };
 template <> struct RowCfg<3, 64, 0>  { static constexpr int RL = 8, RB = 16; using RA = RList<8>; };
 template <> struct RowCfg<3, 64, 1>  { static constexpr int RL = 8, RB = 8;  using RA = RList<8>; };
