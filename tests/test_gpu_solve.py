@@ -344,3 +344,31 @@ def test_persistent_schedule_matches_grid():
     o2 = mor.solve_path(plan2, path, native_phases(j2=True), 1e-6, s2, schedule=mor.SCHED_PERSISTENT)
     assert np.array_equal(o1.eff_stress, o2.eff_stress)
     assert bool((s1 == s2).all())
+
+
+@pytest.mark.parametrize("shape", [(72, 256), (36, 128), (24, 64), (36, 512), (18, 384)])
+def test_ragged_row_tiles(shape):
+    """Row counts that are not a multiple of the row kernel's rows per
+    workgroup (the last workgroup's spare rows gather neighbouring or
+    out-of-range entries and must never be stored): every row variant of the
+    size against the FP64 oracle."""
+    mor = _mor()
+    n0, n1 = shape
+    g = synth.rsa_fibres(n0, n1, min(shape) / 10, min(shape) / 6, seed=n0 * 7 + n1, target_vf=0.3).g
+    eb = [1.5e-3, -5e-4, 8e-4]
+    M = int(math.ceil(0.05 * g.size))
+    _, ref = oracle_reduced(g, eb, M, tol=1e-11)
+    sref = stress_comps(ref.sigma_bar, 2)
+    e_ref, _ = _fields_from_oracle(ref, 2)
+    plan = mor.Plan(g, M)
+    keep = mor.tune_get(2, n1)
+    try:
+        for v in range(mor.tune_variants(2, n1)):
+            mor.tune_set(2, n1, v)
+            out = mor.solve(plan, np.array([eb]), native_phases(), 1e-7, want_fields=True)
+            assert out.status == mor.MOR_OK
+            err = np.max(np.abs(out.eff_stress[0] - sref)) / np.max(np.abs(sref))
+            assert err < 1e-5, (v, err)
+            assert rel_l2(out.strain[0].cpu().numpy(), e_ref) < 1e-4, v
+    finally:
+        mor.tune_set(2, n1, keep)
