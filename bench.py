@@ -254,6 +254,19 @@ def other_configs(mor, ph):
     res["uneven_4096"] = {"workload": "4096 RVEs round robin over 128², 256², 384² fibre RVEs (vf 0.35), M = 5 %, "
                                       "one mor_solve_multi call, residual 1e-6",
                           "solves_per_s": B / el, "ms": el * 1e3, "mean_iterations": float(out.iterations.mean())}
+    # the same after the autotuner has measured every row and column variant of
+    # the three sizes on this workload, with the iteration chunks replayed from
+    # a captured hipGraph; the selections are put back afterwards
+    keep = {(k, n): mor.tune_get(2, n, k) for k in (mor.KERNEL_ROW, mor.KERNEL_COL) for n in (128, 256, 384)}
+    t = time.perf_counter()
+    mor.autotune(plans, po, ebs, ph, TOL, reps=2)
+    t_tune = time.perf_counter() - t
+    picked = {f"{'row' if k == mor.KERNEL_ROW else 'col'}{n}": mor.tune_get(2, n, k) for (k, n) in keep}
+    el, out = timed(lambda: mor.solve_multi(plans, po, ebs, ph, TOL, use_graph=1), 2)
+    res["uneven_4096_autotuned_graph"] = {"solves_per_s": B / el, "ms": el * 1e3, "tune_s": t_tune,
+                                          "variants": picked, "mean_iterations": float(out.iterations.mean())}
+    for (k, n), v in keep.items():
+        mor.tune_set(2, n, v, k)
     del plans
     g3 = synth.rsa_spheres(128, 128, 128, 8.0, 14.0, seed=7, target_vf=0.25).g
     p3 = mor.Plan(g3, int(math.ceil(0.02 * g3.size)))
