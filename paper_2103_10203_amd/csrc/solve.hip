@@ -672,13 +672,18 @@ void launch_dft_stage(SolveCtx& cx, Group& g, int rows, int L) {
   else dft_forward<DFT_F32>(cx, g, C, rows);
 }
 
-// Generic row kernel in FP64 (Hooke phases only: setup rejects J2 with FP64).
+// Generic row kernel in FP64 (Hooke phases only: setup rejects J2 with FP64,
+// and the J2 instantiation reports it rather than launching nothing).
 template <int C, int MODE, int MAT>
-void launch_row64(SolveCtx& cx, Group& g, dim3 gr, size_t shm, float* eps, float* sig) {
+mor_status launch_row64(SolveCtx& cx, Group& g, dim3 gr, size_t shm, float* eps, float* sig) {
   if constexpr (MAT == MAT_HOOKE) {
     k_row<C, MODE, MAT_HOOKE, double, MatDev64><<<gr, 256, shm, cx.st>>>(
         cx.d_plans, g.d_list, cx.d_st, cx.yl64(), cx.off, cx.mat64, nullptr, eps, sig,
         MODE == MODE_FINAL ? cx.d_sigpart : nullptr, g.rb);
+    return MOR_OK;
+  } else {
+    mor_set_error("MOR_PREC_FP64 supports Hooke phases only (J2 runs in FP32)");
+    return MOR_E_UNSUPPORTED;
   }
 }
 
@@ -699,9 +704,10 @@ mor_status launch_iter(SolveCtx& cx, Group& g) {
   ev_begin(cx, PK_ROW, &a);
   if (cx.dft)
     launch_dft_stage<C, MAT>(cx, g, rows, nlen);
-  else if (cx.fp64)
-    launch_row64<C, MODE_ITER, MAT>(cx, g, gr, 2 * shr, nullptr, nullptr);
-  else if (g.fast_row && pers)
+  else if (cx.fp64) {
+    const mor_status s64 = launch_row64<C, MODE_ITER, MAT>(cx, g, gr, 2 * shr, nullptr, nullptr);
+    if (s64 != MOR_OK) return s64;
+  } else if (g.fast_row && pers)
     row_persist<C, MAT>(cx, g);
   else if (g.fast_row)
     row_fast<C, MODE_ITER, MAT>(cx, g, nullptr, nullptr);
@@ -760,9 +766,10 @@ mor_status launch_final(SolveCtx& cx, Group& g, float* eps, float* sig) {
     dim3 gp((rows + kDftRb - 1) / kDftRb, (unsigned)g.rves.size());
     k_dft_point<C, MODE_FINAL, MAT><<<gp, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.off, cx.mat, cx.d_dfte,
                                                            cx.d_jstate, eps, sig, cx.d_sigpart, kDftRb);
-  } else if (cx.fp64)
-    launch_row64<C, MODE_FINAL, MAT>(cx, g, gr, 2 * shr, eps, sig);
-  else if (g.fast_row)
+  } else if (cx.fp64) {
+    const mor_status s64 = launch_row64<C, MODE_FINAL, MAT>(cx, g, gr, 2 * shr, eps, sig);
+    if (s64 != MOR_OK) return s64;
+  } else if (g.fast_row)
     row_fast<C, MODE_FINAL, MAT>(cx, g, eps, sig);
   else
     k_row<C, MODE_FINAL, MAT><<<gr, 256, shr, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.mat,
@@ -1106,8 +1113,10 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
     int64_t tot = 0;
     for (int64_t b = 0; b < cx.B; ++b) tot += (int64_t)cx.C * cx.ncoef_h[b];
     if (cx.fp64) {
-      k_round_c64<<<(unsigned)((tot + 255) / 256), 256, 0, cx.st>>>(cx.coef64(), (cpx<float>*)out->coeffs, tot);
-      MOR_LAUNCH_CHECK("round coefficients");
+      if (tot > 0) {
+        k_round_c64<<<(unsigned)((tot + 255) / 256), 256, 0, cx.st>>>(cx.coef64(), (cpx<float>*)out->coeffs, tot);
+        MOR_LAUNCH_CHECK("round coefficients");
+      }
     } else {
       MOR_HIP_TRY(hipMemcpyAsync(out->coeffs, cx.d_coef, tot * sizeof(cpx<float>), hipMemcpyDeviceToDevice, cx.st));
     }
