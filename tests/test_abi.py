@@ -85,3 +85,21 @@ def test_tune_api_host_side():
         mor.tune_variants(2, 100, mor.KERNEL_COL)
     with pytest.raises(mor.MorError):
         mor.tune_variants(2, 256, 7)
+
+
+def test_precision_constants_match_header():
+    """The binding's precision values are the header's enum (FP32, BF16X3, FP64)."""
+    import paper_2103_10203_amd as mor
+    src = open(os.path.join(ROOT, "include", "mor.h")).read()
+    m = re.search(r"enum\s*\{\s*MOR_PREC_FP32\s*=\s*(\d+),\s*MOR_PREC_BF16X3\s*=\s*(\d+),\s*MOR_PREC_FP64\s*=\s*(\d+)\s*\}",
+                  src)
+    assert m, "precision enum not found"
+    assert (mor.PREC_FP32, mor.PREC_BF16X3, mor.PREC_FP64) == tuple(int(x) for x in m.groups())
+
+
+def test_make_plans_checks_its_arguments():
+    import paper_2103_10203_amd as mor
+    g = np.zeros((16, 16), np.uint8)
+    with pytest.raises(ValueError):
+        mor.make_plans([g, g], [5])
+    assert mor.make_plans([], 5) == []
