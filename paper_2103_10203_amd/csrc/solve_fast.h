@@ -618,11 +618,20 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
     atomicOr(&pmask[jj][k0 >> 5], 1u << (k0 & 31));
   }
   __syncthreads();  // the pattern marks are complete
-  // clear the other positions of every sequence (pad slots are never read)
-  for (int t = tid; t < NSEQ * N0; t += NT) {
-    const int sq = t / N0, k = t % N0;
-    const int jj = sq % CB;
-    if (!((pmask[jj][k >> 5] >> (k & 31)) & 1u)) buf[sq * SS + pad16(k)] = {0.f, 0.f};
+  // clear the other positions of every sequence (pad slots are never read):
+  // thread (s, i) of the transform takes positions i + m TS of its sequence,
+  // so the offsets are compile-time strides from one per-thread base
+  {
+    // thread indices re-derived here rather than kept live across the Green step
+    const int t2 = opaque_tid();
+    const int s2 = t2 / TS, i2 = t2 % TS;
+    cpx<float>* seqb = buf + s2 * SS;
+    const uint32_t* pm = pmask[s2 % CB];
+#pragma unroll
+    for (int m = 0; m < RF; ++m) {
+      const int k = i2 + m * TS;
+      if (!((pm[k >> 5] >> (k & 31)) & 1u)) seqb[pad16(k)] = {0.f, 0.f};
+    }
   }
   __syncthreads();
   // step d), axis 0: inverse passes, the last one straight to global memory
