@@ -230,8 +230,9 @@ def train_network(mor, ph, ntrain, nslots, epochs, log):
 
 def other_configs(mor, ph):
     """Throughput of the other configured workloads (one timed call each,
-    after one untimed call): the 4096-RVE uneven batch, 3D 128^3 with the FFT
-    and the split-bf16 MFMA DFT, and the 512^2 J2 load path."""
+    after one untimed call): the 4096-RVE uneven batch (also autotuned with
+    hipGraph replay), 3D 128^3 with the FFT and the split-bf16 MFMA DFT, the
+    64^2 disk in FP64 to 1e-8, and the 512^2 J2 load path."""
     import torch
 
     def timed(fn, reps=1):
@@ -278,6 +279,17 @@ def other_configs(mor, ph):
                                   "solves_per_s": 8 / el, "ms": el * 1e3,
                                   "mean_iterations": float(out.iterations.mean())}
     del p3
+    # the paper's 64^2 centred disk (M = 205) to its residual 1e-8, FP64 throughout
+    n1 = 64
+    g1 = synth.disk(n1, n1, math.sqrt(0.3 * n1 * n1 / math.pi))
+    p1 = mor.Plan(g1, 205)
+    e1 = synth.macro_strains(256, 3, 1e-3, seed=64)
+    el, out = timed(lambda: mor.solve(p1, e1, ph, 1e-8, precision=mor.PREC_FP64))
+    res["disk64_fp64_1e-8"] = {"workload": "64² centred disk (vf 0.3), M = 205, 256 macro strains in one call, "
+                                           "FP64 throughout, residual 1e-8",
+                               "solves_per_s": 256 / el, "ms": el * 1e3,
+                               "mean_iterations": float(out.iterations.mean())}
+    del p1
     g2 = synth.rsa_fibres(512, 512, 20.0, 40.0, seed=2103, target_vf=0.40).g
     p2 = mor.Plan(g2, int(math.ceil(0.05 * g2.size)))
     path = np.stack([[0.02 * (k + 1) / 20, 0.0, 0.0] for k in range(20)])
