@@ -195,8 +195,12 @@ __device__ __forceinline__ void pass_twiddle(cpx<float>* v, int k, const cpx<flo
 
 // One in-place Stockham pass over NS sequences (base + s*SS, positions
 // padded by padp<PS>) by NT threads.  TW = false skips the pass twiddles (the
-// producer of the pass's input has applied them).
-template <int N, int R, int P, int SIGN, int NS, int SS, int NT, int TWS, int PS = 4, bool TW = true>
+// producer of the pass's input has applied them).  Work item t is butterfly
+// i = t % NB of sequence s = t / NB, or with SF (sequence fastest) butterfly
+// t / NS of sequence t % NS: neighbouring lanes then take the same butterfly
+// of neighbouring sequences, which an odd sequence stride spreads over all
+// banks where the butterflies of one sequence would collide.
+template <int N, int R, int P, int SIGN, int NS, int SS, int NT, int TWS, int PS = 4, bool TW = true, bool SF = false>
 __device__ __forceinline__ void lds_pass(cpx<float>* buf, const cpx<float>* tw, int tid) {
   constexpr int NB = N / R;
   constexpr int TOTAL = NS * NB;
@@ -206,7 +210,8 @@ __device__ __forceinline__ void lds_pass(cpx<float>* buf, const cpx<float>* tw, 
   for (int q = 0; q < PER; ++q) {
     const int t = tid + q * NT;
     if (TOTAL % NT == 0 || t < TOTAL) {
-      const int s = t / NB, i = t % NB;
+      // (t / NS) % NB == t / NS here; the modulo tells the compiler i < NB
+      const int s = SF ? t % NS : t / NB, i = SF ? (t / NS) % NB : t % NB;
       const int k = i % P;
       const cpx<float>* src = buf + s * SS;
 #pragma unroll
@@ -220,7 +225,7 @@ __device__ __forceinline__ void lds_pass(cpx<float>* buf, const cpx<float>* tw, 
   for (int q = 0; q < PER; ++q) {
     const int t = tid + q * NT;
     if (TOTAL % NT == 0 || t < TOTAL) {
-      const int s = t / NB, i = t % NB;
+      const int s = SF ? t % NS : t / NB, i = SF ? (t / NS) % NB : t % NB;
       const int k = i % P;
       cpx<float>* dst = buf + s * SS;
       const int o = (i - k) * R + k;
@@ -235,13 +240,13 @@ template <int... Rs>
 struct RList {};
 
 // Runs the passes of RList in order starting with span P.
-template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS, int PS = 4>
+template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS, int PS = 4, bool SF = false>
 __device__ __forceinline__ void lds_passes(cpx<float>*, const cpx<float>*, int, RList<>) {}
 
-template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS, int PS = 4, int R, int... Rest>
+template <int N, int SIGN, int P, int NS, int SS, int NT, int TWS, int PS = 4, bool SF = false, int R, int... Rest>
 __device__ __forceinline__ void lds_passes(cpx<float>* buf, const cpx<float>* tw, int tid, RList<R, Rest...>) {
-  lds_pass<N, R, P, SIGN, NS, SS, NT, TWS, PS>(buf, tw, tid);
-  lds_passes<N, SIGN, P * R, NS, SS, NT, TWS, PS>(buf, tw, tid, RList<Rest...>{});
+  lds_pass<N, R, P, SIGN, NS, SS, NT, TWS, PS, true, SF>(buf, tw, tid);
+  lds_passes<N, SIGN, P * R, NS, SS, NT, TWS, PS, SF>(buf, tw, tid, RList<Rest...>{});
 }
 
 // Single radix of a one-element list (0 otherwise).

@@ -86,6 +86,18 @@ struct PadOf<Cfg, decltype((void)Cfg::PS)> {
   static constexpr int v = Cfg::PS;
 };
 
+// Minimum waves per SIMD a variant asks the register allocator for (1: no
+// constraint; set where it fits the registers without spills and measured
+// faster).
+template <typename Cfg, typename = void>
+struct WavesOf {
+  static constexpr int v = 1;
+};
+template <typename Cfg>
+struct WavesOf<Cfg, decltype((void)Cfg::W)> {
+  static constexpr int v = Cfg::W;
+};
+
 template <int C, int NH, int V>
 constexpr int row_threads() {
   return RowCfg<C, NH, V>::RB * (NH / RowCfg<C, NH, V>::RL);
@@ -238,7 +250,7 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
     }
     if (c + 1 < C) gather(c + 1);
     __syncthreads();
-    fftr::lds_passes<NH, +1, 1, RB, SS, NT, 2, PS>(buf, T, tid, typename Cfg::RA{});
+    fftr::lds_passes<NH, +1, 1, RB, SS, NT, 2, PS, true>(buf, T, tid, typename Cfg::RA{});
     // register pass: last inverse stage (radix RL, span TR)
     {
       const cpx<float>* src = buf + r * SS;
@@ -343,10 +355,10 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
     }
     __syncthreads();
     if constexpr (kPreTwiddle) {
-      fftr::lds_pass<NH, R2, RL, -1, RB, SS, NT, 2, PS, false>(buf, T, tid);
+      fftr::lds_pass<NH, R2, RL, -1, RB, SS, NT, 2, PS, false, true>(buf, T, tid);
     } else {
-      fftr::lds_passes<NH, -1, RL, RB, SS, NT, 2, PS>(buf, T, tid,
-                                                  typename fftr::Rev<typename Cfg::RA, RList<>>::type{});
+      fftr::lds_passes<NH, -1, RL, RB, SS, NT, 2, PS, true>(buf, T, tid,
+                                                        typename fftr::Rev<typename Cfg::RA, RList<>>::type{});
     }
     // unpack X[k] = (Z[k] + conj Z[NH-k]) / 2 - i T[k] (Z[k] - conj Z[NH-k]) / 2
     // at the sampled frequencies and store them
@@ -368,7 +380,8 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
 
 // Grid schedule: workgroup (tile, list position).
 template <int C, int NH, int V, int MODE, int MAT>
-__global__ __launch_bounds__((row_threads<C, NH, V>())) void k_row_fast(
+__global__ __launch_bounds__((row_threads<C, NH, V>())) __attribute__((amdgpu_waves_per_eu(
+    MAT == MAT_HOOKE ? WavesOf<RowCfg<C, NH, V>>::v : 1))) void k_row_fast(
     const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
     cpx<float>* __restrict__ Yl, Offs off, MatDev mat, float* __restrict__ jstate, float* __restrict__ out_eps,
     float* __restrict__ out_sig, double* __restrict__ sig_part) {
@@ -433,18 +446,6 @@ template <> struct ColCfg<6, 64, 0>  { static constexpr int RF = 8,  CB = 4, W =
 template <> struct ColCfg<6, 128, 0> { static constexpr int RF = 16, CB = 4; using FA = RList<8>; };
 template <> struct ColCfg<6, 128, 1> { static constexpr int RF = 8,  CB = 2; using FA = RList<4, 4>; };
 template <> struct ColVar<6, 128> { static constexpr int count = 2; };
-
-// Minimum waves per SIMD a variant asks the register allocator for (1: no
-// constraint; set where it fits the registers without spills and measured
-// faster).
-template <typename Cfg, typename = void>
-struct WavesOf {
-  static constexpr int v = 1;
-};
-template <typename Cfg>
-struct WavesOf<Cfg, decltype((void)Cfg::W)> {
-  static constexpr int v = Cfg::W;
-};
 
 template <int C, int N0, int V>
 constexpr int col_threads() {
