@@ -99,7 +99,6 @@ def cpu_baseline(gs, ebs, budget_s=15.0):
 
 
 SOLVE_SOURCES = ("fft_lds.h", "fft_reg.h", "mor_internal.h", "solve_fast.h", "solve_kernels.h", "solve.hip")
-PLAN_WORKERS = 8  # host threads building plans (make_plans)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "solve_256x256_m3277_b1024_hbm_traffic.txt")
 
 
@@ -247,7 +246,7 @@ def other_configs(mor, ph):
     res = {}
     gs = [synth.rsa_fibres(n, n, n / 32, n / 16, seed=seed, target_vf=0.35).g
           for n, seed in ((128, 31), (256, 32), (384, 33))]
-    plans = [mor.Plan(g, int(math.ceil(0.05 * g.size))) for g in gs]
+    plans = mor.make_plans(gs, [int(math.ceil(0.05 * g.size)) for g in gs])
     B = 4096
     po = np.arange(B) % 3
     ebs = synth.macro_strains(B, 3, 5e-3, seed=2026)
@@ -327,8 +326,6 @@ def main():
                     help="1: replay each chunk of iterations of the batched solves from a hipGraph")
     ap.add_argument("--schedule", choices=["grid", "persistent"], default="grid",
                     help="workgroup schedule of the iteration kernels")
-    ap.add_argument("--plan-threads", type=int, default=PLAN_WORKERS,
-                    help="host threads building the plans (1 under a kernel-tracing profiler)")
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the timings of the other configured workloads")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -368,11 +365,10 @@ def main():
     ph = phases()
     log(f"generated {B} held-out RVEs in {t_gen:.1f} s")
 
-    # plans: one mor_plan_create per RVE, from PLAN_WORKERS host threads on
-    # streams of their own (end to end); the one-thread rate on a sample is
-    # reported beside it
+    # plans: all RVEs in one batched construction (end to end); one
+    # mor_plan_create per RVE on a sample is reported beside it
     nseq = min(B, 128)
-    warmup_plans = [mor.Plan(g, M_FREQ) for g in gs[:4]]  # first launches load the plan kernels
+    warmup_plans = mor.make_plans(gs[:4], M_FREQ)  # first launches load the plan kernels
     del warmup_plans
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -382,7 +378,7 @@ def main():
     del seq
     torch.cuda.synchronize()
     t = time.perf_counter()
-    plans = mor.make_plans(gs, M_FREQ, workers=args.plan_threads)
+    plans = mor.make_plans(gs, M_FREQ)
     torch.cuda.synchronize()
     plan_ms = (time.perf_counter() - t) * 1e3 / B
     plan_of = np.arange(B)
@@ -516,8 +512,7 @@ def main():
             "learned": itstats(learned["out"].iterations) if learned else None,
         },
         "plan_ms_per_rve": plan_ms,
-        "plan_ms_per_rve_one_thread": plan_ms_seq,
-        "plan_threads": args.plan_threads,
+        "plan_ms_per_rve_single_calls": plan_ms_seq,
         "end_to_end_solves_per_s": 1.0 / (1.0 / value + plan_ms * 1e-3),
         "workload_gen_s": t_gen,
     }

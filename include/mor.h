@@ -98,6 +98,28 @@ typedef struct {
 mor_status mor_plan_create(const mor_grid* grid, const uint8_t* phase_map, int64_t M,
                            const mor_plan_opts* opts, mor_plan_t* out);
 
+/*
+ * mor_plan_create_batch - mor_plan_create for `count` microstructures on one
+ * grid (Sec. 4.2, one pattern per microstructure, as for the integration
+ * points of an FE-FFT computation, Sec. 1).  Each step of the construction
+ * runs as one launch over the whole batch, so the cost per plan is device
+ * work rather than launch and synchronisation latency.  The plans are the
+ * ones mor_plan_create returns for each map and M, bit for bit.
+ *
+ *   grid        as for mor_plan_create, shared by every map.
+ *   count       >= 0; 0 creates nothing and returns MOR_OK.
+ *   phase_maps  host uint8 [count][N], C order, values 0 or 1.
+ *   M           host int64 [count], each in [1, N].
+ *   opts        NULL for defaults (gamma_kind and stream apply to all).
+ *   out         host [count]; receives the plans.  On any error every
+ *               entry is NULL: plans already built are destroyed.
+ * Device scratch is drawn in chunks of microstructures of at most
+ * 512 MiB (environment variable MOR_PLAN_SCRATCH_BYTES overrides the size),
+ * held in the library's block pool for reuse.
+ */
+mor_status mor_plan_create_batch(const mor_grid* grid, int64_t count, const uint8_t* phase_maps,
+                                 const int64_t* M, const mor_plan_opts* opts, mor_plan_t* out);
+
 mor_status mor_plan_get_info(mor_plan_t plan, mor_plan_info* info);
 
 /*

@@ -76,6 +76,8 @@ class mor_outputs(ct.Structure):
 _SIGS = {
     "mor_plan_create": (ct.c_int, [ct.POINTER(mor_grid), ct.c_void_p, ct.c_int64, ct.POINTER(mor_plan_opts),
                                    ct.POINTER(ct.c_void_p)]),
+    "mor_plan_create_batch": (ct.c_int, [ct.POINTER(mor_grid), ct.c_int64, ct.c_void_p, ct.c_void_p,
+                                         ct.POINTER(mor_plan_opts), ct.c_void_p]),
     "mor_plan_get_info": (ct.c_int, [ct.c_void_p, ct.POINTER(mor_plan_info)]),
     "mor_plan_pattern": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.POINTER(ct.c_int64)]),
     "mor_plan_coeff_index": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64]),
@@ -177,23 +179,34 @@ def _phases(phases):
     return arr
 
 
+def _grid_of(shape):
+    if len(shape) not in (2, 3):
+        raise ValueError("phase map must be 2D or 3D")
+    grid = mor_grid()
+    grid.ndim = len(shape)
+    for a in range(3):
+        grid.n[a] = shape[a] if a < len(shape) else 1
+    return grid
+
+
 class Plan:
     """Adapted sampling pattern of one microstructure (mor_plan_create)."""
 
-    def __init__(self, g: np.ndarray, M: int, gamma_kind: int = GAMMA_ROTATED, stream=None):
+    def __init__(self, g: np.ndarray, M: int, gamma_kind: int = GAMMA_ROTATED, stream=None, _handle=None):
+        if _handle is not None:  # a plan from mor_plan_create_batch (make_plans)
+            self._adopt(_handle, tuple(g))
+            return
         g = np.ascontiguousarray(g, dtype=np.uint8)
-        if g.ndim not in (2, 3):
-            raise ValueError("phase map must be 2D or 3D")
-        grid = mor_grid()
-        grid.ndim = g.ndim
-        for a in range(3):
-            grid.n[a] = g.shape[a] if a < g.ndim else 1
+        grid = _grid_of(g.shape)
         opts = mor_plan_opts(gamma_kind, 0, _stream_ptr(stream))
         h = ct.c_void_p()
         _check(lib.mor_plan_create(ct.byref(grid), _np_ptr(g), int(M), ct.byref(opts), ct.byref(h)))
+        self._adopt(h, g.shape)
+
+    def _adopt(self, h, shape):
         self._h = h
-        self.shape = g.shape
-        self.ndim = g.ndim
+        self.shape = tuple(shape)
+        self.ndim = len(shape)
         inf = mor_plan_info()
         _check(lib.mor_plan_get_info(self._h, ct.byref(inf)))
         self.info = {k: getattr(inf, k) for k, _ in mor_plan_info._fields_}
@@ -244,31 +257,30 @@ class Plan:
             pass
 
 
-def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, workers: int = 4):
-    """Plans of many microstructures (mor_plan_create each), built from
-    `workers` host threads, each on a HIP stream of its own: a plan is a chain
-    of small launches and one host synchronisation, so several chains overlap
-    on the device.  M: one value or one per grid.  Plans come back in input
-    order and are complete (each construction synchronises its stream)."""
-    from concurrent.futures import ThreadPoolExecutor
-    torch = _torch()
-    grids = list(grids)
+def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, stream=None):
+    """Plans of many microstructures: one mor_plan_create_batch call for all
+    maps of the same shape, so the construction runs as a few launches over
+    the whole group instead of a chain of small launches per map.  M: one
+    value or one per map.  Plans come back in input order, identical to
+    Plan(g, M) of each map."""
+    grids = [np.ascontiguousarray(g, dtype=np.uint8) for g in grids]
     Ms = [int(M)] * len(grids) if np.isscalar(M) else [int(m) for m in M]
     if len(Ms) != len(grids):
         raise ValueError("one M per grid, or a single M")
-    workers = max(1, min(int(workers), len(grids)))
-    if workers == 1:  # in the calling thread, on its current stream
-        return [Plan(g, m, gamma_kind) for g, m in zip(grids, Ms)]
-    streams = [torch.cuda.Stream() for _ in range(workers)]
+    groups = {}
+    for i, g in enumerate(grids):
+        groups.setdefault(g.shape, []).append(i)
     out = [None] * len(grids)
-
-    def work(w):
-        for i in range(w, len(grids), workers):
-            out[i] = Plan(grids[i], Ms[i], gamma_kind, stream=streams[w])
-
-    with ThreadPoolExecutor(workers) as ex:
-        for f in [ex.submit(work, w) for w in range(workers)]:
-            f.result()
+    opts = mor_plan_opts(gamma_kind, 0, _stream_ptr(stream))
+    for shape, idx in groups.items():
+        grid = _grid_of(shape)
+        maps = np.stack([grids[i] for i in idx])
+        marr = np.array([Ms[i] for i in idx], np.int64)
+        hs = (ct.c_void_p * len(idx))()
+        _check(lib.mor_plan_create_batch(ct.byref(grid), len(idx), _np_ptr(maps), _np_ptr(marr), ct.byref(opts),
+                                         ct.cast(hs, ct.c_void_p)))
+        for j, i in enumerate(idx):
+            out[i] = Plan(shape, 0, _handle=ct.c_void_p(hs[j]))
     return out
 
 

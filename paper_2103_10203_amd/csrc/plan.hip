@@ -15,6 +15,8 @@
 #include <cmath>
 #include <cstring>
 #include <vector>
+#include <string>
+#include <cstdlib>
 
 #include "mor_internal.h"
 
@@ -92,6 +94,40 @@ __device__ int block_excl_scan(int v, int* lds, int* total) {
   return res;
 }
 
+// Per-plan device destinations of a batched construction (one entry per
+// microstructure; workgroups find theirs from the batch index).
+struct PlanPtrs {
+  uint8_t* g;
+  int64_t* rank;
+  int64_t* slot_rep;
+  cpx<float>* slot_ghat;
+  int64_t* sorted;
+  int32_t* ints;
+  int64_t* coef_lin;
+  float* coef_n;
+  double* coef_n64;
+  uint8_t* coef_flag;
+  int32_t* coef_slot;
+  cpx<float>* tw;
+  cpx<double>* tw64;
+  PlanDev* dev;
+  int64_t M, nslots;
+  int32_t ncol, nlast;
+};
+
+// Offsets of the integer tables inside PlanPtrs::ints (the same for every
+// plan of a grid): col_k | col_last | col_off | last_k | last_off | coef_k0.
+struct IntLayout {
+  int32_t col_k, col_last, col_off, last_k, last_off, coef_k0;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T>* plan_tw(const PlanPtrs& q);
+template <>
+__device__ __forceinline__ cpx<float>* plan_tw<float>(const PlanPtrs& q) { return q.tw; }
+template <>
+__device__ __forceinline__ cpx<double>* plan_tw<double>(const PlanPtrs& q) { return q.tw64; }
+
 // ------------------------------------------------------------------ kernels
 
 __global__ void k_twiddle_f64(cpx<double>* tw, int n) {
@@ -106,7 +142,8 @@ __global__ void k_twiddle_f64(cpx<double>* tw, int n) {
 // twh [nh] | rtw [nl], each exp(-2 pi i t / length) evaluated in FP64 (and
 // rounded for the FP32 tables).
 template <typename T>
-__global__ void k_twiddle4(cpx<T>* tw, int n0, int n1, int nh, int nl) {
+__global__ void k_twiddle4(const PlanPtrs* __restrict__ pp, int n0, int n1, int nh, int nl) {
+  cpx<T>* __restrict__ tw = plan_tw<T>(pp[blockIdx.y]);
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int n;
   int u = t;
@@ -126,17 +163,21 @@ __global__ void k_twiddle4(cpx<T>* tw, int n0, int n1, int nh, int nl) {
   tw[t] = {(T)c, (T)(-s)};
 }
 
-__global__ void k_g_to_cplx(const uint8_t* __restrict__ g, cpx<double>* __restrict__ S, int64_t N,
-                            unsigned long long* count) {
+// Phase maps [batch][N] -> each plan's copy of g and the complex FP64 input
+// of the spectrum; blockIdx.y = plan.
+__global__ void k_g_to_cplx(const uint8_t* __restrict__ G, const PlanPtrs* __restrict__ pp,
+                            cpx<double>* __restrict__ S, int64_t N, unsigned long long* count) {
+  const int b = blockIdx.y;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int v = 0;
   if (i < N) {
-    v = g[i];
-    S[i] = {(double)v, 0.0};
+    v = G[(int64_t)b * N + i];
+    pp[b].g[i] = (uint8_t)v;
+    S[(int64_t)b * N + i] = {(double)v, 0.0};
   }
   // integer count of inclusion voxels (order-independent, exact)
-  unsigned long long b = __ballot(v != 0);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+  unsigned long long m = __ballot(v != 0);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count + b, (unsigned long long)__popcll(m));
 }
 
 // FFT of every line along one axis of a C-ordered complex array viewed as
@@ -173,10 +214,16 @@ __global__ void k_fft_axis_f64(cpx<double>* __restrict__ S, int outer, int na, i
 }
 
 // Ranking keys; appends one SortEl per conjugate pair (its representative).
+// blockIdx.y = plan: its spectrum at S + b N, its elements at out + b stride.
 __global__ void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N, const unsigned long long* count,
-                       SortEl* __restrict__ out, unsigned int* nout) {
+                       SortEl* __restrict__ out, int64_t stride, unsigned int* nout) {
+  const int b = blockIdx.y;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
+  S += (int64_t)b * N;
+  count += b;
+  out += (int64_t)b * stride;
+  nout += b;
   int k[3], c[3];
   unravel(d, i, k);
   conj_k(d, k, c);
@@ -203,18 +250,21 @@ __global__ void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N, con
   out[pos] = {~__float_as_uint(key), s2, lr, (uint32_t)i};
 }
 
-__global__ void k_fill_sentinel(SortEl* el, int64_t from, int64_t to) {
+__global__ void k_fill_sentinel(SortEl* el, int64_t from, int64_t to, int64_t stride) {
   int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < to) el[i] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+  if (i < to) el[(int64_t)blockIdx.y * stride + i] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
 }
 
-// Bitonic network, ascending.  Global compare-exchange step (k, j).
-__global__ void k_bitonic_global(SortEl* el, int64_t n, int64_t k, int64_t j) {
+// Bitonic network, ascending, over n elements made of independent segments of
+// `seg` (a power of two, one per plan): compare-exchange pairs never leave a
+// segment (j < k <= seg), and the direction is taken from the index inside
+// the segment, so every segment ends sorted ascending.  Global step (k, j).
+__global__ void k_bitonic_global(SortEl* el, int64_t n, int64_t seg, int64_t k, int64_t j) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // pair index
   if (t >= n / 2) return;
   int64_t i = (t / j) * 2 * j + (t % j);
   int64_t l = i + j;
-  bool asc = (i & k) == 0;
+  bool asc = ((i & (seg - 1)) & k) == 0;
   SortEl x = el[i], y = el[l];
   bool sw = asc ? el_less(y, x) : el_less(x, y);
   if (sw) {
@@ -226,7 +276,7 @@ __global__ void k_bitonic_global(SortEl* el, int64_t n, int64_t k, int64_t j) {
 // In-LDS part of the network for tiles of `tile` elements (blockDim = tile/2).
 // kmin == 0: full local sort of each tile (k = 2 .. tile).  Otherwise: merge
 // steps j = tile/2 .. 1 for the given k.
-__global__ void k_bitonic_local(SortEl* el, int tile, int64_t kglob) {
+__global__ void k_bitonic_local(SortEl* el, int tile, int64_t seg, int64_t kglob) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   SortEl* s = reinterpret_cast<SortEl*>(smem_raw);
   const int64_t base = (int64_t)blockIdx.x * tile;
@@ -236,7 +286,7 @@ __global__ void k_bitonic_local(SortEl* el, int tile, int64_t kglob) {
     int t = threadIdx.x;
     int i = (t / j) * 2 * j + (t % j);
     int l = i + j;
-    bool asc = ((base + i) & k) == 0;
+    bool asc = (((base + i) & (seg - 1)) & k) == 0;
     SortEl x = s[i], y = s[l];
     bool sw = asc ? el_less(y, x) : el_less(x, y);
     if (sw) {
@@ -254,12 +304,21 @@ __global__ void k_bitonic_local(SortEl* el, int tile, int64_t kglob) {
   for (int t = threadIdx.x; t < tile; t += blockDim.x) el[base + t] = s[t];
 }
 
-// Pair-atomic selection in rank order (single workgroup).  Also records, for
-// every selected frequency, its pair index in rank order (bit 30 set for the
-// partner of the pair's representative); Mact[1] = number of selected pairs.
-__global__ void k_select(const SortEl* __restrict__ el, int64_t nreps, Dims d, int64_t M, uint8_t* __restrict__ mask,
-                         int64_t* __restrict__ rank, int64_t* __restrict__ Mact, int* __restrict__ pairof) {
+// Pair-atomic selection in rank order (one workgroup per plan, blockIdx.x).
+// Also records, for every selected frequency, its pair index in rank order
+// (bit 30 set for the partner of the pair's representative); Mact[1] = number
+// of selected pairs.
+__global__ void k_select(const SortEl* __restrict__ el, int64_t stride, int64_t nreps, Dims d, int64_t N,
+                         const PlanPtrs* __restrict__ pp, uint8_t* __restrict__ mask, int64_t* __restrict__ Mact,
+                         int* __restrict__ pairof) {
   __shared__ int lds[32];
+  const int b = blockIdx.x;
+  el += (int64_t)b * stride;
+  mask += (int64_t)b * N;
+  pairof += (int64_t)b * N;
+  Mact += 2 * b;
+  const int64_t M = pp[b].M;
+  int64_t* __restrict__ rank = pp[b].rank;
   int64_t base = 0;
   for (int64_t c0 = 0; c0 < nreps; c0 += blockDim.x) {
     int64_t i = c0 + threadIdx.x;
@@ -295,14 +354,16 @@ __global__ void k_select(const SortEl* __restrict__ el, int64_t nreps, Dims d, i
   }
 }
 
-// Mask -> ascending linear indices (single workgroup).
 // Sorted pattern (increasing linear index) in three launches: per-chunk
-// counts, an exclusive scan of the counts, and the scatter of each chunk.
+// counts, an exclusive scan of the counts, and the scatter of each chunk
+// (plan = blockIdx.y, for the scan blockIdx.x).
 constexpr int kCompactChunk = 4096;
 
 __global__ __launch_bounds__(256) void k_compact_count(const uint8_t* __restrict__ mask, int64_t N,
-                                                       int* __restrict__ ccount) {
+                                                       int* __restrict__ ccount, int nchunk) {
   __shared__ int lds[32];
+  mask += (int64_t)blockIdx.y * N;
+  ccount += (int64_t)blockIdx.y * nchunk;
   const int64_t c0 = (int64_t)blockIdx.x * kCompactChunk;
   int n = 0;
   for (int t = threadIdx.x; t < kCompactChunk; t += 256) {
@@ -316,6 +377,7 @@ __global__ __launch_bounds__(256) void k_compact_count(const uint8_t* __restrict
 
 __global__ __launch_bounds__(1024) void k_compact_scan(int* __restrict__ ccount, int nchunk) {
   __shared__ int lds[32];
+  ccount += (int64_t)blockIdx.x * nchunk;
   int base = 0;
   for (int c0 = 0; c0 < nchunk; c0 += 1024) {
     const int i = c0 + threadIdx.x;
@@ -328,8 +390,12 @@ __global__ __launch_bounds__(1024) void k_compact_scan(int* __restrict__ ccount,
 }
 
 __global__ __launch_bounds__(256) void k_compact_scatter(const uint8_t* __restrict__ mask, int64_t N,
-                                                         const int* __restrict__ cbase, int64_t* __restrict__ sorted) {
+                                                         const int* __restrict__ cbase, int nchunk,
+                                                         const PlanPtrs* __restrict__ pp) {
   __shared__ int lds[32];
+  mask += (int64_t)blockIdx.y * N;
+  cbase += (int64_t)blockIdx.y * nchunk;
+  int64_t* __restrict__ sorted = pp[blockIdx.y].sorted;
   const int64_t c0 = (int64_t)blockIdx.x * kCompactChunk;
   int base = cbase[blockIdx.x];
   for (int t0 = 0; t0 < kCompactChunk; t0 += 256) {
@@ -344,10 +410,16 @@ __global__ __launch_bounds__(256) void k_compact_scatter(const uint8_t* __restri
 
 // Slot tables of the warm-start network: slot s = pair s+1 in rank order
 // (pair 0 is xi = 0): representative's linear index and g^(rep) / count.
-__global__ void k_slots(const SortEl* __restrict__ el, int64_t nslots, const cpx<double>* __restrict__ S,
-                        const unsigned long long* count, int64_t* __restrict__ slot_rep, cpx<float>* __restrict__ slot_ghat) {
+__global__ void k_slots(const SortEl* __restrict__ el, int64_t stride, const cpx<double>* __restrict__ S, int64_t N,
+                        const unsigned long long* count, const PlanPtrs* __restrict__ pp) {
+  const int b = blockIdx.y;
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nslots) return;
+  if (s >= pp[b].nslots) return;
+  el += (int64_t)b * stride;
+  S += (int64_t)b * N;
+  count += b;
+  int64_t* __restrict__ slot_rep = pp[b].slot_rep;
+  cpx<float>* __restrict__ slot_ghat = pp[b].slot_ghat;
   const int64_t rep = el[s + 1].idx;
   const double c = (double)(*count);
   const cpx<double> v = S[rep];
@@ -357,12 +429,15 @@ __global__ void k_slots(const SortEl* __restrict__ el, int64_t nslots, const cpx
 
 // Half-spectrum columns: column c = kh * n1 + k1 (3D) or c = kh (2D), kh the
 // last-axis frequency in [0, nlen/2].
-__global__ __launch_bounds__(256) void k_tab_count(const uint8_t* __restrict__ mask, Dims d, int ncolall,
-                                                   int* __restrict__ cnt, int* __restrict__ lastcnt) {
-  // one wavefront per column: lanes stride over k0, wavefront sum
+__global__ __launch_bounds__(256) void k_tab_count(const uint8_t* __restrict__ mask, Dims d, int64_t N, int ncolall,
+                                                   int nkh, int* __restrict__ cnt, int* __restrict__ lastcnt) {
+  // one wavefront per column: lanes stride over k0, wavefront sum; plan = blockIdx.y
   const int c = blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (c >= ncolall) return;
+  mask += (int64_t)blockIdx.y * N;
+  cnt += (int64_t)blockIdx.y * ncolall;
+  lastcnt += (int64_t)blockIdx.y * nkh;
   int n = 0;
   const int kh = d.nd == 2 ? c : c / d.n1;
   if (d.nd == 2) {
@@ -378,13 +453,22 @@ __global__ __launch_bounds__(256) void k_tab_count(const uint8_t* __restrict__ m
   }
 }
 
-// Single workgroup: column and last-axis indices and offsets.
+// One workgroup per plan (blockIdx.x): column and last-axis indices and offsets.
 __global__ void k_tab_scan(const int* __restrict__ cnt, const int* __restrict__ lastcnt, Dims d, int ncolall, int nkh,
-                           int* __restrict__ colidx, int* __restrict__ col_k, int* __restrict__ col_kh,
-                           int* __restrict__ col_off, int* __restrict__ lastidx, int* __restrict__ last_k,
-                           int* __restrict__ meta) {
+                           int* __restrict__ colidx, int* __restrict__ col_kh, int* __restrict__ lastidx,
+                           int* __restrict__ meta, const PlanPtrs* __restrict__ pp, IntLayout il) {
   __shared__ int lds[32];
   __shared__ int lds2[32];
+  const int b = blockIdx.x;
+  cnt += (int64_t)b * ncolall;
+  colidx += (int64_t)b * ncolall;
+  col_kh += (int64_t)b * ncolall;
+  lastcnt += (int64_t)b * nkh;
+  lastidx += (int64_t)b * nkh;
+  meta += 4 * b;
+  int32_t* __restrict__ col_k = pp[b].ints + il.col_k;
+  int32_t* __restrict__ col_off = pp[b].ints + il.col_off;
+  int32_t* __restrict__ last_k = pp[b].ints + il.last_k;
   int jb = 0, ob = 0;
   for (int c0 = 0; c0 < ncolall; c0 += blockDim.x) {
     int c = c0 + threadIdx.x;
@@ -420,10 +504,16 @@ __global__ void k_tab_scan(const int* __restrict__ cnt, const int* __restrict__ 
   if (threadIdx.x == 0) meta[1] = lb;  // nlast
 }
 
-__global__ void k_tab_groups(const int* __restrict__ col_kh, const int* __restrict__ lastidx, int ncol, int nlast,
-                             int* __restrict__ col_last, int* __restrict__ last_off) {
+__global__ void k_tab_groups(const int* __restrict__ col_kh, const int* __restrict__ lastidx, int ncolall, int nkh,
+                             const PlanPtrs* __restrict__ pp, IntLayout il) {
+  const int b = blockIdx.y;
+  const int ncol = pp[b].ncol, nlast = pp[b].nlast;
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j > ncol) return;
+  col_kh += (int64_t)b * ncolall;
+  lastidx += (int64_t)b * nkh;
+  int32_t* __restrict__ col_last = pp[b].ints + il.col_last;
+  int32_t* __restrict__ last_off = pp[b].ints + il.last_off;
   if (j == ncol) {
     last_off[nlast] = ncol;
     return;
@@ -501,15 +591,24 @@ __device__ void coef_entry(const uint8_t* __restrict__ mask, Dims d, int gamma_k
 // Coefficient tables: one wavefront per half-spectrum column c walks k0 in
 // chunks of 64; a ballot and the popcount of the lower lanes give each
 // selected entry its slot (entries of a column stay in increasing k0).
-__global__ __launch_bounds__(256) void k_tab_fill(const uint8_t* __restrict__ mask, Dims d, int ncolall,
-                                                  const int* __restrict__ colidx, const int* __restrict__ col_off,
-                                                  int gamma_kind, int* __restrict__ coef_k0,
-                                                  int64_t* __restrict__ coef_lin, float* __restrict__ coef_n,
-                                                  double* __restrict__ coef_n64, uint8_t* __restrict__ flag,
-                                                  const int* __restrict__ pairof, int* __restrict__ coef_slot) {
+__global__ __launch_bounds__(256) void k_tab_fill(const uint8_t* __restrict__ mask, Dims d, int64_t N, int ncolall,
+                                                  const int* __restrict__ colidx, const int* __restrict__ pairof,
+                                                  int gamma_kind, const PlanPtrs* __restrict__ pp, IntLayout il) {
   const int c = blockIdx.x * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (c >= ncolall) return;
+  const int b = blockIdx.y;
+  mask += (int64_t)b * N;
+  pairof += (int64_t)b * N;
+  colidx += (int64_t)b * ncolall;
+  const PlanPtrs& q = pp[b];
+  const int32_t* __restrict__ col_off = q.ints + il.col_off;
+  int32_t* __restrict__ coef_k0 = q.ints + il.coef_k0;
+  int64_t* __restrict__ coef_lin = q.coef_lin;
+  float* __restrict__ coef_n = q.coef_n;
+  double* __restrict__ coef_n64 = q.coef_n64;
+  uint8_t* __restrict__ flag = q.coef_flag;
+  int32_t* __restrict__ coef_slot = q.coef_slot;
   const int j = colidx[c];
   if (j < 0) return;
   int e = col_off[j];
@@ -542,6 +641,15 @@ __global__ __launch_bounds__(256) void k_tab_fill(const uint8_t* __restrict__ ma
     }
     e += __popcll(bal);
   }
+}
+
+// Each plan's PlanDev from an array staged in device memory (blockIdx.x = plan).
+static_assert(sizeof(PlanDev) % 4 == 0, "PlanDev is copied in 4-byte words");
+__global__ void k_put_plandev(const PlanDev* __restrict__ src, const PlanPtrs* __restrict__ pp) {
+  const int b = blockIdx.x;
+  const uint32_t* __restrict__ from = reinterpret_cast<const uint32_t*>(src + b);
+  uint32_t* __restrict__ to = reinterpret_cast<uint32_t*>(pp[b].dev);
+  for (int w = threadIdx.x; w < (int)(sizeof(PlanDev) / 4); w += blockDim.x) to[w] = from[w];
 }
 
 bool size_ok(int64_t n) {
@@ -657,31 +765,106 @@ static void plan_free(mor_plan* p) {
   delete p;
 }
 
-static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t st) {
+// Builds `cnt` plans of one grid (P[i]->M may differ) from host phase maps
+// [cnt][N]: every step is one launch over the whole batch (plan = a grid
+// dimension of the launch), with two host synchronisations for the sizes of
+// the per-plan tables.  Scratch: about 22 N + 16 N' bytes per plan (N' the
+// next power of two above the number of conjugate pairs).
+static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint8_t* maps, hipStream_t st) {
   PlanScratch sc(st);  // declared first: released last, after the stream has drained
-  const int nd = P->ndim;
-  const int64_t N = P->N;
-  Dims d{nd, P->n[0], P->n[1], nd == 3 ? P->n[2] : 1};
-  const int nlen = nd == 2 ? P->n[1] : P->n[2];
+  const mor_plan& P0 = *P[0];
+  const int nd = P0.ndim;
+  const int64_t N = P0.N;
+  Dims d{nd, P0.n[0], P0.n[1], nd == 3 ? P0.n[2] : 1};
+  const int nlen = nd == 2 ? P0.n[1] : P0.n[2];
+  const unsigned nb = (unsigned)cnt;
 
-  MOR_HIP_TRY(plan_alloc(P, &P->d_g, N));
-  MOR_HIP_TRY(hipMemcpyAsync(P->d_g, phase_map, N, hipMemcpyHostToDevice, st));
+  std::vector<PlanPtrs> hp(cnt);
+  DevBuf<PlanPtrs> pp;
+  DevBuf<uint8_t> G;
+  MOR_HIP_TRY(pp.alloc(sc, cnt));
+  MOR_HIP_TRY(G.alloc(sc, (size_t)cnt * N));
+  MOR_HIP_TRY(hipMemcpyAsync(G.p, maps, (size_t)cnt * N, hipMemcpyHostToDevice, st));
+  // Every device table of a plan lives in one block of the pool, laid out
+  // with upper bounds known before the selection: M_actual <= M + 1, and the
+  // selected pairs, slots and stored coefficients are at most M_actual.
+  const int nkh = nlen / 2 + 1;
+  const int ncolall = nd == 2 ? nkh : nkh * P0.n[1];
+  const int64_t cap_col = ncolall, cap_last = nkh;
+  IntLayout il;
+  il.col_k = 0;
+  il.col_last = (int32_t)cap_col;
+  il.col_off = (int32_t)(2 * cap_col);
+  il.last_k = (int32_t)(3 * cap_col + 1);
+  il.last_off = (int32_t)(3 * cap_col + 1 + cap_last);
+  il.coef_k0 = (int32_t)(3 * cap_col + 1 + 2 * cap_last + 1);
+  const int n0 = P0.n[0], n1 = P0.n[1];
+  const int ntw = n0 + n1 + nlen / 2 + nlen;
+  for (int b = 0; b < cnt; ++b) {
+    mor_plan* Q = P[b];
+    const int64_t m1 = Q->M + 1;
+    size_t at = 0;
+    auto take = [&at](size_t bytes) {
+      const size_t o = at;
+      at += (bytes + 255) / 256 * 256;
+      return o;
+    };
+    const size_t o_g = take(N), o_rank = take(m1 * 8), o_srep = take(m1 * 8), o_sghat = take(m1 * 8),
+                 o_sorted = take(m1 * 8), o_ints = take((il.coef_k0 + m1) * 4), o_clin = take(m1 * 8),
+                 o_cn = take(m1 * 12), o_cn64 = take(m1 * 24), o_flag = take(m1), o_slot = take(m1 * 4),
+                 o_tw = take(ntw * sizeof(cpx<float>)), o_tw64 = take(ntw * sizeof(cpx<double>)),
+                 o_dev = take(sizeof(PlanDev));
+    unsigned char* base = nullptr;
+    MOR_HIP_TRY(plan_alloc(Q, &base, at));
+    Q->d_g = base + o_g;
+    Q->d_rank = (int64_t*)(base + o_rank);
+    Q->d_slot_rep = (int64_t*)(base + o_srep);
+    Q->d_slot_ghat = (cpx<float>*)(base + o_sghat);
+    Q->d_sorted = (int64_t*)(base + o_sorted);
+    Q->d_ints = (int32_t*)(base + o_ints);
+    Q->d_coef_lin = (int64_t*)(base + o_clin);
+    Q->d_coef_n = (float*)(base + o_cn);
+    Q->d_coef_n64 = (double*)(base + o_cn64);
+    Q->d_coef_flag = base + o_flag;
+    Q->d_coef_slot = (int32_t*)(base + o_slot);
+    Q->d_tw = (cpx<float>*)(base + o_tw);
+    Q->d_tw64 = (cpx<double>*)(base + o_tw64);
+    Q->d_dev = (PlanDev*)(base + o_dev);
+    PlanPtrs& h = hp[b];
+    h = PlanPtrs{};
+    h.g = Q->d_g;
+    h.rank = Q->d_rank;
+    h.slot_rep = Q->d_slot_rep;
+    h.slot_ghat = Q->d_slot_ghat;
+    h.sorted = Q->d_sorted;
+    h.ints = Q->d_ints;
+    h.coef_lin = Q->d_coef_lin;
+    h.coef_n = Q->d_coef_n;
+    h.coef_n64 = Q->d_coef_n64;
+    h.coef_flag = Q->d_coef_flag;
+    h.coef_slot = Q->d_coef_slot;
+    h.tw = Q->d_tw;
+    h.tw64 = Q->d_tw64;
+    h.dev = Q->d_dev;
+    h.M = Q->M;
+  }
+  MOR_HIP_TRY(hipMemcpyAsync(pp.p, hp.data(), cnt * sizeof(PlanPtrs), hipMemcpyHostToDevice, st));
 
-  // 1. FP64 spectrum
+  // 1. FP64 spectrum of every phase map ([cnt][N], each axis batched as lines)
   DevBuf<cpx<double>> S;
   DevBuf<cpx<double>> tw64;
-  DevBuf<unsigned long long> cnt;
-  MOR_HIP_TRY(S.alloc(sc, N));
+  DevBuf<unsigned long long> count;
+  MOR_HIP_TRY(S.alloc(sc, (size_t)cnt * N));
   MOR_HIP_TRY(tw64.alloc(sc, 1024));
-  MOR_HIP_TRY(cnt.alloc(sc, 1));
-  MOR_HIP_TRY(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), st));
-  k_g_to_cplx<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(P->d_g, S.p, N, cnt.p);
+  MOR_HIP_TRY(count.alloc(sc, cnt));
+  MOR_HIP_TRY(hipMemsetAsync(count.p, 0, cnt * sizeof(unsigned long long), st));
+  k_g_to_cplx<<<dim3((unsigned)((N + 255) / 256), nb), 256, 0, st>>>(G.p, pp.p, S.p, N, count.p);
   MOR_LAUNCH_CHECK("g_to_cplx");
   for (int a = 0; a < nd; ++a) {
-    int na = P->n[a];
-    int outer = 1, inner = 1;
-    for (int b = 0; b < a; ++b) outer *= P->n[b];
-    for (int b = a + 1; b < nd; ++b) inner *= P->n[b];
+    int na = P0.n[a];
+    int outer = cnt, inner = 1;
+    for (int b = 0; b < a; ++b) outer *= P0.n[b];
+    for (int b = a + 1; b < nd; ++b) inner *= P0.n[b];
     FftDesc fd;
     fft_make_desc(na, &fd);
     k_twiddle_f64<<<(na + 255) / 256, 256, 0, st>>>(tw64.p, na);
@@ -693,36 +876,39 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
     MOR_LAUNCH_CHECK("fft_axis_f64");
   }
 
-  // 2. keys of pair representatives
+  // 2. keys of pair representatives, one segment of npow2 elements per plan
   int64_t nselfc = 1;
   for (int a = 0; a < nd; ++a) nselfc *= 2;  // every axis is even
   const int64_t nreps = (N + nselfc) / 2;
   int64_t npow2 = 1;
   while (npow2 < nreps) npow2 <<= 1;
+  const int64_t nel = (int64_t)cnt * npow2;
   DevBuf<SortEl> el;
   DevBuf<unsigned int> nout;
-  MOR_HIP_TRY(el.alloc(sc, npow2));
-  MOR_HIP_TRY(nout.alloc(sc, 1));
-  MOR_HIP_TRY(hipMemsetAsync(nout.p, 0, sizeof(unsigned int), st));
-  k_keys<<<(unsigned)((N + 255) / 256), 256, 0, st>>>(S.p, d, N, cnt.p, el.p, nout.p);
+  MOR_HIP_TRY(el.alloc(sc, nel));
+  MOR_HIP_TRY(nout.alloc(sc, cnt));
+  MOR_HIP_TRY(hipMemsetAsync(nout.p, 0, cnt * sizeof(unsigned int), st));
+  k_keys<<<dim3((unsigned)((N + 255) / 256), nb), 256, 0, st>>>(S.p, d, N, count.p, el.p, npow2, nout.p);
   MOR_LAUNCH_CHECK("keys");
   if (npow2 > nreps) {
-    k_fill_sentinel<<<(unsigned)((npow2 - nreps + 255) / 256), 256, 0, st>>>(el.p, nreps, npow2);
+    k_fill_sentinel<<<dim3((unsigned)((npow2 - nreps + 255) / 256), nb), 256, 0, st>>>(el.p, nreps, npow2, npow2);
     MOR_LAUNCH_CHECK("fill_sentinel");
   }
 
-  // 3. bitonic sort
+  // 3. bitonic sort of every segment
   const int tile = (int)std::min<int64_t>(npow2, 2048);
   const unsigned nt = (unsigned)std::max(1, tile / 2);
   if (npow2 >= 2) {
-    k_bitonic_local<<<(unsigned)(npow2 / tile), nt, tile * sizeof(SortEl), st>>>(el.p, tile, 0);
+    const unsigned ntiles = (unsigned)(nel / tile);
+    const unsigned npairb = (unsigned)((nel / 2 + 255) / 256);
+    k_bitonic_local<<<ntiles, nt, tile * sizeof(SortEl), st>>>(el.p, tile, npow2, 0);
     MOR_LAUNCH_CHECK("bitonic_local");
     for (int64_t k = 2 * (int64_t)tile; k <= npow2; k <<= 1) {
       for (int64_t j = k >> 1; j >= tile; j >>= 1) {
-        k_bitonic_global<<<(unsigned)((npow2 / 2 + 255) / 256), 256, 0, st>>>(el.p, npow2, k, j);
+        k_bitonic_global<<<npairb, 256, 0, st>>>(el.p, nel, npow2, k, j);
         MOR_LAUNCH_CHECK("bitonic_global");
       }
-      k_bitonic_local<<<(unsigned)(npow2 / tile), nt, tile * sizeof(SortEl), st>>>(el.p, tile, k);
+      k_bitonic_local<<<ntiles, nt, tile * sizeof(SortEl), st>>>(el.p, tile, npow2, k);
       MOR_LAUNCH_CHECK("bitonic_local");
     }
   }
@@ -730,139 +916,241 @@ static mor_status plan_build(mor_plan* P, const uint8_t* phase_map, hipStream_t 
   // 4. selection
   DevBuf<uint8_t> mask;
   DevBuf<int64_t> mact;
-  MOR_HIP_TRY(mask.alloc(sc, N));
-  MOR_HIP_TRY(mact.alloc(sc, 2));
-  MOR_HIP_TRY(hipMemsetAsync(mask.p, 0, N, st));
-  MOR_HIP_TRY(plan_alloc(P, &P->d_rank, (P->M + 1) * sizeof(int64_t)));
   DevBuf<int> pairof;
-  MOR_HIP_TRY(pairof.alloc(sc, N));
-  MOR_HIP_TRY(hipMemsetAsync(pairof.p, 0, N * sizeof(int), st));
-  k_select<<<1, 1024, 0, st>>>(el.p, nreps, d, P->M, mask.p, P->d_rank, mact.p, pairof.p);
+  MOR_HIP_TRY(mask.alloc(sc, (size_t)cnt * N));
+  MOR_HIP_TRY(mact.alloc(sc, 2 * (size_t)cnt));
+  MOR_HIP_TRY(pairof.alloc(sc, (size_t)cnt * N));
+  MOR_HIP_TRY(hipMemsetAsync(mask.p, 0, (size_t)cnt * N, st));
+  MOR_HIP_TRY(hipMemsetAsync(pairof.p, 0, (size_t)cnt * N * sizeof(int), st));
+  k_select<<<nb, 1024, 0, st>>>(el.p, npow2, nreps, d, N, pp.p, mask.p, mact.p, pairof.p);
   MOR_LAUNCH_CHECK("select");
-  int64_t hm[2] = {0, 0};
-  MOR_HIP_TRY(hipMemcpyAsync(hm, mact.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  MOR_HIP_TRY(hipMemcpyAsync(&P->count, cnt.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  std::vector<int64_t> hm(2 * (size_t)cnt);
+  std::vector<unsigned long long> hcount(cnt);
+  MOR_HIP_TRY(hipMemcpyAsync(hm.data(), mact.p, 2 * cnt * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MOR_HIP_TRY(hipMemcpyAsync(hcount.data(), count.p, cnt * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   MOR_HIP_TRY(hipStreamSynchronize(st));
-  P->M_actual = hm[0];
-  P->nslots = hm[1] - 1;
+
+  // sizes of the selection
+  int64_t max_slots = 0;
+  for (int b = 0; b < cnt; ++b) {
+    mor_plan* Q = P[b];
+    Q->M_actual = hm[2 * b];
+    Q->nslots = hm[2 * b + 1] - 1;
+    Q->count = (int64_t)hcount[b];
+    if (Q->M_actual < 1 || Q->M_actual > Q->M + 1 || Q->nslots < 0 || Q->nslots >= Q->M_actual) {
+      mor_set_error("mor_plan: selection sizes outside their bounds");
+      return MOR_E_DEVICE;
+    }
+    max_slots = std::max(max_slots, Q->nslots);
+    hp[b].nslots = Q->nslots;
+  }
+  MOR_HIP_TRY(hipMemcpyAsync(pp.p, hp.data(), cnt * sizeof(PlanPtrs), hipMemcpyHostToDevice, st));
 
   // slot tables of the warm-start network
-  MOR_HIP_TRY(plan_alloc(P, &P->d_slot_rep, std::max<int64_t>(P->nslots, 1) * sizeof(int64_t)));
-  MOR_HIP_TRY(plan_alloc(P, &P->d_slot_ghat, std::max<int64_t>(P->nslots, 1) * sizeof(cpx<float>)));
-  if (P->nslots > 0) {
-    k_slots<<<(unsigned)((P->nslots + 255) / 256), 256, 0, st>>>(el.p, P->nslots, S.p, cnt.p, P->d_slot_rep,
-                                                                 P->d_slot_ghat);
+  if (max_slots > 0) {
+    k_slots<<<dim3((unsigned)((max_slots + 255) / 256), nb), 256, 0, st>>>(el.p, npow2, S.p, N, count.p, pp.p);
     MOR_LAUNCH_CHECK("slots");
   }
 
   // 5. sorted pattern
-  MOR_HIP_TRY(plan_alloc(P, &P->d_sorted, P->M_actual * sizeof(int64_t)));
   {
     const int nchunk = (int)((N + kCompactChunk - 1) / kCompactChunk);
     DevBuf<int> ccount;
-    MOR_HIP_TRY(ccount.alloc(sc, nchunk));
-    k_compact_count<<<nchunk, 256, 0, st>>>(mask.p, N, ccount.p);
-    k_compact_scan<<<1, 1024, 0, st>>>(ccount.p, nchunk);
-    k_compact_scatter<<<nchunk, 256, 0, st>>>(mask.p, N, ccount.p, P->d_sorted);
+    MOR_HIP_TRY(ccount.alloc(sc, (size_t)cnt * nchunk));
+    k_compact_count<<<dim3(nchunk, nb), 256, 0, st>>>(mask.p, N, ccount.p, nchunk);
+    k_compact_scan<<<nb, 1024, 0, st>>>(ccount.p, nchunk);
+    k_compact_scatter<<<dim3(nchunk, nb), 256, 0, st>>>(mask.p, N, ccount.p, nchunk, pp.p);
     MOR_LAUNCH_CHECK("compact");
   }
 
   // 6. tables
-  const int nkh = nlen / 2 + 1;
-  const int ncolall = nd == 2 ? nkh : nkh * P->n[1];
   DevBuf<int> cntc, lastcnt, colidx, col_kh, lastidx, meta;
-  MOR_HIP_TRY(cntc.alloc(sc, ncolall));
-  MOR_HIP_TRY(lastcnt.alloc(sc, nkh));
-  MOR_HIP_TRY(colidx.alloc(sc, ncolall));
-  MOR_HIP_TRY(col_kh.alloc(sc, ncolall));
-  MOR_HIP_TRY(lastidx.alloc(sc, nkh));
-  MOR_HIP_TRY(meta.alloc(sc, 4));
-  MOR_HIP_TRY(hipMemsetAsync(lastcnt.p, 0, nkh * sizeof(int), st));
-  // integer layout: col_k | col_last | col_off | last_k | last_off | coef_k0
-  const int64_t cap_col = ncolall, cap_last = nkh, cap_coef = P->M_actual;
-  const int64_t nint = cap_col + cap_col + (cap_col + 1) + cap_last + (cap_last + 1) + cap_coef;
-  MOR_HIP_TRY(plan_alloc(P, &P->d_ints, nint * sizeof(int32_t)));
-  int32_t* col_k = P->d_ints;
-  int32_t* col_last = col_k + cap_col;
-  int32_t* col_off = col_last + cap_col;
-  int32_t* last_k = col_off + cap_col + 1;
-  int32_t* last_off = last_k + cap_last;
-  int32_t* coef_k0 = last_off + cap_last + 1;
-  k_tab_count<<<(ncolall + 3) / 4, 256, 0, st>>>(mask.p, d, ncolall, cntc.p, lastcnt.p);
+  MOR_HIP_TRY(cntc.alloc(sc, (size_t)cnt * ncolall));
+  MOR_HIP_TRY(lastcnt.alloc(sc, (size_t)cnt * nkh));
+  MOR_HIP_TRY(colidx.alloc(sc, (size_t)cnt * ncolall));
+  MOR_HIP_TRY(col_kh.alloc(sc, (size_t)cnt * ncolall));
+  MOR_HIP_TRY(lastidx.alloc(sc, (size_t)cnt * nkh));
+  MOR_HIP_TRY(meta.alloc(sc, 4 * (size_t)cnt));
+  MOR_HIP_TRY(hipMemsetAsync(lastcnt.p, 0, (size_t)cnt * nkh * sizeof(int), st));
+  k_tab_count<<<dim3((ncolall + 3) / 4, nb), 256, 0, st>>>(mask.p, d, N, ncolall, nkh, cntc.p, lastcnt.p);
   MOR_LAUNCH_CHECK("tab_count");
-  k_tab_scan<<<1, 1024, 0, st>>>(cntc.p, lastcnt.p, d, ncolall, nkh, colidx.p, col_k, col_kh.p, col_off, lastidx.p,
-                                 last_k, meta.p);
+  k_tab_scan<<<nb, 1024, 0, st>>>(cntc.p, lastcnt.p, d, ncolall, nkh, colidx.p, col_kh.p, lastidx.p, meta.p, pp.p, il);
   MOR_LAUNCH_CHECK("tab_scan");
-  int hmeta[4] = {0, 0, 0, 0};
-  MOR_HIP_TRY(hipMemcpyAsync(hmeta, meta.p, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+  std::vector<int> hmeta(4 * (size_t)cnt);
+  MOR_HIP_TRY(hipMemcpyAsync(hmeta.data(), meta.p, 4 * cnt * sizeof(int), hipMemcpyDeviceToHost, st));
   MOR_HIP_TRY(hipStreamSynchronize(st));
-  const int ncol = hmeta[0], nlast = hmeta[1], ncoef = hmeta[2];
-  k_tab_groups<<<(ncol + 1 + 255) / 256, 256, 0, st>>>(col_kh.p, lastidx.p, ncol, nlast, col_last, last_off);
+
+  int max_col = 0;
+  std::vector<PlanDev> hdev(cnt);
+  for (int b = 0; b < cnt; ++b) {
+    mor_plan* Q = P[b];
+    const int ncol = hmeta[4 * b], nlast = hmeta[4 * b + 1], ncoef = hmeta[4 * b + 2];
+    max_col = std::max(max_col, ncol);
+    if (ncol < 0 || ncol > ncolall || nlast < 0 || nlast > nkh || ncoef < 0 || ncoef > Q->M_actual) {
+      mor_set_error("mor_plan: table sizes outside their bounds");
+      return MOR_E_DEVICE;
+    }
+    hp[b].ncol = ncol;
+    hp[b].nlast = nlast;
+
+    PlanDev& v = Q->dev;
+    v = PlanDev{};
+    v.ndim = nd;
+    v.n0 = n0;
+    v.n1 = n1;
+    v.n2 = nd == 3 ? P0.n[2] : 1;
+    v.N = (int32_t)N;
+    v.nlen = nlen;
+    v.rows = (int32_t)(N / nlen);
+    v.ncol = ncol;
+    v.nlast = nlast;
+    v.ncoef = ncoef;
+    v.inv_N = (float)(1.0 / (double)N);
+    v.g = Q->d_g;
+    v.col_k = Q->d_ints + il.col_k;
+    v.col_last = Q->d_ints + il.col_last;
+    v.col_off = Q->d_ints + il.col_off;
+    v.last_k = Q->d_ints + il.last_k;
+    v.last_off = Q->d_ints + il.last_off;
+    v.coef_k0 = Q->d_ints + il.coef_k0;
+    v.coef_n = Q->d_coef_n;
+    v.coef_flag = Q->d_coef_flag;
+    v.tw0 = Q->d_tw;
+    v.tw1 = v.tw0 + n0;
+    v.twh = v.tw1 + n1;
+    v.rtw = v.twh + nlen / 2;
+    v.coef_n64 = Q->d_coef_n64;
+    v.tw0_64 = Q->d_tw64;
+    v.tw1_64 = v.tw0_64 + n0;
+    v.twh_64 = v.tw1_64 + n1;
+    v.rtw_64 = v.twh_64 + nlen / 2;
+    fft_make_desc(n0, &v.fd0);
+    fft_make_desc(n1, &v.fd1);
+    fft_make_desc(nlen / 2, &v.fdh);
+    hdev[b] = v;
+  }
+  MOR_HIP_TRY(hipMemcpyAsync(pp.p, hp.data(), cnt * sizeof(PlanPtrs), hipMemcpyHostToDevice, st));
+  k_tab_groups<<<dim3((max_col + 1 + 255) / 256, nb), 256, 0, st>>>(col_kh.p, lastidx.p, ncolall, nkh, pp.p, il);
   MOR_LAUNCH_CHECK("tab_groups");
-  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_lin, std::max(ncoef, 1) * sizeof(int64_t)));
-  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_n, std::max(ncoef, 1) * 3 * sizeof(float)));
-  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_n64, std::max(ncoef, 1) * 3 * sizeof(double)));
-  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_flag, std::max(ncoef, 1)));
-  MOR_HIP_TRY(plan_alloc(P, &P->d_coef_slot, std::max(ncoef, 1) * sizeof(int)));
-  k_tab_fill<<<(ncolall + 3) / 4, 256, 0, st>>>(mask.p, d, ncolall, colidx.p, col_off, P->gamma_kind, coef_k0,
-                                                    P->d_coef_lin, P->d_coef_n, P->d_coef_n64, P->d_coef_flag,
-                                                    pairof.p, P->d_coef_slot);
+  k_tab_fill<<<dim3((ncolall + 3) / 4, nb), 256, 0, st>>>(mask.p, d, N, ncolall, colidx.p, pairof.p, P0.gamma_kind,
+                                                          pp.p, il);
   MOR_LAUNCH_CHECK("tab_fill");
 
-  // twiddles for the solver transforms
-  const int n0 = P->n[0], n1 = P->n[1];
-  const int ntw = n0 + n1 + nlen / 2 + nlen;
-  MOR_HIP_TRY(plan_alloc(P, &P->d_tw, ntw * sizeof(cpx<float>)));
-  cpx<float>* tw0 = P->d_tw;
-  cpx<float>* tw1 = tw0 + n0;
-  cpx<float>* twh = tw1 + n1;
-  cpx<float>* rtw = twh + nlen / 2;
-  k_twiddle4<float><<<(ntw + 255) / 256, 256, 0, st>>>(P->d_tw, n0, n1, nlen / 2, nlen);
+  // twiddles of the solver transforms, and each plan's device descriptor
+  k_twiddle4<float><<<dim3((ntw + 255) / 256, nb), 256, 0, st>>>(pp.p, n0, n1, nlen / 2, nlen);
   MOR_LAUNCH_CHECK("twiddle_f32");
-  MOR_HIP_TRY(plan_alloc(P, &P->d_tw64, ntw * sizeof(cpx<double>)));
-  k_twiddle4<double><<<(ntw + 255) / 256, 256, 0, st>>>(P->d_tw64, n0, n1, nlen / 2, nlen);
+  k_twiddle4<double><<<dim3((ntw + 255) / 256, nb), 256, 0, st>>>(pp.p, n0, n1, nlen / 2, nlen);
   MOR_LAUNCH_CHECK("twiddle_f64");
-  (void)tw0;
-  (void)tw1;
-  (void)twh;
-  (void)rtw;
-
-  PlanDev& v = P->dev;
-  v.ndim = nd;
-  v.n0 = n0;
-  v.n1 = n1;
-  v.n2 = nd == 3 ? P->n[2] : 1;
-  v.N = (int32_t)N;
-  v.nlen = nlen;
-  v.rows = (int32_t)(N / nlen);
-  v.ncol = ncol;
-  v.nlast = nlast;
-  v.ncoef = ncoef;
-  v.inv_N = (float)(1.0 / (double)N);
-  v.g = P->d_g;
-  v.col_k = col_k;
-  v.col_last = col_last;
-  v.col_off = col_off;
-  v.last_k = last_k;
-  v.last_off = last_off;
-  v.coef_k0 = coef_k0;
-  v.coef_n = P->d_coef_n;
-  v.coef_flag = P->d_coef_flag;
-  v.tw0 = tw0;
-  v.tw1 = tw1;
-  v.twh = twh;
-  v.rtw = rtw;
-  v.coef_n64 = P->d_coef_n64;
-  v.tw0_64 = P->d_tw64;
-  v.tw1_64 = v.tw0_64 + n0;
-  v.twh_64 = v.tw1_64 + n1;
-  v.rtw_64 = v.twh_64 + nlen / 2;
-  fft_make_desc(n0, &v.fd0);
-  fft_make_desc(n1, &v.fd1);
-  fft_make_desc(nlen / 2, &v.fdh);
-  MOR_HIP_TRY(plan_alloc(P, &P->d_dev, sizeof(PlanDev)));
-  MOR_HIP_TRY(hipMemcpyAsync(P->d_dev, &v, sizeof(PlanDev), hipMemcpyHostToDevice, st));
+  DevBuf<PlanDev> dstage;
+  MOR_HIP_TRY(dstage.alloc(sc, cnt));
+  MOR_HIP_TRY(hipMemcpyAsync(dstage.p, hdev.data(), cnt * sizeof(PlanDev), hipMemcpyHostToDevice, st));
+  k_put_plandev<<<nb, 64, 0, st>>>(dstage.p, pp.p);
+  MOR_LAUNCH_CHECK("put_plandev");
   MOR_HIP_TRY(hipStreamSynchronize(st));
+  return MOR_OK;
+}
+
+// Scratch bytes of one plan in plan_build_batch.
+static size_t plan_scratch_bytes(const mor_grid* grid, int64_t N) {
+  int64_t nselfc = 1;
+  for (int a = 0; a < grid->ndim; ++a) nselfc *= 2;
+  const int64_t nreps = (N + nselfc) / 2;
+  int64_t npow2 = 1;
+  while (npow2 < nreps) npow2 <<= 1;
+  const int64_t nlen = grid->n[grid->ndim - 1];
+  const int64_t ncolall = (nlen / 2 + 1) * (grid->ndim == 3 ? grid->n[1] : 1);
+  return (size_t)(22 * N + 16 * npow2 + 12 * ncolall + 8 * (nlen / 2 + 1) + 4 * (N / 4096 + 1) +
+                  sizeof(PlanPtrs) + sizeof(PlanDev) + 64);
+}
+
+// Shared by mor_plan_create (count 1) and mor_plan_create_batch.
+static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t count, const uint8_t* maps,
+                                const int64_t* Ms, const mor_plan_opts* opts, mor_plan_t* out) {
+  if (!grid || (count > 0 && (!maps || !Ms || !out))) {
+    mor_set_error(std::string(who) + ": NULL argument");
+    return MOR_E_INVALID_ARG;
+  }
+  if (count < 0) {
+    mor_set_error(std::string(who) + ": negative count");
+    return MOR_E_INVALID_ARG;
+  }
+  for (int64_t b = 0; b < count; ++b) out[b] = nullptr;
+  if (grid->ndim != 2 && grid->ndim != 3) {
+    mor_set_error(std::string(who) + ": ndim must be 2 or 3");
+    return MOR_E_INVALID_ARG;
+  }
+  int64_t N = 1;
+  for (int a = 0; a < grid->ndim; ++a) {
+    if (grid->n[a] < 2) {
+      mor_set_error(std::string(who) + ": every grid size must be >= 2");
+      return MOR_E_INVALID_ARG;
+    }
+    N *= grid->n[a];
+  }
+  for (int a = 0; a < grid->ndim; ++a) {
+    if (!size_ok(grid->n[a])) {
+      mor_set_error(std::string(who) + ": grid sizes must be even, 2^a 3^b, within [4, 1024]");
+      return MOR_E_UNSUPPORTED;
+    }
+  }
+  if (N > (int64_t)1 << 27) {
+    mor_set_error(std::string(who) + ": grid larger than 2^27 points");
+    return MOR_E_UNSUPPORTED;
+  }
+  for (int64_t b = 0; b < count; ++b) {
+    if (Ms[b] < 1 || Ms[b] > N) {
+      mor_set_error(std::string(who) + ": M must lie in [1, N] (microstructure " + std::to_string(b) + ")");
+      return MOR_E_INVALID_ARG;
+    }
+  }
+  int gk = opts ? opts->gamma_kind : MOR_GAMMA_ROTATED;
+  if (gk != MOR_GAMMA_ROTATED && gk != MOR_GAMMA_CONTINUOUS) {
+    mor_set_error(std::string(who) + ": unknown gamma_kind");
+    return MOR_E_INVALID_ARG;
+  }
+  for (int64_t i = 0; i < count * N; ++i) {
+    if (maps[i] > 1) {
+      mor_set_error(std::string(who) + ": phase_map values must be 0 or 1 (microstructure " + std::to_string(i / N) + ")");
+      return MOR_E_INVALID_ARG;
+    }
+  }
+  if (count == 0) return MOR_OK;
+
+  size_t budget = (size_t)512 << 20;
+  if (const char* e = getenv("MOR_PLAN_SCRATCH_BYTES")) {
+    long long v = atoll(e);
+    if (v > 0) budget = (size_t)v;
+  }
+  const int64_t chunk =
+      std::max<int64_t>(1, std::min<int64_t>({count, (int64_t)(budget / plan_scratch_bytes(grid, N)), 65535}));
+
+  static std::atomic<uint64_t> next_uid{0};
+  std::vector<mor_plan*> P((size_t)count, nullptr);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  for (int64_t b = 0; b < count; ++b) {
+    mor_plan* Q = new mor_plan();
+    Q->uid = ++next_uid;
+    Q->ndim = grid->ndim;
+    for (int a = 0; a < grid->ndim; ++a) Q->n[a] = (int)grid->n[a];
+    Q->N = N;
+    Q->M = Ms[b];
+    Q->gamma_kind = gk;
+    Q->device = dev;
+    P[b] = Q;
+  }
+  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  mor_status s = MOR_OK;
+  for (int64_t b0 = 0; b0 < count && s == MOR_OK; b0 += chunk) {
+    const int n = (int)std::min<int64_t>(chunk, count - b0);
+    s = plan_build_batch(P.data() + b0, n, maps + b0 * N, st);
+  }
+  if (s != MOR_OK) {
+    (void)hipStreamSynchronize(st);
+    for (mor_plan* Q : P) plan_free(Q);
+    return s;
+  }
+  for (int64_t b = 0; b < count; ++b) out[b] = P[b];
   return MOR_OK;
 }
 
@@ -872,62 +1160,12 @@ extern "C" mor_status mor_plan_create(const mor_grid* grid, const uint8_t* phase
     mor_set_error("mor_plan_create: NULL argument");
     return MOR_E_INVALID_ARG;
   }
-  *out = nullptr;
-  if (grid->ndim != 2 && grid->ndim != 3) {
-    mor_set_error("mor_plan_create: ndim must be 2 or 3");
-    return MOR_E_INVALID_ARG;
-  }
-  int64_t N = 1;
-  for (int a = 0; a < grid->ndim; ++a) {
-    if (grid->n[a] < 2) {
-      mor_set_error("mor_plan_create: every grid size must be >= 2");
-      return MOR_E_INVALID_ARG;
-    }
-    N *= grid->n[a];
-  }
-  for (int a = 0; a < grid->ndim; ++a) {
-    if (!size_ok(grid->n[a])) {
-      mor_set_error("mor_plan_create: grid sizes must be even, 2^a 3^b, within [4, 1024]");
-      return MOR_E_UNSUPPORTED;
-    }
-  }
-  if (N > (int64_t)1 << 27) {
-    mor_set_error("mor_plan_create: grid larger than 2^27 points");
-    return MOR_E_UNSUPPORTED;
-  }
-  if (M < 1 || M > N) {
-    mor_set_error("mor_plan_create: M must lie in [1, N]");
-    return MOR_E_INVALID_ARG;
-  }
-  int gk = opts ? opts->gamma_kind : MOR_GAMMA_ROTATED;
-  if (gk != MOR_GAMMA_ROTATED && gk != MOR_GAMMA_CONTINUOUS) {
-    mor_set_error("mor_plan_create: unknown gamma_kind");
-    return MOR_E_INVALID_ARG;
-  }
-  for (int64_t i = 0; i < N; ++i) {
-    if (phase_map[i] > 1) {
-      mor_set_error("mor_plan_create: phase_map values must be 0 or 1");
-      return MOR_E_INVALID_ARG;
-    }
-  }
-  static std::atomic<uint64_t> next_uid{0};
-  mor_plan* P = new mor_plan();
-  P->uid = ++next_uid;
-  P->ndim = grid->ndim;
-  for (int a = 0; a < grid->ndim; ++a) P->n[a] = (int)grid->n[a];
-  P->N = N;
-  P->M = M;
-  P->gamma_kind = gk;
-  (void)hipGetDevice(&P->device);
-  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
-  mor_status s = plan_build(P, phase_map, st);
-  if (s != MOR_OK) {
-    (void)hipStreamSynchronize(st);
-    plan_free(P);
-    return s;
-  }
-  *out = P;
-  return MOR_OK;
+  return plan_create_n("mor_plan_create", grid, 1, phase_map, &M, opts, out);
+}
+
+extern "C" mor_status mor_plan_create_batch(const mor_grid* grid, int64_t count, const uint8_t* phase_maps,
+                                            const int64_t* M, const mor_plan_opts* opts, mor_plan_t* out) {
+  return plan_create_n("mor_plan_create_batch", grid, count, phase_maps, M, opts, out);
 }
 
 extern "C" mor_status mor_plan_get_info(mor_plan_t plan, mor_plan_info* info) {

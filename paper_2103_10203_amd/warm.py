@@ -66,7 +66,7 @@ def build_training_set(gs, M, phases, nslots, tol=1e-6, chunk=512, log=None):
     for c0 in range(0, len(gs), chunk):
         part = gs[c0:c0 + chunk]
         t = time.perf_counter()
-        plans = [nat.Plan(g, M) for g in part]
+        plans = nat.make_plans(part, M)
         t_plan += time.perf_counter() - t
         nb = len(part)
         plan_of = np.repeat(np.arange(nb), 3)

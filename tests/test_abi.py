@@ -52,6 +52,43 @@ def test_plan_create_rejects(shape, M, val, code):
     assert len(nat.lib.mor_last_error()) > 0
 
 
+@pytest.mark.parametrize("case,code", [
+    ("negative_count", 1),
+    ("bad_M_in_second", 1),
+    ("bad_phase_in_third", 1),
+    ("unsupported_grid", 6),
+])
+def test_plan_create_batch_rejects(case, code):
+    """mor_plan_create_batch checks every map and M before any device work;
+    on error every output entry is NULL."""
+    import ctypes as ct
+    from paper_2103_10203_amd import _native as nat
+    shape = (14, 16) if case == "unsupported_grid" else (16, 16)
+    n = 3
+    maps = np.zeros((n,) + shape, np.uint8)
+    Ms = np.full(n, 5, np.int64)
+    if case == "bad_M_in_second":
+        Ms[1] = 257
+    if case == "bad_phase_in_third":
+        maps[2].flat[7] = 3
+    count = -1 if case == "negative_count" else n
+    grid = nat._grid_of(shape)
+    hs = (ct.c_void_p * n)(*([ct.c_void_p(1).value] * n))
+    st = nat.lib.mor_plan_create_batch(ct.byref(grid), count, maps.ctypes.data_as(ct.c_void_p),
+                                       Ms.ctypes.data_as(ct.c_void_p), None, ct.cast(hs, ct.c_void_p))
+    assert st == code
+    assert len(nat.lib.mor_last_error()) > 0
+    if count > 0:
+        assert all(h is None for h in hs)
+
+
+def test_plan_create_batch_of_nothing():
+    import ctypes as ct
+    from paper_2103_10203_amd import _native as nat
+    grid = nat._grid_of((16, 16))
+    assert nat.lib.mor_plan_create_batch(ct.byref(grid), 0, None, None, None, None) == nat.MOR_OK
+
+
 def test_null_arguments():
     from paper_2103_10203_amd import _native as nat
     assert nat.lib.mor_solve(None, None, 1, None, 1e-6, None, None) == nat.MOR_E_INVALID_ARG

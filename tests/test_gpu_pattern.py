@@ -68,21 +68,59 @@ def test_pattern_independent_of_material_and_deterministic():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def test_concurrent_plan_construction_matches_sequential():
-    """make_plans (several host threads, one HIP stream each) gives the same
-    plans as one mor_plan_create after another: pattern, rank order and
-    coefficient order, on mixed 2D and 3D grids with one M per grid."""
+def _same_plan(a, b):
+    assert a.info == b.info
+    sa, ra = a.pattern()
+    sb, rb = b.pattern()
+    assert np.array_equal(sa, sb) and np.array_equal(ra, rb)
+    assert np.array_equal(a.coeff_index(), b.coeff_index())
+
+
+def test_batched_plan_construction_matches_single():
+    """make_plans (one mor_plan_create_batch per grid shape) gives the plans
+    of one mor_plan_create after another: pattern, rank order and coefficient
+    order, on mixed 2D and 3D grids with one M per map, the maps of a shape
+    interleaved with the others in the input order."""
     import paper_2103_10203_amd as mor
     gs = [synth.rsa_fibres(n, n, n / 32, n / 16, seed=300 + n, target_vf=0.35).g for n in (64, 128, 96, 256)]
     gs += [synth.rsa_spheres(32, 32, 32, r_lo=4.0, r_hi=6.0, seed=5, target_vf=0.2).g]
     gs = gs * 3
-    Ms = [int(math.ceil(0.05 * g.size)) for g in gs]
+    Ms = [int(math.ceil(r * g.size)) for r, g in zip([0.05, 0.01, 0.2] * 5, gs)]
     seq = [mor.Plan(g, M) for g, M in zip(gs, Ms)]
-    par = mor.make_plans(gs, Ms, workers=6)
-    assert len(par) == len(seq)
-    for a, b in zip(seq, par):
-        assert a.info == b.info
-        sa, ra = a.pattern()
-        sb, rb = b.pattern()
-        assert np.array_equal(sa, sb) and np.array_equal(ra, rb)
-        assert np.array_equal(a.coeff_index(), b.coeff_index())
+    bat = mor.make_plans(gs, Ms)
+    assert len(bat) == len(seq)
+    for a, b in zip(seq, bat):
+        _same_plan(a, b)
+
+
+def test_batched_plans_edge_cases_and_chunks(monkeypatch):
+    """Degenerate maps (all matrix, all inclusion, one voxel), M = 1 and
+    M = N, the odd shapes of a 2^a 3^b grid, and a scratch budget so small
+    that every map is its own chunk: still the single-call plans."""
+    import paper_2103_10203_amd as mor
+    n0, n1 = 48, 36
+    maps = [np.zeros((n0, n1), np.uint8), np.ones((n0, n1), np.uint8)]
+    one = np.zeros((n0, n1), np.uint8)
+    one[5, 7] = 1
+    maps.append(one)
+    maps += [synth.rsa_fibres(n0, n1, 3, 6, seed=s, target_vf=0.3).g for s in (1, 2, 3)]
+    Ms = [1, n0 * n1, 17, 1, n0 * n1, 87]
+    seq = [mor.Plan(g, M) for g, M in zip(maps, Ms)]
+    _ = [_same_plan(a, b) for a, b in zip(seq, mor.make_plans(maps, Ms))]
+    monkeypatch.setenv("MOR_PLAN_SCRATCH_BYTES", "1")
+    _ = [_same_plan(a, b) for a, b in zip(seq, mor.make_plans(maps, Ms))]
+
+
+def test_batched_plan_solves_like_single():
+    """A solve on a batched plan gives the single plan's results bit for bit."""
+    import paper_2103_10203_amd as mor
+    from tests.gpu_common import native_phases
+    gs = [synth.rsa_fibres(64, 64, 3, 5, seed=s, target_vf=0.35).g for s in (11, 12, 13)]
+    ebs = synth.macro_strains(3, 3, 2e-3, seed=4)
+    single = [mor.Plan(g, 205) for g in gs]
+    bat = mor.make_plans(gs, 205)
+    po = np.arange(3)
+    a = mor.solve_multi(single, po, ebs, native_phases(), 1e-6)
+    b = mor.solve_multi(bat, po, ebs, native_phases(), 1e-6)
+    assert np.array_equal(a.eff_stress, b.eff_stress)
+    assert np.array_equal(a.iterations, b.iterations)
