@@ -108,16 +108,19 @@ mor_status mor_plan_create(const mor_grid* grid, const uint8_t* phase_map, int64
  *
  *   grid        as for mor_plan_create, shared by every map.
  *   count       >= 0; 0 creates nothing and returns MOR_OK.
- *   phase_maps  host uint8 [count][N], C order, values 0 or 1.
+ *   phase_maps  host [count] pointers, each to a host uint8 [N] map (C
+ *               order, values 0 or 1); the maps need not be adjacent.
  *   M           host int64 [count], each in [1, N].
  *   opts        NULL for defaults (gamma_kind and stream apply to all).
  *   out         host [count]; receives the plans.  On any error every
  *               entry is NULL: plans already built are destroyed.
- * Device scratch is drawn in chunks of microstructures of at most
- * 512 MiB (environment variable MOR_PLAN_SCRATCH_BYTES overrides the size),
- * held in the library's block pool for reuse.
+ * Every map and M is checked before any device work.  Device scratch is
+ * drawn in chunks of microstructures of at most 512 MiB (environment
+ * variable MOR_PLAN_SCRATCH_BYTES overrides the size), held in the library's
+ * block pool for reuse; each chunk's maps are staged in pinned host memory
+ * allocated and released by the call.
  */
-mor_status mor_plan_create_batch(const mor_grid* grid, int64_t count, const uint8_t* phase_maps,
+mor_status mor_plan_create_batch(const mor_grid* grid, int64_t count, const uint8_t* const* phase_maps,
                                  const int64_t* M, const mor_plan_opts* opts, mor_plan_t* out);
 
 mor_status mor_plan_get_info(mor_plan_t plan, mor_plan_info* info);

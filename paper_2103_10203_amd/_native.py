@@ -260,9 +260,9 @@ class Plan:
 def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, stream=None):
     """Plans of many microstructures: one mor_plan_create_batch call for all
     maps of the same shape, so the construction runs as a few launches over
-    the whole group instead of a chain of small launches per map.  M: one
-    value or one per map.  Plans come back in input order, identical to
-    Plan(g, M) of each map."""
+    the whole group instead of a chain of small launches per map (the maps
+    are passed by pointer, not copied here).  M: one value or one per map.
+    Plans come back in input order, identical to Plan(g, M) of each map."""
     grids = [np.ascontiguousarray(g, dtype=np.uint8) for g in grids]
     Ms = [int(M)] * len(grids) if np.isscalar(M) else [int(m) for m in M]
     if len(Ms) != len(grids):
@@ -274,11 +274,11 @@ def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, stream=None):
     opts = mor_plan_opts(gamma_kind, 0, _stream_ptr(stream))
     for shape, idx in groups.items():
         grid = _grid_of(shape)
-        maps = np.stack([grids[i] for i in idx])
+        ptrs = (ct.c_void_p * len(idx))(*[grids[i].ctypes.data for i in idx])
         marr = np.array([Ms[i] for i in idx], np.int64)
         hs = (ct.c_void_p * len(idx))()
-        _check(lib.mor_plan_create_batch(ct.byref(grid), len(idx), _np_ptr(maps), _np_ptr(marr), ct.byref(opts),
-                                         ct.cast(hs, ct.c_void_p)))
+        _check(lib.mor_plan_create_batch(ct.byref(grid), len(idx), ct.cast(ptrs, ct.c_void_p), _np_ptr(marr),
+                                         ct.byref(opts), ct.cast(hs, ct.c_void_p)))
         for j, i in enumerate(idx):
             out[i] = Plan(shape, 0, _handle=ct.c_void_p(hs[j]))
     return out

@@ -213,10 +213,15 @@ __global__ void k_fft_axis_f64(cpx<double>* __restrict__ S, int outer, int na, i
   }
 }
 
-// Ranking keys; appends one SortEl per conjugate pair (its representative).
+// Ranking keys: one SortEl per conjugate pair (its representative), appended
+// to `out`, and one per self-conjugate frequency (a member of every axis is 0
+// or n/2; 2^ndim of them), appended to `side` (kSide slots per plan).
 // blockIdx.y = plan: its spectrum at S + b N, its elements at out + b stride.
+constexpr int kSide = 8;
+
 __global__ void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N, const unsigned long long* count,
-                       SortEl* __restrict__ out, int64_t stride, unsigned int* nout) {
+                       SortEl* __restrict__ out, int64_t stride, unsigned int* nout, SortEl* __restrict__ side,
+                       unsigned int* nside) {
   const int b = blockIdx.y;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -246,8 +251,47 @@ __global__ void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N, con
     int s = signed_k(k[a], n[a]);
     s2 += (uint32_t)(s * s);
   }
-  unsigned int pos = atomicAdd(nout, 1u);
-  out[pos] = {~__float_as_uint(key), s2, lr, (uint32_t)i};
+  const SortEl e = {~__float_as_uint(key), s2, lr, (uint32_t)i};
+  if (lr == lc) {
+    const unsigned int pos = atomicAdd(nside + b, 1u);
+    side[(int64_t)b * kSide + pos] = e;
+  } else {
+    const unsigned int pos = atomicAdd(nout, 1u);
+    out[pos] = e;
+  }
+}
+
+// Rank order of every representative of a plan (blockIdx.y): its sorted pairs
+// (main, nmain of them) merged with its nside self-conjugate frequencies
+// (unsorted, at most kSide).  Keys are a total order, so each element's place
+// is its index in its own list plus the count of smaller ones in the other.
+__global__ void k_merge_side(const SortEl* __restrict__ main, int64_t stride, int64_t nmain,
+                             const SortEl* __restrict__ side, int nside, SortEl* __restrict__ out, int64_t nreps) {
+  const int b = blockIdx.y;
+  main += (int64_t)b * stride;
+  side += (int64_t)b * kSide;
+  out += (int64_t)b * nreps;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nmain) {
+    const SortEl x = main[i];
+    int c = 0;
+    for (int t = 0; t < nside; ++t) c += el_less(side[t], x) ? 1 : 0;
+    out[i + c] = x;
+  } else if (i < nmain + nside) {
+    const SortEl x = side[i - nmain];
+    int r = 0;
+    for (int t = 0; t < nside; ++t) r += el_less(side[t], x) ? 1 : 0;
+    int64_t lo = 0, hi = nmain;  // first main element not less than x
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      if (el_less(main[mid], x)) {
+        lo = mid + 1;
+      } else {
+        hi = mid;
+      }
+    }
+    out[r + lo] = x;
+  }
 }
 
 __global__ void k_fill_sentinel(SortEl* el, int64_t from, int64_t to, int64_t stride) {
@@ -765,12 +809,26 @@ static void plan_free(mor_plan* p) {
   delete p;
 }
 
+// Pinned host staging of a batch's phase maps; released after its stream
+// has drained (the copy from it is asynchronous).
+struct PinnedStage {
+  hipStream_t st;
+  void* p = nullptr;
+  explicit PinnedStage(hipStream_t s) : st(s) {}
+  ~PinnedStage() {
+    if (p) {
+      (void)hipStreamSynchronize(st);
+      (void)hipHostFree(p);
+    }
+  }
+};
+
 // Builds `cnt` plans of one grid (P[i]->M may differ) from host phase maps
-// [cnt][N]: every step is one launch over the whole batch (plan = a grid
+// maps[0..cnt) (each N bytes, already checked)// [cnt][N]: every step is one launch over the whole batch (plan = a grid
 // dimension of the launch), with two host synchronisations for the sizes of
-// the per-plan tables.  Scratch: about 22 N + 16 N' bytes per plan (N' the
-// next power of two above the number of conjugate pairs).
-static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint8_t* maps, hipStream_t st) {
+// the per-plan tables.  Scratch: about 30 N + 16 N' bytes per plan (N' the
+// power of two at or above the number of conjugate pairs).
+static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint8_t* const* maps, hipStream_t st) {
   PlanScratch sc(st);  // declared first: released last, after the stream has drained
   const mor_plan& P0 = *P[0];
   const int nd = P0.ndim;
@@ -784,7 +842,17 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
   DevBuf<uint8_t> G;
   MOR_HIP_TRY(pp.alloc(sc, cnt));
   MOR_HIP_TRY(G.alloc(sc, (size_t)cnt * N));
-  MOR_HIP_TRY(hipMemcpyAsync(G.p, maps, (size_t)cnt * N, hipMemcpyHostToDevice, st));
+  // The maps reach the device in one copy: through a pinned staging buffer
+  // when there are several (a host memcpy of each, then one DMA), straight
+  // from the caller's memory when there is one.
+  PinnedStage stage(st);
+  if (cnt == 1) {
+    MOR_HIP_TRY(hipMemcpyAsync(G.p, maps[0], N, hipMemcpyHostToDevice, st));
+  } else {
+    MOR_HIP_TRY(hipHostMalloc(&stage.p, (size_t)cnt * N, hipHostMallocDefault));
+    for (int b = 0; b < cnt; ++b) std::memcpy((uint8_t*)stage.p + (size_t)b * N, maps[b], (size_t)N);
+    MOR_HIP_TRY(hipMemcpyAsync(G.p, stage.p, (size_t)cnt * N, hipMemcpyHostToDevice, st));
+  }
   // Every device table of a plan lives in one block of the pool, laid out
   // with upper bounds known before the selection: M_actual <= M + 1, and the
   // selected pairs, slots and stored coefficients are at most M_actual.
@@ -876,26 +944,32 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
     MOR_LAUNCH_CHECK("fft_axis_f64");
   }
 
-  // 2. keys of pair representatives, one segment of npow2 elements per plan
+  // 2. keys: the conjugate pairs' representatives in one segment of npow2
+  // elements per plan (sorted below), the self-conjugate frequencies aside
+  // (for grids of 2^k points the pairs then fill N/2 slots, not N)
   int64_t nselfc = 1;
   for (int a = 0; a < nd; ++a) nselfc *= 2;  // every axis is even
   const int64_t nreps = (N + nselfc) / 2;
+  const int64_t nmain = (N - nselfc) / 2;
   int64_t npow2 = 1;
-  while (npow2 < nreps) npow2 <<= 1;
+  while (npow2 < nmain) npow2 <<= 1;
   const int64_t nel = (int64_t)cnt * npow2;
-  DevBuf<SortEl> el;
+  DevBuf<SortEl> el, side, ranked;
   DevBuf<unsigned int> nout;
   MOR_HIP_TRY(el.alloc(sc, nel));
-  MOR_HIP_TRY(nout.alloc(sc, cnt));
-  MOR_HIP_TRY(hipMemsetAsync(nout.p, 0, cnt * sizeof(unsigned int), st));
-  k_keys<<<dim3((unsigned)((N + 255) / 256), nb), 256, 0, st>>>(S.p, d, N, count.p, el.p, npow2, nout.p);
+  MOR_HIP_TRY(side.alloc(sc, (size_t)cnt * kSide));
+  MOR_HIP_TRY(ranked.alloc(sc, (size_t)cnt * nreps));
+  MOR_HIP_TRY(nout.alloc(sc, 2 * (size_t)cnt));
+  MOR_HIP_TRY(hipMemsetAsync(nout.p, 0, 2 * cnt * sizeof(unsigned int), st));
+  k_keys<<<dim3((unsigned)((N + 255) / 256), nb), 256, 0, st>>>(S.p, d, N, count.p, el.p, npow2, nout.p, side.p,
+                                                                nout.p + cnt);
   MOR_LAUNCH_CHECK("keys");
-  if (npow2 > nreps) {
-    k_fill_sentinel<<<dim3((unsigned)((npow2 - nreps + 255) / 256), nb), 256, 0, st>>>(el.p, nreps, npow2, npow2);
+  if (npow2 > nmain) {
+    k_fill_sentinel<<<dim3((unsigned)((npow2 - nmain + 255) / 256), nb), 256, 0, st>>>(el.p, nmain, npow2, npow2);
     MOR_LAUNCH_CHECK("fill_sentinel");
   }
 
-  // 3. bitonic sort of every segment
+  // 3. bitonic sort of every plan's pairs
   const int tile = (int)std::min<int64_t>(npow2, 2048);
   const unsigned nt = (unsigned)std::max(1, tile / 2);
   if (npow2 >= 2) {
@@ -913,6 +987,10 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
     }
   }
 
+  k_merge_side<<<dim3((unsigned)((nreps + 255) / 256), nb), 256, 0, st>>>(el.p, npow2, nmain, side.p, (int)nselfc,
+                                                                          ranked.p, nreps);
+  MOR_LAUNCH_CHECK("merge_side");
+
   // 4. selection
   DevBuf<uint8_t> mask;
   DevBuf<int64_t> mact;
@@ -922,7 +1000,7 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
   MOR_HIP_TRY(pairof.alloc(sc, (size_t)cnt * N));
   MOR_HIP_TRY(hipMemsetAsync(mask.p, 0, (size_t)cnt * N, st));
   MOR_HIP_TRY(hipMemsetAsync(pairof.p, 0, (size_t)cnt * N * sizeof(int), st));
-  k_select<<<nb, 1024, 0, st>>>(el.p, npow2, nreps, d, N, pp.p, mask.p, mact.p, pairof.p);
+  k_select<<<nb, 1024, 0, st>>>(ranked.p, nreps, nreps, d, N, pp.p, mask.p, mact.p, pairof.p);
   MOR_LAUNCH_CHECK("select");
   std::vector<int64_t> hm(2 * (size_t)cnt);
   std::vector<unsigned long long> hcount(cnt);
@@ -948,7 +1026,7 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
 
   // slot tables of the warm-start network
   if (max_slots > 0) {
-    k_slots<<<dim3((unsigned)((max_slots + 255) / 256), nb), 256, 0, st>>>(el.p, npow2, S.p, N, count.p, pp.p);
+    k_slots<<<dim3((unsigned)((max_slots + 255) / 256), nb), 256, 0, st>>>(ranked.p, nreps, S.p, N, count.p, pp.p);
     MOR_LAUNCH_CHECK("slots");
   }
 
@@ -1054,17 +1132,17 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
 static size_t plan_scratch_bytes(const mor_grid* grid, int64_t N) {
   int64_t nselfc = 1;
   for (int a = 0; a < grid->ndim; ++a) nselfc *= 2;
-  const int64_t nreps = (N + nselfc) / 2;
+  const int64_t nreps = (N + nselfc) / 2, nmain = (N - nselfc) / 2;
   int64_t npow2 = 1;
-  while (npow2 < nreps) npow2 <<= 1;
+  while (npow2 < nmain) npow2 <<= 1;
   const int64_t nlen = grid->n[grid->ndim - 1];
   const int64_t ncolall = (nlen / 2 + 1) * (grid->ndim == 3 ? grid->n[1] : 1);
-  return (size_t)(22 * N + 16 * npow2 + 12 * ncolall + 8 * (nlen / 2 + 1) + 4 * (N / 4096 + 1) +
-                  sizeof(PlanPtrs) + sizeof(PlanDev) + 64);
+  return (size_t)(22 * N + 16 * npow2 + 16 * nreps + 16 * kSide + 12 * ncolall + 8 * (nlen / 2 + 1) +
+                  4 * (N / 4096 + 1) + sizeof(PlanPtrs) + sizeof(PlanDev) + 64);
 }
 
 // Shared by mor_plan_create (count 1) and mor_plan_create_batch.
-static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t count, const uint8_t* maps,
+static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t count, const uint8_t* const* maps,
                                 const int64_t* Ms, const mor_plan_opts* opts, mor_plan_t* out) {
   if (!grid || (count > 0 && (!maps || !Ms || !out))) {
     mor_set_error(std::string(who) + ": NULL argument");
@@ -1108,9 +1186,16 @@ static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t c
     mor_set_error(std::string(who) + ": unknown gamma_kind");
     return MOR_E_INVALID_ARG;
   }
-  for (int64_t i = 0; i < count * N; ++i) {
-    if (maps[i] > 1) {
-      mor_set_error(std::string(who) + ": phase_map values must be 0 or 1 (microstructure " + std::to_string(i / N) + ")");
+  for (int64_t b = 0; b < count; ++b) {
+    const uint8_t* g = maps[b];
+    if (!g) {
+      mor_set_error(std::string(who) + ": NULL phase map (microstructure " + std::to_string(b) + ")");
+      return MOR_E_INVALID_ARG;
+    }
+    uint8_t any = 0;  // OR of the values: above 1 iff some value is
+    for (int64_t i = 0; i < N; ++i) any |= g[i];
+    if (any > 1) {
+      mor_set_error(std::string(who) + ": phase_map values must be 0 or 1 (microstructure " + std::to_string(b) + ")");
       return MOR_E_INVALID_ARG;
     }
   }
@@ -1143,7 +1228,7 @@ static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t c
   mor_status s = MOR_OK;
   for (int64_t b0 = 0; b0 < count && s == MOR_OK; b0 += chunk) {
     const int n = (int)std::min<int64_t>(chunk, count - b0);
-    s = plan_build_batch(P.data() + b0, n, maps + b0 * N, st);
+    s = plan_build_batch(P.data() + b0, n, maps + b0, st);
   }
   if (s != MOR_OK) {
     (void)hipStreamSynchronize(st);
@@ -1160,10 +1245,11 @@ extern "C" mor_status mor_plan_create(const mor_grid* grid, const uint8_t* phase
     mor_set_error("mor_plan_create: NULL argument");
     return MOR_E_INVALID_ARG;
   }
-  return plan_create_n("mor_plan_create", grid, 1, phase_map, &M, opts, out);
+  const uint8_t* const maps[1] = {phase_map};
+  return plan_create_n("mor_plan_create", grid, 1, maps, &M, opts, out);
 }
 
-extern "C" mor_status mor_plan_create_batch(const mor_grid* grid, int64_t count, const uint8_t* phase_maps,
+extern "C" mor_status mor_plan_create_batch(const mor_grid* grid, int64_t count, const uint8_t* const* phase_maps,
                                             const int64_t* M, const mor_plan_opts* opts, mor_plan_t* out) {
   return plan_create_n("mor_plan_create_batch", grid, count, phase_maps, M, opts, out);
 }

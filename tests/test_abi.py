@@ -54,6 +54,7 @@ def test_plan_create_rejects(shape, M, val, code):
 
 @pytest.mark.parametrize("case,code", [
     ("negative_count", 1),
+    ("null_map", 1),
     ("bad_M_in_second", 1),
     ("bad_phase_in_third", 1),
     ("unsupported_grid", 6),
@@ -74,7 +75,10 @@ def test_plan_create_batch_rejects(case, code):
     count = -1 if case == "negative_count" else n
     grid = nat._grid_of(shape)
     hs = (ct.c_void_p * n)(*([ct.c_void_p(1).value] * n))
-    st = nat.lib.mor_plan_create_batch(ct.byref(grid), count, maps.ctypes.data_as(ct.c_void_p),
+    ptrs = (ct.c_void_p * n)(*[maps[b].ctypes.data for b in range(n)])
+    if case == "null_map":
+        ptrs[1] = None
+    st = nat.lib.mor_plan_create_batch(ct.byref(grid), count, ct.cast(ptrs, ct.c_void_p),
                                        Ms.ctypes.data_as(ct.c_void_p), None, ct.cast(hs, ct.c_void_p))
     assert st == code
     assert len(nat.lib.mor_last_error()) > 0
