@@ -207,9 +207,16 @@ class Plan:
         self._h = h
         self.shape = tuple(shape)
         self.ndim = len(shape)
-        inf = mor_plan_info()
-        _check(lib.mor_plan_get_info(self._h, ct.byref(inf)))
-        self.info = {k: getattr(inf, k) for k, _ in mor_plan_info._fields_}
+        self._info = None
+
+    @property
+    def info(self):
+        """mor_plan_get_info as a dict (fetched on first use)."""
+        if self._info is None:
+            inf = mor_plan_info()
+            _check(lib.mor_plan_get_info(self._h, ct.byref(inf)))
+            self._info = {k: getattr(inf, k) for k, _ in mor_plan_info._fields_}
+        return self._info
 
     @property
     def handle(self):

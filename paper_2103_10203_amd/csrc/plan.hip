@@ -824,11 +824,13 @@ struct PinnedStage {
 };
 
 // Builds `cnt` plans of one grid (P[i]->M may differ) from host phase maps
-// maps[0..cnt) (each N bytes, already checked)// [cnt][N]: every step is one launch over the whole batch (plan = a grid
+// maps[0..cnt) (each N bytes, already checked), staged through `pinned`
+// (cnt N bytes of pinned host memory, or NULL to copy the maps one by one)// [cnt][N]: every step is one launch over the whole batch (plan = a grid
 // dimension of the launch), with two host synchronisations for the sizes of
 // the per-plan tables.  Scratch: about 30 N + 16 N' bytes per plan (N' the
 // power of two at or above the number of conjugate pairs).
-static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint8_t* const* maps, hipStream_t st) {
+static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint8_t* const* maps, uint8_t* pinned,
+                                   hipStream_t st) {
   PlanScratch sc(st);  // declared first: released last, after the stream has drained
   const mor_plan& P0 = *P[0];
   const int nd = P0.ndim;
@@ -842,16 +844,15 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
   DevBuf<uint8_t> G;
   MOR_HIP_TRY(pp.alloc(sc, cnt));
   MOR_HIP_TRY(G.alloc(sc, (size_t)cnt * N));
-  // The maps reach the device in one copy: through a pinned staging buffer
-  // when there are several (a host memcpy of each, then one DMA), straight
-  // from the caller's memory when there is one.
-  PinnedStage stage(st);
-  if (cnt == 1) {
-    MOR_HIP_TRY(hipMemcpyAsync(G.p, maps[0], N, hipMemcpyHostToDevice, st));
+  // The maps reach the device in one copy from the pinned staging buffer (a
+  // host memcpy of each, then one DMA; the previous chunk's copy has drained
+  // at its final synchronisation), else one copy per map.
+  if (pinned) {
+    for (int b = 0; b < cnt; ++b) std::memcpy(pinned + (size_t)b * N, maps[b], (size_t)N);
+    MOR_HIP_TRY(hipMemcpyAsync(G.p, pinned, (size_t)cnt * N, hipMemcpyHostToDevice, st));
   } else {
-    MOR_HIP_TRY(hipHostMalloc(&stage.p, (size_t)cnt * N, hipHostMallocDefault));
-    for (int b = 0; b < cnt; ++b) std::memcpy((uint8_t*)stage.p + (size_t)b * N, maps[b], (size_t)N);
-    MOR_HIP_TRY(hipMemcpyAsync(G.p, stage.p, (size_t)cnt * N, hipMemcpyHostToDevice, st));
+    for (int b = 0; b < cnt; ++b)
+      MOR_HIP_TRY(hipMemcpyAsync(G.p + (size_t)b * N, maps[b], N, hipMemcpyHostToDevice, st));
   }
   // Every device table of a plan lives in one block of the pool, laid out
   // with upper bounds known before the selection: M_actual <= M + 1, and the
@@ -1226,9 +1227,18 @@ static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t c
   }
   hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
   mor_status s = MOR_OK;
+  PinnedStage stage(st);
+  if (count > 1) {
+    const hipError_t e = hipHostMalloc(&stage.p, (size_t)chunk * N, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      stage.p = nullptr;
+      mor_set_error(std::string(who) + ": pinned staging buffer: " + hipGetErrorString(e));
+      s = e == hipErrorOutOfMemory ? MOR_E_OUT_OF_MEMORY : MOR_E_DEVICE;
+    }
+  }
   for (int64_t b0 = 0; b0 < count && s == MOR_OK; b0 += chunk) {
     const int n = (int)std::min<int64_t>(chunk, count - b0);
-    s = plan_build_batch(P.data() + b0, n, maps + b0, st);
+    s = plan_build_batch(P.data() + b0, n, maps + b0, (uint8_t*)stage.p, st);
   }
   if (s != MOR_OK) {
     (void)hipStreamSynchronize(st);
