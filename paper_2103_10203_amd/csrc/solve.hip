@@ -576,8 +576,8 @@ bool has_fast_mid(int n1) { return n1 == 32 || n1 == 64 || n1 == 128; }
 
 template <int N1, int DIR>
 void go_mid_fast(SolveCtx& cx, Group& g, int check_active) {
-  dim3 gm((g.n0 + MidCfg<N1>::XB - 1) / MidCfg<N1>::XB, g.nlast_max, (unsigned)g.rves.size());
-  k_mid_fast<6, N1, DIR><<<gm, mid_threads<6, N1>(), mid_lds_bytes<6, N1>(), cx.st>>>(
+  dim3 gm(6 * ((g.n0 + MidCfg<N1>::XB - 1) / MidCfg<N1>::XB), g.nlast_max, (unsigned)g.rves.size());
+  k_mid_fast<6, N1, DIR><<<gm, mid_threads<N1>(), mid_lds_bytes<N1>(), cx.st>>>(
       cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.d_yc, cx.off, check_active);
 }
 

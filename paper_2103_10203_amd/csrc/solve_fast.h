@@ -681,36 +681,37 @@ __global__ __launch_bounds__((col_threads<C, N0, V>())) void k_col_persist(
 }
 
 // 3D axis-1 kernels (between the row and the column stages), compile-time
-// specialised for n1 = 32 / 64 / 128: per workgroup XB values of x0 x C
-// components for one last-axis frequency j2 of one RVE, N1/RF threads per
-// sequence.  Forward: lines of Yl along x1 -> FFT (first pass from HBM into
-// registers, the rest in LDS) -> the group's (k1, j2) columns of Yc.
-// Inverse: those columns -> zero-padded lines -> inverse FFT (last pass from
-// registers to HBM) -> Yl.
+// specialised for n1 = 32 / 64 / 128: per workgroup XB consecutive values of
+// x0 of one strain component c for one last-axis frequency j2 of one RVE
+// (blockIdx.x = c * ceil(n0 / XB) + x0 block), N1/RF threads per sequence.
+// Forward: lines of Yl along x1 -> FFT (first pass from HBM into registers,
+// the rest in LDS) -> the group's (k1, j2) columns of Yc.  Inverse: those
+// columns -> zero-padded lines -> inverse FFT (last pass from registers to
+// HBM) -> Yl.  Columns of Yc run along x0, so XB = 16 makes every column
+// access a 128-byte run; the XB lines read or written are adjacent in Yl.
 template <int N1>
 struct MidCfg;
-template <> struct MidCfg<32>  { static constexpr int RF = 8, XB = 8; using FA = RList<4>; };
-template <> struct MidCfg<64>  { static constexpr int RF = 8, XB = 4; using FA = RList<8>; };
-template <> struct MidCfg<128> { static constexpr int RF = 8, XB = 2; using FA = RList<4, 4>; };
+template <> struct MidCfg<32>  { static constexpr int RF = 8, XB = 16; using FA = RList<4>; };
+template <> struct MidCfg<64>  { static constexpr int RF = 8, XB = 16; using FA = RList<8>; };
+template <> struct MidCfg<128> { static constexpr int RF = 8, XB = 16; using FA = RList<4, 4>; };
 
-template <int C, int N1>
+template <int N1>
 constexpr int mid_threads() {
-  return C * MidCfg<N1>::XB * (N1 / MidCfg<N1>::RF);
+  return MidCfg<N1>::XB * (N1 / MidCfg<N1>::RF);
 }
-template <int C, int N1>
+template <int N1>
 constexpr size_t mid_lds_bytes() {
-  return (size_t)(pad16(N1 - 1) + 1 + C * MidCfg<N1>::XB * fftr::seq_stride(N1)) * sizeof(cpx<float>);
+  return (size_t)(pad16(N1 - 1) + 1 + MidCfg<N1>::XB * fftr::seq_stride(N1)) * sizeof(cpx<float>);
 }
 
 template <int C, int N1, int DIR>
-__global__ __launch_bounds__((mid_threads<C, N1>())) void k_mid_fast(
+__global__ __launch_bounds__((mid_threads<N1>())) void k_mid_fast(
     const PlanDev* __restrict__ plans, const int* __restrict__ rve_list, RveState* __restrict__ st,
     cpx<float>* __restrict__ Yl, cpx<float>* __restrict__ Yc, Offs off, int check_active) {
   using Cfg = MidCfg<N1>;
   constexpr int RF = Cfg::RF, XB = Cfg::XB;
   constexpr int TS = N1 / RF;
-  constexpr int NT = mid_threads<C, N1>();
-  constexpr int NSEQ = C * XB;
+  constexpr int NT = mid_threads<N1>();
   constexpr int SS = fftr::seq_stride(N1);
   static_assert(NT % 64 == 0, "workgroups are whole wavefronts");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -721,23 +722,22 @@ __global__ __launch_bounds__((mid_threads<C, N1>())) void k_mid_fast(
   const int j2 = blockIdx.y;
   if (j2 >= P.nlast) return;
   const int n0 = P.n0;
-  const int x00 = blockIdx.x * XB;
-  if (x00 >= n0) return;
+  const int nxb = (n0 + XB - 1) / XB;
+  const int c = blockIdx.x / nxb;
+  if (c >= C) return;
+  const int x00 = (blockIdx.x - c * nxb) * XB;
   const int nx = min(XB, n0 - x00);
   cpx<float>* tw = reinterpret_cast<cpx<float>*>(smem_raw);
   cpx<float>* buf = tw + pad16(N1 - 1) + 1;
   for (int t = tid; t < N1; t += NT) tw[pad16(t)] = P.tw1[t];
   const int rows = P.rows, nlast = P.nlast, ncol = P.ncol;
-  cpx<float>* L = Yl + off.yl[b];
-  cpx<float>* Cc = Yc + off.yc[b];
-  const int64_t lcs = (int64_t)nlast * rows;
-  const int64_t ccs = (int64_t)ncol * n0;
+  cpx<float>* L = Yl + off.yl[b] + c * (int64_t)nlast * rows;
+  cpx<float>* Cc = Yc + off.yc[b] + c * (int64_t)ncol * n0;
   const int ja = P.last_off[j2], jb = P.last_off[j2 + 1];
   const int ng = jb - ja;
-  const int s = tid / TS, i = tid % TS;  // sequence s = c * XB + xi
-  const int c_s = s / XB, xi_s = s % XB;
-  const bool live = xi_s < nx;
-  cpx<float>* line = L + c_s * lcs + (int64_t)j2 * rows + (int64_t)(x00 + xi_s) * N1;
+  const int s = tid / TS, i = tid % TS;  // sequence s = x0 - x00
+  const bool live = s < nx;
+  cpx<float>* line = L + (int64_t)j2 * rows + (int64_t)(x00 + s) * N1;
   if (DIR < 0) {
     cpx<float> v[RF];
 #pragma unroll
@@ -748,27 +748,23 @@ __global__ __launch_bounds__((mid_threads<C, N1>())) void k_mid_fast(
 #pragma unroll
     for (int j = 0; j < RF; ++j) dst[pad16(i * RF + j)] = v[j];
     __syncthreads();
-    fftr::lds_passes<N1, -1, RF, NSEQ, SS, NT, 1>(buf, tw, tid, typename Cfg::FA{});
-    for (int t = tid; t < C * ng * nx; t += NT) {
+    fftr::lds_passes<N1, -1, RF, XB, SS, NT, 1>(buf, tw, tid, typename Cfg::FA{});
+    for (int t = tid; t < ng * nx; t += NT) {
       const int xi = t % nx;
-      const int q = t / nx;
-      const int g = q % ng, c = q / ng;
-      const int j = ja + g;
-      Cc[c * ccs + (int64_t)j * n0 + x00 + xi] = buf[(c * XB + xi) * SS + pad16(P.col_k[j])];
+      const int j = ja + t / nx;
+      Cc[(int64_t)j * n0 + x00 + xi] = buf[xi * SS + pad16(P.col_k[j])];
     }
   } else {
-    for (int t = tid; t < NSEQ * SS; t += NT) buf[t] = {0.f, 0.f};
+    for (int t = tid; t < XB * SS; t += NT) buf[t] = {0.f, 0.f};
     __syncthreads();
-    for (int t = tid; t < C * ng * nx; t += NT) {
+    for (int t = tid; t < ng * nx; t += NT) {
       const int xi = t % nx;
-      const int q = t / nx;
-      const int g = q % ng, c = q / ng;
-      const int j = ja + g;
-      buf[(c * XB + xi) * SS + pad16(P.col_k[j])] = Cc[c * ccs + (int64_t)j * n0 + x00 + xi];
+      const int j = ja + t / nx;
+      buf[xi * SS + pad16(P.col_k[j])] = Cc[(int64_t)j * n0 + x00 + xi];
     }
     __syncthreads();
-    fftr::lds_passes<N1, +1, 1, NSEQ, SS, NT, 1>(buf, tw, tid,
-                                                 typename fftr::Rev<typename Cfg::FA, RList<>>::type{});
+    fftr::lds_passes<N1, +1, 1, XB, SS, NT, 1>(buf, tw, tid,
+                                               typename fftr::Rev<typename Cfg::FA, RList<>>::type{});
     cpx<float> v[RF];
     const cpx<float>* src = buf + s * SS;
 #pragma unroll

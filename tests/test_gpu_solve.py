@@ -165,7 +165,9 @@ def test_other_grid_sizes(n, R):
     assert np.max(np.abs(out.eff_stress[0] - sref)) / np.max(np.abs(sref)) < 1e-5
 
 
-@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 64, 64), (64, 32, 128)])
+# (24, 128, 32) and (36, 64, 16): the axis-1 kernels of n1 = 128 and 64 with a
+# ragged last block of x0 values (16 per workgroup)
+@pytest.mark.parametrize("shape", [(16, 16, 16), (32, 64, 64), (64, 32, 128), (24, 128, 32), (36, 64, 16)])
 def test_3d_parity(shape):
     mor = _mor()
     g = synth.rsa_spheres(*shape, r_lo=min(shape) / 8, r_hi=min(shape) / 5, seed=sum(shape), target_vf=0.2).g
