@@ -317,9 +317,10 @@ mor_status mor_warm_apply(const mor_plan_t* plans, int64_t nplans, const int64_t
  * row and column kernels; not part of the paper's method).  Variants of one
  * size give the same results up to FP32 rounding; a solve uses the variants
  * selected for its sizes when it starts.  Unselected sizes use variant 0,
- * except the row kernel of 512-point last axes with J2 phases, which uses
- * variant 4 (smaller register pass); mor_tune_get reports a selection, or 0
- * when there is none.  The selection is per process, shared by all threads
+ * except the row kernel with J2 phases on 512-point last axes (variant 4)
+ * and 384-point last axes (variant 9), whose smaller register passes leave
+ * room for the plastic state; mor_tune_get reports a selection, or 0 when
+ * there is none.  The selection is per process, shared by all threads
  * and devices.
  *   kernel  MOR_KERNEL_ROW (last axis) or MOR_KERNEL_COL (axis 0)
  *   ndim    2 or 3; length = the grid's last-axis length n[ndim-1] (row) or

@@ -123,6 +123,29 @@ struct Dft<8, SIGN> {
 };
 
 template <int SIGN>
+struct Dft<12, SIGN> {
+  // Good-Thomas 3 x 4 (coprime factors, so no twiddles between the stages):
+  // length-3 DFTs over n1 of x[(4 n1 + 3 n2) mod 12] for each n2, then
+  // length-4 DFTs over n2 for each k1, output k = (4 k1 + 9 k2) mod 12.
+  __device__ __forceinline__ static void run(cpx<float>* v) {
+    cpx<float> a[4][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 3; ++n1) a[n2][n1] = v[(4 * n1 + 3 * n2) % 12];
+      Dft<3, SIGN>::run(a[n2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      cpx<float> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4, SIGN>::run(b);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[(4 * k1 + 9 * k2) % 12] = b[k2];
+    }
+  }
+};
+
+template <int SIGN>
 struct Dft<16, SIGN> {
   // 4 x 4: length-4 DFTs over n1 of x[4 n1 + n2], twiddles w16^{n2 k1}, then
   // length-4 DFTs over n2; output k1 + 4 k2.  Fewer operations than halving

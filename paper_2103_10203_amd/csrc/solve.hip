@@ -181,7 +181,10 @@ int row_variant(int C, int nh, bool j2 = false) {
   std::lock_guard<std::mutex> lk(g_var_mu);
   auto it = g_row_var.find({C, nh});
   if (it != g_row_var.end()) return it->second;
+  // with the plastic state in registers the radix-4 (256) and radix-6 (192)
+  // register passes keep more waves resident than the defaults
   if (j2 && C == 3 && nh == 256) return 4;
+  if (j2 && C == 3 && nh == 192) return 9;
   return 0;
 }
 
@@ -394,7 +397,7 @@ void go_row_fast_v(SolveCtx& cx, Group& g, float* eps, float* sig, int rows) {
 
 template <int C, int NH, int MODE, int MAT>
 void go_row_fast(SolveCtx& cx, Group& g, float* eps, float* sig, int rows) {
-  static_assert(RowVar<C, NH>::count <= 9, "dispatch covers nine variants");
+  static_assert(RowVar<C, NH>::count <= 11, "dispatch covers eleven variants");
   switch (g.rvar) {
     case 0: go_row_fast_v<C, NH, 0, MODE, MAT>(cx, g, eps, sig, rows); break;
     case 1: go_row_fast_v<C, NH, 1, MODE, MAT>(cx, g, eps, sig, rows); break;
@@ -404,7 +407,9 @@ void go_row_fast(SolveCtx& cx, Group& g, float* eps, float* sig, int rows) {
     case 5: go_row_fast_v<C, NH, 5, MODE, MAT>(cx, g, eps, sig, rows); break;
     case 6: go_row_fast_v<C, NH, 6, MODE, MAT>(cx, g, eps, sig, rows); break;
     case 7: go_row_fast_v<C, NH, 7, MODE, MAT>(cx, g, eps, sig, rows); break;
-    default: go_row_fast_v<C, NH, 8, MODE, MAT>(cx, g, eps, sig, rows); break;
+    case 8: go_row_fast_v<C, NH, 8, MODE, MAT>(cx, g, eps, sig, rows); break;
+    case 9: go_row_fast_v<C, NH, 9, MODE, MAT>(cx, g, eps, sig, rows); break;
+    default: go_row_fast_v<C, NH, 10, MODE, MAT>(cx, g, eps, sig, rows); break;
   }
 }
 
@@ -493,6 +498,7 @@ void go_row_persist_v(SolveCtx& cx, Group& g, int rows) {
 
 template <int C, int NH, int MAT>
 void go_row_persist(SolveCtx& cx, Group& g, int rows) {
+  static_assert(RowVar<C, NH>::count <= 11, "dispatch covers eleven variants");
   switch (g.rvar) {
     case 0: go_row_persist_v<C, NH, 0, MAT>(cx, g, rows); break;
     case 1: go_row_persist_v<C, NH, 1, MAT>(cx, g, rows); break;
@@ -502,7 +508,9 @@ void go_row_persist(SolveCtx& cx, Group& g, int rows) {
     case 5: go_row_persist_v<C, NH, 5, MAT>(cx, g, rows); break;
     case 6: go_row_persist_v<C, NH, 6, MAT>(cx, g, rows); break;
     case 7: go_row_persist_v<C, NH, 7, MAT>(cx, g, rows); break;
-    default: go_row_persist_v<C, NH, 8, MAT>(cx, g, rows); break;
+    case 8: go_row_persist_v<C, NH, 8, MAT>(cx, g, rows); break;
+    case 9: go_row_persist_v<C, NH, 9, MAT>(cx, g, rows); break;
+    default: go_row_persist_v<C, NH, 10, MAT>(cx, g, rows); break;
   }
 }
 

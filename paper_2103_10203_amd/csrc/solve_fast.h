@@ -48,7 +48,7 @@ template <> struct RowCfg<3, 128, 4> { static constexpr int RL = 4, RB = 8;  usi
 template <> struct RowCfg<3, 128, 5> { static constexpr int RL = 8, RB = 4;  using RA = RList<16>; };
 template <> struct RowCfg<3, 128, 6> { static constexpr int RL = 8, RB = 16, PS = 5; using RA = RList<16>; };
 template <> struct RowVar<3, 128> { static constexpr int count = 7; };
-template <> struct RowCfg<3, 192, 0> { static constexpr int RL = 6, RB = 16; using RA = RList<8, 4>; };
+template <> struct RowCfg<3, 192, 0> { static constexpr int RL = 12, RB = 16; using RA = RList<16>; };
 template <> struct RowCfg<3, 192, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<8, 3>; };
 template <> struct RowCfg<3, 192, 2> { static constexpr int RL = 4, RB = 8;  using RA = RList<4, 4, 3>; };
 template <> struct RowCfg<3, 192, 3> { static constexpr int RL = 4, RB = 8;  using RA = RList<3, 4, 4>; };
@@ -57,13 +57,16 @@ template <> struct RowCfg<3, 192, 5> { static constexpr int RL = 4, RB = 16; usi
 template <> struct RowCfg<3, 192, 6> { static constexpr int RL = 6, RB = 8;  using RA = RList<4, 8>; };
 template <> struct RowCfg<3, 192, 7> { static constexpr int RL = 6, RB = 32; using RA = RList<8, 4>; };
 template <> struct RowCfg<3, 192, 8> { static constexpr int RL = 6, RB = 8;  using RA = RList<8, 4>; };
-template <> struct RowVar<3, 192> { static constexpr int count = 9; };
-template <> struct RowCfg<3, 256, 0> { static constexpr int RL = 8, RB = 8;  using RA = RList<4, 8>; };
+template <> struct RowCfg<3, 192, 9> { static constexpr int RL = 6, RB = 16; using RA = RList<8, 4>; };
+template <> struct RowCfg<3, 192, 10> { static constexpr int RL = 12, RB = 8; using RA = RList<16>; };
+template <> struct RowVar<3, 192> { static constexpr int count = 11; };
+template <> struct RowCfg<3, 256, 0> { static constexpr int RL = 16, RB = 16; using RA = RList<16>; };
 template <> struct RowCfg<3, 256, 1> { static constexpr int RL = 8, RB = 8;  using RA = RList<16, 2>; };
 template <> struct RowCfg<3, 256, 2> { static constexpr int RL = 8, RB = 16; using RA = RList<4, 8>; };
 template <> struct RowCfg<3, 256, 3> { static constexpr int RL = 8, RB = 4;  using RA = RList<4, 8>; };
 template <> struct RowCfg<3, 256, 4> { static constexpr int RL = 4, RB = 8;  using RA = RList<8, 8>; };
-template <> struct RowVar<3, 256> { static constexpr int count = 5; };
+template <> struct RowCfg<3, 256, 5> { static constexpr int RL = 8, RB = 8;  using RA = RList<4, 8>; };
+template <> struct RowVar<3, 256> { static constexpr int count = 6; };
 template <> struct RowCfg<6, 32, 0>  { static constexpr int RL = 4, RB = 16; using RA = RList<8>; };
 template <> struct RowCfg<6, 32, 1>  { static constexpr int RL = 8, RB = 16; using RA = RList<4>; };
 template <> struct RowVar<6, 32> { static constexpr int count = 2; };
