@@ -785,8 +785,8 @@ mor_status launch_final(SolveCtx& cx, Group& g, float* eps, float* sig) {
   MOR_LAUNCH_CHECK("row(final)");
   ev_end(cx, PK_FINAL, a);
   constexpr int S = Comp<C>::S;
-  const int n = (int)g.rves.size() * S;
-  k_sig_reduce<S><<<(n + 255) / 256, 256, 0, cx.st>>>(cx.d_plans, cx.d_st, g.d_list, (int)g.rves.size(), cx.d_sigpart, cx.off,
+  const int n = (int)g.rves.size() * S;  // one wavefront each
+  k_sig_reduce<S><<<(n + 3) / 4, 256, 0, cx.st>>>(cx.d_plans, cx.d_st, g.d_list, (int)g.rves.size(), cx.d_sigpart, cx.off,
                                                       cx.d_nblk, cx.d_eff, S);
   MOR_LAUNCH_CHECK("sig_reduce");
   return MOR_OK;

@@ -630,20 +630,28 @@ __global__ __launch_bounds__(256) void k_converge(const PlanDev* __restrict__ pl
   }
 }
 
-// Per-RVE grid mean of the stress: FP64 sum of the block partials in a fixed
-// order, divided by N (paper Sec. 2, volume average).
+// Per-RVE grid mean of the stress: FP64 sum of the block partials divided by
+// N (paper Sec. 2, volume average).  One wavefront per (RVE, component):
+// lane l sums partials l, l + 64, ... in order, then a fixed butterfly over
+// the lanes, so the result does not depend on scheduling.
 template <int S>
-__global__ void k_sig_reduce(const PlanDev* __restrict__ plans, const RveState* __restrict__ st,
-                             const int* __restrict__ rve_list, int nrve, const double* __restrict__ sig_part,
-                             Offs off, const int* __restrict__ nblk, double* __restrict__ eff, int eff_stride) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrve * S) return;
-  const int i = t / S, s = t - i * S;
+__global__ __launch_bounds__(256) void k_sig_reduce(const PlanDev* __restrict__ plans,
+                                                    const RveState* __restrict__ st,
+                                                    const int* __restrict__ rve_list, int nrve,
+                                                    const double* __restrict__ sig_part, Offs off,
+                                                    const int* __restrict__ nblk, double* __restrict__ eff,
+                                                    int eff_stride) {
+  const int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) / 64);  // uniform per wavefront
+  const int lane = threadIdx.x % 64;
+  if (w >= nrve * S) return;
+  const int i = w / S, s = w - i * S;
   const int b = rve_list[i];
   double acc = 0.0;
   const int nb = nblk[i];
-  for (int k = 0; k < nb; ++k) acc += sig_part[(off.part[b] + k) * S + s];
-  eff[(int64_t)b * eff_stride + s] = acc / (double)plans[st[b].plan].N;
+  for (int k = lane; k < nb; k += 64) acc += sig_part[(off.part[b] + k) * S + s];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) eff[(int64_t)b * eff_stride + s] = acc / (double)plans[st[b].plan].N;
 }
 
 }  // namespace mor_k
