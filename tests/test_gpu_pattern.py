@@ -111,6 +111,22 @@ def test_batched_plans_edge_cases_and_chunks(monkeypatch):
     _ = [_same_plan(a, b) for a, b in zip(seq, mor.make_plans(maps, Ms))]
 
 
+def test_batched_3d_plans_in_chunks_on_a_stream(monkeypatch):
+    """3D maps built one per chunk, on a non-default stream: the single-call
+    plans (the self-conjugate frequencies of a 3D grid are eight)."""
+    import torch
+    import paper_2103_10203_amd as mor
+    maps = [synth.rsa_spheres(16, 24, 12, r_lo=2.0, r_hi=4.0, seed=s, target_vf=0.2).g for s in (21, 22, 23)]
+    maps.append(np.zeros((16, 24, 12), np.uint8))
+    Ms = [1, 77, 16 * 24 * 12, 9]
+    seq = [mor.Plan(g, M) for g, M in zip(maps, Ms)]
+    monkeypatch.setenv("MOR_PLAN_SCRATCH_BYTES", "1")
+    st = torch.cuda.Stream()
+    bat = mor.make_plans(maps, Ms, stream=st)
+    for a, b in zip(seq, bat):
+        _same_plan(a, b)
+
+
 def test_batched_plan_solves_like_single():
     """A solve on a batched plan gives the single plan's results bit for bit."""
     import paper_2103_10203_amd as mor
