@@ -318,7 +318,7 @@ mor_status mor_warm_apply(const mor_plan_t* plans, int64_t nplans, const int64_t
  * size give the same results up to FP32 rounding; a solve uses the variants
  * selected for its sizes when it starts.  Unselected sizes use variant 0,
  * except the row kernel with J2 phases on 512-point last axes (variant 4)
- * and 384-point last axes (variant 9), whose smaller register passes leave
+ * and 384-point last axes (variant 2), whose radix-4 register passes leave
  * room for the plastic state; mor_tune_get reports a selection, or 0 when
  * there is none.  The selection is per process, shared by all threads
  * and devices.

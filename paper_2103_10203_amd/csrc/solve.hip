@@ -181,10 +181,10 @@ int row_variant(int C, int nh, bool j2 = false) {
   std::lock_guard<std::mutex> lk(g_var_mu);
   auto it = g_row_var.find({C, nh});
   if (it != g_row_var.end()) return it->second;
-  // with the plastic state in registers the radix-4 (256) and radix-6 (192)
-  // register passes keep more waves resident than the defaults
+  // with the plastic state in registers the radix-4 register passes keep
+  // more waves resident than the defaults (measured on J2 load paths)
   if (j2 && C == 3 && nh == 256) return 4;
-  if (j2 && C == 3 && nh == 192) return 9;
+  if (j2 && C == 3 && nh == 192) return 2;
   return 0;
 }
 
