@@ -42,6 +42,32 @@ def test_load_path_matches_oracle(n, R, steps):
     assert np.max(alpha) > 0.0
 
 
+@pytest.mark.parametrize("n1", [384, 512])
+def test_load_path_long_rows(n1):
+    """Rows of 384 and 512 points, where J2 phases select their own row-kernel
+    variant (a radix-4 register pass), against the oracle."""
+    import torch
+    import paper_2103_10203_amd as mor
+    n0, steps = 32, 3
+    g = synth.rsa_fibres(n0, n1, 3.0, 6.0, seed=n1, target_vf=0.35).g
+    M = int(math.ceil(0.05 * g.size))
+    final = np.array([0.015, -0.002, 0.004])
+    path = np.stack([final * (k + 1) / steps for k in range(steps)])
+    plan = mor.Plan(g, M)
+    state = torch.zeros(5 * g.size, dtype=torch.float32, device="cuda")
+    out = mor.solve_path(plan, path, native_phases(j2=True), 1e-6, state)
+    assert out.status == mor.MOR_OK
+    p = pattern.build_pattern(g, M)
+    ref = solver.solve_path(g, ORACLE_J2, solver.macro_tensor(final, 2), steps, mask=p.mask(), tol=1e-10)
+    for k in range(steps):
+        want = stress_comps(ref[k].sigma_bar, 2)
+        err = np.max(np.abs(out.eff_stress[k] - want)) / np.max(np.abs(want))
+        assert err < 1e-4, (k, err)
+    alpha = state.view(5, n0, n1)[4].double().cpu().numpy()
+    assert np.max(alpha) > 0.0
+    assert rel_l2(alpha, ref[-1].alpha) < 1e-3
+
+
 def test_homogeneous_j2_one_iteration_per_step():
     import torch
     import paper_2103_10203_amd as mor
