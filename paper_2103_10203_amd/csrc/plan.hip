@@ -1,8 +1,10 @@
 // Adapted sampling pattern and plan tables (paper Sec. 4.2; reduced scheme of
-// Sec. 4).  Every step runs on the device:
+// Sec. 4), for one microstructure or a batch of them on one grid.  Every step
+// runs on the device, each as one launch over the batch:
 //   1. FP64 FFT of the phase indicator g (Stockham along each axis),
 //   2. per-frequency ranking keys and pair representatives,
-//   3. bitonic sort of the representatives by (key desc, |s|^2, lexrank),
+//   3. bitonic sort of the conjugate pairs by (key desc, |s|^2, lexrank), and
+//      the merge of the self-conjugate frequencies into that order,
 //   4. pair-atomic selection of the first M frequencies,
 //   5. compaction of the selection mask into sorted linear indices,
 //   6. column / last-axis tables, Green-operator directions, twiddles.
@@ -825,10 +827,11 @@ struct PinnedStage {
 
 // Builds `cnt` plans of one grid (P[i]->M may differ) from host phase maps
 // maps[0..cnt) (each N bytes, already checked), staged through `pinned`
-// (cnt N bytes of pinned host memory, or NULL to copy the maps one by one)// [cnt][N]: every step is one launch over the whole batch (plan = a grid
-// dimension of the launch), with two host synchronisations for the sizes of
-// the per-plan tables.  Scratch: about 30 N + 16 N' bytes per plan (N' the
-// power of two at or above the number of conjugate pairs).
+// (cnt N bytes of pinned host memory, or NULL to copy the maps one by one).
+// Every step is one launch over the whole batch (plan = a grid dimension of
+// the launch), with two host synchronisations for the sizes of the per-plan
+// tables.  Scratch: about 30 N + 16 N' bytes per plan (N' the power of two at
+// or above the number of conjugate pairs).
 static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint8_t* const* maps, uint8_t* pinned,
                                    hipStream_t st) {
   PlanScratch sc(st);  // declared first: released last, after the stream has drained
