@@ -326,11 +326,24 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
     }
   }
   if (MODE == MODE_FINAL) {
-    __shared__ double red[16];
+    // all S sums at once (each in the fixed order of a wavefront tree, then
+    // the wavefronts in order), with one exchange through LDS
+    __shared__ double red[(NT / 64) * S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      double w = block_sum_d(acc[s], red);
-      if (tid == 0) sig_part[(off.part[b] + tile) * S + s] = w;
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) acc[s] += __shfl_down(acc[s], o, 64);
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) red[(tid >> 6) * S + s] = acc[s];
+    }
+    __syncthreads();
+    if (tid < S) {
+      double w = 0.0;
+      for (int q = 0; q < NT / 64; ++q) w += red[q * S + tid];
+      sig_part[(off.part[b] + tile) * S + tid] = w;
     }
     return;
   }
