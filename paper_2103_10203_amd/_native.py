@@ -306,6 +306,23 @@ SCHED_GRID = 0
 SCHED_PERSISTENT = 1
 
 
+def _check_tensor(t, name, dtype, numel):
+    """A device buffer handed to the library by pointer: a contiguous CUDA
+    tensor of the expected dtype and exact size, else ValueError (a wrong
+    size would make the kernels read or write outside it)."""
+    if t is None:
+        return
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.numel() != int(numel):
+        raise ValueError(f"{name} must have {int(numel)} elements, got {t.numel()}")
+
+
 def _opts(max_iter, check_every, warm_start, stream, precision=PREC_FP32, transform=TRANSFORM_AUTO, use_graph=0,
           schedule=SCHED_GRID):
     ws = ct.c_void_p(warm_start.data_ptr()) if warm_start is not None else ct.c_void_p(None)
@@ -343,6 +360,7 @@ def solve(plan: Plan, macro_strain, phases, tol: float, max_iter: int = 0, warm_
     B, C = eb.shape
     if C != plan.ncomp:
         raise ValueError(f"macro strain needs {plan.ncomp} components")
+    _check_tensor(warm_start, "warm_start", "complex64", B * C * plan.n_coeff)
     S = plan.nstress
     out, eff, its, res, strain, stress, coeffs = _outputs(B, S, B, want_fields, want_coeffs, B * plan.N, C,
                                                           B * C * plan.n_coeff)
@@ -365,10 +383,13 @@ def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int 
     eb = np.ascontiguousarray(np.atleast_2d(macro_strain), dtype=np.float64)
     B, C = eb.shape
     po = np.ascontiguousarray(plan_of, dtype=np.int64)
+    if po.shape != (B,) or (B and (po.min() < 0 or po.max() >= len(plans))):
+        raise ValueError("plan_of needs one index into plans per RVE")
     handles = (ct.c_void_p * len(plans))(*[p.handle.value for p in plans])
     S = plans[0].nstress
     npts = int(sum(plans[i].N for i in po))
     ncoef = int(sum(plans[i].n_coeff for i in po)) * C
+    _check_tensor(warm_start, "warm_start", "complex64", ncoef)
     out, eff, its, res, strain, stress, coeffs = _outputs(B, S, B, want_fields, want_coeffs, npts, C, ncoef)
     opts = _opts(max_iter, check_every, warm_start, stream, precision, transform, use_graph, schedule)
     st = _check(lib.mor_solve_multi(handles, len(plans), _np_ptr(po), _np_ptr(eb), B, _phases(phases), float(tol),
@@ -383,6 +404,9 @@ def solve_path(plan: Plan, macro_strains, phases, tol: float, state, max_iter: i
     """mor_solve_path: macro_strains [steps][ncomp]; state: torch float32 cuda [nstate][N] (in/out)."""
     eb = np.ascontiguousarray(np.atleast_2d(macro_strains), dtype=np.float64)
     steps, C = eb.shape
+    if C != plan.ncomp:
+        raise ValueError(f"macro strains need {plan.ncomp} components")
+    _check_tensor(state, "state", "float32", (5 if plan.ndim == 2 else 7) * plan.N)
     S = plan.nstress
     out, eff, its, res, strain, stress, coeffs = _outputs(steps, S, steps, want_fields, False, plan.N, C, 0)
     opts = _opts(max_iter, check_every, None, stream, precision, transform, use_graph, schedule)
@@ -463,6 +487,9 @@ class MLP:
 
     def forward(self, X, precision: int = MLP_FP32, stream=None):
         torch = _torch()
+        if X.dim() != 2 or X.shape[1] != self.in_dim:
+            raise ValueError(f"X must be [B][{self.in_dim}]")
+        _check_tensor(X, "X", "float32", X.shape[0] * self.in_dim)
         B = X.shape[0]
         Y = torch.empty((B, self.out_dim), dtype=torch.float32, device=X.device)
         _check(lib.mor_mlp_forward(self._h, ct.c_void_p(X.data_ptr()), B, ct.c_void_p(Y.data_ptr()),
@@ -470,6 +497,10 @@ class MLP:
         return Y
 
     def grad(self, X, T, stream=None) -> float:
+        if X.dim() != 2 or X.shape[1] != self.in_dim or T.dim() != 2 or T.shape != (X.shape[0], self.out_dim):
+            raise ValueError(f"X must be [B][{self.in_dim}] and T [B][{self.out_dim}]")
+        _check_tensor(X, "X", "float32", X.numel())
+        _check_tensor(T, "T", "float32", T.numel())
         loss = ct.c_double()
         _check(lib.mor_mlp_grad(self._h, ct.c_void_p(X.data_ptr()), ct.c_void_p(T.data_ptr()), X.shape[0],
                                 ct.byref(loss), _stream_ptr(stream)))
@@ -506,6 +537,7 @@ def warm_features(plans, plan_of, nslots: int, stream=None):
 def warm_targets(plans, plan_of, nslots: int, phases, coeffs, stream=None):
     torch = _torch()
     po = np.ascontiguousarray(plan_of, dtype=np.int64)
+    _check_tensor(coeffs, "coeffs", "complex64", 9 * int(sum(plans[i].n_coeff for i in po)))
     T = torch.empty((len(po), 18 * nslots), dtype=torch.float32, device="cuda")
     _check(lib.mor_warm_targets(_plan_array(plans), len(plans), _np_ptr(po), len(po), nslots, _phases(phases),
                                 ct.c_void_p(coeffs.data_ptr()), ct.c_void_p(T.data_ptr()), _stream_ptr(stream)))
@@ -516,6 +548,9 @@ def warm_apply(plans, plan_of, nslots: int, phases, Y, macro_strain, stream=None
     torch = _torch()
     po = np.ascontiguousarray(plan_of, dtype=np.int64)
     eb = np.ascontiguousarray(macro_strain, dtype=np.float64)
+    if eb.shape != (len(po), 3):
+        raise ValueError("macro_strain must be [B][3]")
+    _check_tensor(Y, "Y", "float32", len(po) * 18 * int(nslots))
     n = int(sum(plans[i].n_coeff for i in po)) * 3
     W = torch.empty(n, dtype=torch.complex64, device="cuda")
     _check(lib.mor_warm_apply(_plan_array(plans), len(plans), _np_ptr(po), len(po), nslots, _phases(phases),

@@ -135,7 +135,7 @@ struct RveState {
   double denom;     // N * ||eps_bar||_F (or N when eps_bar = 0)
   double tol;
   int32_t max_iter;
-  int32_t pad_;
+  int32_t warm_ok;  // 1: the warm start (if any) is used; 0: it held a NaN/Inf and the RVE starts cold
 };
 
 // Kernel ids of the profiling counters.

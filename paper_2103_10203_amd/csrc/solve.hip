@@ -1004,7 +1004,7 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     r.denom = (double)plans[plan_of[b]]->N * (nrm2 > 0.0 ? std::sqrt(nrm2) : 1.0);
     r.tol = tol;
     r.max_iter = max_iter;
-    r.pad_ = 0;
+    r.warm_ok = 1;
   }
   if ((s = upload(cx, cx.d_st, hs)) != MOR_OK) return s;
   if ((s = upload(cx, cx.d_ebar, eb)) != MOR_OK) return s;
@@ -1057,6 +1057,14 @@ struct GraphChunk {
 
 mor_status run(SolveCtx& cx, const cpx<float>* warm, const mor_solve_opts* opts, float* eps, float* sig) {
   mor_status s;
+  if (warm) {
+    // an RVE whose warm coefficients hold a NaN/Inf starts cold instead
+    for (auto& g : cx.groups) {
+      k_warm_check<<<(unsigned)g.rves.size(), 256, 0, cx.st>>>(cx.d_plans, g.d_list, (int)g.rves.size(), cx.d_st,
+                                                               warm, cx.off, cx.C);
+      MOR_LAUNCH_CHECK("warm_check");
+    }
+  }
   for (auto& g : cx.groups)
     if ((s = do_init(cx, g, warm)) != MOR_OK) return s;
   const int check = (opts && opts->check_every > 0) ? opts->check_every : 8;

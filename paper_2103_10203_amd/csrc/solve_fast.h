@@ -594,7 +594,7 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
       green<C>(nv, tr_, nr_, mat.g_inv_mu0, mat.g_k);
       green<C>(nv, ti_, ni_, mat.g_inv_mu0, mat.g_k);
     } else {
-      if (warm) {
+      if (warm && st[b].warm_ok) {
         float wr[C], wi[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {

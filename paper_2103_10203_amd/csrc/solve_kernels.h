@@ -470,7 +470,7 @@ __global__ __launch_bounds__(256) void k_col(const PlanDev* __restrict__ plans, 
         green<C, T>(nv, tr_, nr_, mat.g_inv_mu0, mat.g_k);
         green<C, T>(nv, ti_, ni_, mat.g_inv_mu0, mat.g_k);
       } else {
-        if (warm) {
+        if (warm && st[b].warm_ok) {
           T wr[C], wi[C];
 #pragma unroll
           for (int c = 0; c < C; ++c) {
@@ -586,6 +586,31 @@ __global__ __launch_bounds__(256) void k_mid(const PlanDev* __restrict__ plans, 
       L[c * lcs + (int64_t)j2 * rows + (int64_t)(x00 + xi) * n1 + x1] = R[(c * xb + xi) * n1 + x1];
     }
   }
+}
+
+// Warm-start guard: one workgroup per RVE scans its warm coefficients (the
+// zero-frequency and dropped entries are not used and are skipped); a NaN or
+// Inf anywhere makes the RVE start cold instead, so the iteration still runs
+// from a finite compatible field.
+__global__ __launch_bounds__(256) void k_warm_check(const PlanDev* __restrict__ plans,
+                                                    const int* __restrict__ rve_list, int nrve,
+                                                    RveState* __restrict__ st, const cpx<float>* __restrict__ warm,
+                                                    Offs off, int C) {
+  const int i = blockIdx.x;
+  if (i >= nrve) return;
+  const int b = rve_list[i];
+  const PlanDev& P = plans[st[b].plan];
+  const int ncoef = P.ncoef;
+  const cpx<float>* w = warm + off.coef[b];
+  int bad = 0;
+  for (int t = threadIdx.x; t < C * ncoef; t += blockDim.x) {
+    const int e = t % ncoef;
+    if (P.coef_flag[e] & (COEF_ZERO | COEF_DEAD)) continue;
+    const cpx<float> v = w[t];
+    bad |= (isfinite(v.x) && isfinite(v.y)) ? 0 : 1;
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) st[b].warm_ok = bad ? 0 : 1;
 }
 
 // Convergence decision after a column pass (one wavefront per RVE, 4 per

@@ -1,0 +1,105 @@
+"""Failure paths of the solve through the C ABI (each forced by ordinary
+input values; no kernel is made to fault or hang):
+
+* a warm start holding a NaN/Inf: that RVE starts cold (the plain iteration
+  is the fallback), the others keep their warm start;
+* phase parameters outside their domain (Sec. 2: mu > 0, positive bulk
+  modulus, sigma_y0 > 0 and H >= 0 for a plastic phase) refused at solve
+  time before any device work;
+* an iteration that overflows FP32 (a macro strain of 1e35) ends with
+  MOR_E_NONFINITE after one iteration, while the other RVEs of the batch
+  still converge to their own results.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_common import native_phases
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(mor, n=64, seed=601):
+    g = synth.rsa_fibres(n, n, n / 16, n / 8, seed=seed, target_vf=0.35).g
+    return mor.Plan(g, int(math.ceil(0.05 * g.size)))
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_nonfinite_warm_start_falls_back_to_cold(bad):
+    import torch
+    import paper_2103_10203_amd as mor
+    plan = _plan(mor)
+    eb = synth.macro_strains(3, 3, 5e-3, seed=11)
+    ph = native_phases()
+    cold = mor.solve(plan, eb, ph, 1e-6, want_coeffs=True)
+    warm = cold.coeffs.clone()  # the converged coefficients: a near-perfect start
+    warm[1, 2, plan.n_coeff // 2] = complex(bad, 0.0)
+    hot = mor.solve(plan, eb, ph, 1e-6, warm_start=warm.reshape(-1))
+    assert hot.status == mor.MOR_OK
+    # RVE 1 ran from the cold start: the same iterations and stress bit for bit
+    assert hot.iterations[1] == cold.iterations[1]
+    assert np.array_equal(hot.eff_stress[1], cold.eff_stress[1])
+    # the others used their (finite) warm start
+    assert hot.iterations[0] <= 2 and hot.iterations[2] <= 2
+    torch.cuda.synchronize()
+
+
+def test_nonfinite_warm_start_3d_and_multi():
+    import paper_2103_10203_amd as mor
+    g = synth.rsa_spheres(32, 32, 32, 3.0, 5.0, seed=602, target_vf=0.2).g
+    plan = mor.Plan(g, int(math.ceil(0.05 * g.size)))
+    eb = synth.macro_strains(2, 6, 1e-3, seed=12)
+    ph = native_phases()
+    cold = mor.solve_multi([plan], [0, 0], eb, ph, 1e-6, want_coeffs=True)
+    warm = cold.coeffs.clone()
+    warm[plan.n_coeff * 6 + 3] = complex(0.0, float("nan"))  # RVE 1
+    hot = mor.solve_multi([plan], [0, 0], eb, ph, 1e-6, warm_start=warm)
+    assert hot.status == mor.MOR_OK
+    assert hot.iterations[1] == cold.iterations[1]
+    assert np.array_equal(hot.eff_stress[1], cold.eff_stress[1])
+    assert hot.iterations[0] <= 2
+
+
+@pytest.mark.parametrize("field,value", [("mu", 0.0), ("mu", -1.0), ("lam", -30.0), ("lam", float("nan")),
+                                         ("sigma_y0", 0.0), ("H", -0.1)])
+def test_invalid_phase_rejected_at_solve(field, value):
+    import dataclasses
+    import paper_2103_10203_amd as mor
+    plan = _plan(mor, n=32, seed=603)
+    ph = native_phases(j2=True)
+    ph[0] = dataclasses.replace(ph[0], **{field: value})
+    eb = np.array([[1e-3, 0.0, 0.0]])
+    with pytest.raises(mor.MorError) as ei:
+        mor.solve(plan, eb, ph, 1e-6)
+    assert ei.value.status == mor.MOR_E_INVALID_ARG
+    import torch
+    state = torch.zeros(5 * plan.N, dtype=torch.float32, device="cuda")
+    with pytest.raises(mor.MorError) as ei:
+        mor.solve_path(plan, eb, ph, 1e-6, state)
+    assert ei.value.status == mor.MOR_E_INVALID_ARG
+
+
+def test_invalid_solve_arguments():
+    import paper_2103_10203_amd as mor
+    plan = _plan(mor, n=32, seed=604)
+    ph = native_phases()
+    for eb, tol in (([[float("inf"), 0.0, 0.0]], 1e-6), ([[1e-3, 0.0, 0.0]], 0.0), ([[1e-3, 0.0, 0.0]], -1.0)):
+        with pytest.raises(mor.MorError) as ei:
+            mor.solve(plan, np.array(eb), ph, tol)
+        assert ei.value.status == mor.MOR_E_INVALID_ARG
+
+
+def test_overflow_reports_nonfinite():
+    import paper_2103_10203_amd as mor
+    plan = _plan(mor, seed=605)
+    ph = native_phases()
+    eb = np.array([[1e-3, -2e-3, 5e-4], [1e35, 0.0, 0.0]])
+    out = mor.solve(plan, eb, ph, 1e-6, allow=(mor.MOR_E_NONFINITE,))
+    assert out.status == mor.MOR_E_NONFINITE
+    assert out.iterations[1] == 1 and not np.isfinite(out.residual[1])
+    alone = mor.solve(plan, eb[:1], ph, 1e-6)
+    assert alone.status == mor.MOR_OK
+    assert out.iterations[0] == alone.iterations[0]
+    assert np.array_equal(out.eff_stress[0], alone.eff_stress[0])
