@@ -1,6 +1,8 @@
 """Geometrically adapted sampling pattern (paper Sec. 4.2, Figs. GeoRealFourier /
 SamplingReduced): FFT of the binary phase indicator g, then keep the given
-fraction R of frequencies with the highest amplitudes |g^(xi)|.
+fraction R of frequencies with the highest amplitudes |g^(xi)|.  Also the
+fixed radial pattern it is compared with (Sec. 4.1, fig. FixedSampling):
+straight lines through xi = 0 at equally spaced angles, independent of g.
 
 The paper is silent on ties, conjugate pairs, xi = 0, the rounding of R*N and
 floating-point noise.  The oracle fixes them as follows (listed in the design doc):
@@ -158,3 +160,92 @@ def _unstable_cut(keys, ratio, cut_key) -> bool:
         if np.any(np.abs(ratio - b) <= UNSTABLE_REL * b):
             return True
     return False
+
+
+# ---------------------------------------------------------------- fixed radial pattern
+RADIAL_TIE_MARGIN = 1e-9
+
+
+def _round_half_away(x: np.ndarray) -> np.ndarray:
+    """Nearest integer, halves away from zero (odd-symmetric: r(-x) = -r(x))."""
+    return np.sign(x) * np.floor(np.abs(x) + 0.5)
+
+
+def radial_lines(shape, L: int):
+    """Signed frequencies (s0, s1) of the fixed radial sampling pattern with L
+    straight lines through xi = 0 (paper Sec. 4.1, fig. FixedSampling; the
+    paper does not give the rasterisation, so this is a reading):
+
+    line l = 0..L-1 has the angle theta_l = l pi / L, measured from the axis-1
+    direction towards axis 0.  A line with theta in [0, pi/4] or [3 pi/4, pi)
+    (integer test 4l <= L or 4l >= 3L) advances one step along axis 1 at a
+    time: s1 = -(n1/2 - 1) .. n1/2 - 1 and s0 = round(s1 tan theta).  The
+    other lines advance along axis 0: s0 = -(n0/2 - 1) .. n0/2 - 1 and
+    s1 = round(s0 tan(pi/2 - theta)).  round = nearest, halves away from
+    zero; points beyond |s_a| <= n_a/2 - 1 are dropped.  The Nyquist index
+    n_a/2 is never used, so every line is closed under m -> -m.
+
+    Returns (s0, s1, margin): the points (with repeats) and the smallest
+    distance of any rounded product from a half-integer (rounding ties do not
+    occur: tan(l pi / L) is irrational unless it is 0 or +-1)."""
+    n0, n1 = int(shape[0]), int(shape[1])
+    h0, h1 = n0 // 2 - 1, n1 // 2 - 1
+    S0, S1 = [], []
+    margin = np.inf
+    for l in range(int(L)):
+        if 4 * l <= L or 4 * l >= 3 * L:
+            u = np.arange(-h1, h1 + 1, dtype=np.float64)
+            x = u * np.tan(np.pi * l / L)
+            v = _round_half_away(x)
+            keep = np.abs(v) <= h0
+            S0.append(v[keep].astype(np.int64))
+            S1.append(u[keep].astype(np.int64))
+        else:
+            u = np.arange(-h0, h0 + 1, dtype=np.float64)
+            x = u * np.tan(np.pi * (L - 2 * l) / (2 * L))
+            v = _round_half_away(x)
+            keep = np.abs(v) <= h1
+            S0.append(u[keep].astype(np.int64))
+            S1.append(v[keep].astype(np.int64))
+        frac = np.abs(x - np.floor(x) - 0.5)
+        margin = min(margin, float(frac.min()) if frac.size else np.inf)
+    return np.concatenate(S0), np.concatenate(S1), margin
+
+
+def build_radial_pattern(shape, L: int) -> Pattern:
+    """Fixed radial pattern of L lines (2D only; Sec. 4.1).  The pattern does
+    not depend on the microstructure.  Its rank order (``rank_idx``, used for
+    the warm-start slots) is the adapted ranking with every selected
+    frequency given the same key: pairs by |s|^2 ascending, then lexrank of
+    the representative.  ``unstable`` flags a rounding product within
+    RADIAL_TIE_MARGIN of a half-integer."""
+    shape = tuple(int(n) for n in shape)
+    if len(shape) != 2:
+        raise ValueError("the radial pattern is defined for 2D grids")
+    if L < 1:
+        raise ValueError("L must be >= 1")
+    n0, n1 = shape
+    N = n0 * n1
+    s0, s1, margin = radial_lines(shape, L)
+    sel = np.zeros(N, dtype=bool)
+    sel[(s0 % n0) * n1 + (s1 % n1)] = True
+    ks = _coords(shape)
+    s = [signed_freq(k, n) for k, n in zip(ks, shape)]
+    s2 = s[0].astype(np.int64) ** 2 + s[1].astype(np.int64) ** 2
+    lex = _lexrank(s, shape)
+    conj = conjugate_index(shape)
+    lin = np.arange(N, dtype=np.int64)
+    if not np.array_equal(sel, sel[conj]):
+        raise AssertionError("radial pattern not closed under m -> -m")
+    reps = lin[sel & (lex <= lex[conj])]
+    reps = reps[np.lexsort((lex[reps], s2[reps]))]
+    rank = []
+    for a in reps.tolist():
+        rank.append(a)
+        if conj[a] != a:
+            rank.append(int(conj[a]))
+    rank_idx = np.asarray(rank, dtype=np.int64)
+    keys = sel.astype(np.float32).reshape(shape)
+    M = int(rank_idx.size)
+    return Pattern(shape=shape, M=M, sorted_idx=np.sort(rank_idx), rank_idx=rank_idx, keys=keys,
+                   unstable=bool(margin < RADIAL_TIE_MARGIN))

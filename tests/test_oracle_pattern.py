@@ -162,3 +162,96 @@ def test_laminate_pattern_covers_support():
     assert set(support.tolist()) <= set(p.sorted_idx.tolist())
     k0, k1 = np.unravel_index(support, g.shape)
     assert np.all(k1 == 0)
+
+
+# ---------------------------------------------------------------- fixed radial pattern (Sec. 4.1)
+def _radial_set(shape, L):
+    p = pattern.build_radial_pattern(shape, L)
+    n0, n1 = shape
+    s0 = pattern.signed_freq(p.sorted_idx // n1, n0)
+    s1 = pattern.signed_freq(p.sorted_idx % n1, n1)
+    return p, set(zip(s0.tolist(), s1.tolist()))
+
+
+@pytest.mark.parametrize("shape", [(16, 12), (24, 24), (256, 256)])
+def test_radial_closed_forms(shape):
+    """L = 1: the axis-1 line through xi = 0 without its Nyquist point; L = 2:
+    both axis lines; L = 4 on a square grid: the axes and both diagonals."""
+    n0, n1 = shape
+    h0, h1 = n0 // 2 - 1, n1 // 2 - 1
+    _, s = _radial_set(shape, 1)
+    assert s == {(0, b) for b in range(-h1, h1 + 1)}
+    _, s = _radial_set(shape, 2)
+    assert s == {(0, b) for b in range(-h1, h1 + 1)} | {(a, 0) for a in range(-h0, h0 + 1)}
+    if n0 == n1:
+        p, s = _radial_set(shape, 4)
+        want = {(a, b) for a in range(-h0, h0 + 1) for b in range(-h1, h1 + 1)
+                if a == 0 or b == 0 or abs(a) == abs(b)}
+        assert s == want and p.M_actual == 4 * (n0 - 1) - 3
+
+
+@pytest.mark.parametrize("shape", [(16, 16), (12, 20), (24, 18)])
+@pytest.mark.parametrize("L", [1, 3, 5, 6, 7, 12])
+def test_radial_pixel_membership_brute_force(shape, L):
+    """The line rasterisation restated pixel by pixel: a frequency belongs to
+    line l when, along the line's minor axis, it is the lattice point nearest
+    to the line (distance below one half) and inside the non-Nyquist box."""
+    n0, n1 = shape
+    h0, h1 = n0 // 2 - 1, n1 // 2 - 1
+    want = set()
+    for a in range(-h0, h0 + 1):
+        for b in range(-h1, h1 + 1):
+            for l in range(L):
+                th = math.pi * l / L
+                if 4 * l <= L or 4 * l >= 3 * L:
+                    hit = abs(a - b * math.tan(th)) < 0.5
+                else:
+                    hit = abs(b - a / math.tan(th)) < 0.5
+                if hit:
+                    want.add((a, b))
+                    break
+    _, s = _radial_set(shape, L)
+    assert s == want
+
+
+@pytest.mark.parametrize("L", [2, 4, 6, 8, 16])
+def test_radial_square_symmetry_and_nesting(L):
+    """Even L on a square grid: invariant under swapping the axes and under
+    reflecting axis 0 (the line set maps onto itself); the L-line pattern is
+    contained in the 2L- and 3L-line patterns; conjugate-closed; xi = 0
+    first in rank order and |s|^2 non-decreasing over the pairs."""
+    shape = (32, 32)
+    p, s = _radial_set(shape, L)
+    assert s == {(b, a) for a, b in s}
+    assert s == {(-a, b) for a, b in s}
+    assert s == {(-a, -b) for a, b in s}
+    for k in (2, 3):
+        _, s2 = _radial_set(shape, k * L)
+        assert s <= s2
+    assert p.rank_idx[0] == 0
+    n = 32
+    r = p.rank_idx
+    sq = [pattern.signed_freq(i // n, n) ** 2 + pattern.signed_freq(i % n, n) ** 2 for i in r.tolist()]
+    reps = sq[1::2]  # [xi = 0, rep, partner, rep, partner, ...]: no self-conjugate point besides 0
+    assert all(reps[i] <= reps[i + 1] for i in range(len(reps) - 1))
+    assert all(sq[i] == sq[i + 1] for i in range(1, len(sq) - 1, 2))
+    assert not p.unstable
+
+
+def test_radial_paper_counts_256():
+    """On 256^2 one line keeps 0.39 % and two lines 0.78 % of the frequencies,
+    the two smallest fixed-pattern R values of the paper's 2D tables
+    (tables OneIncTimeFixed / PlastTimeFixed).  The larger line counts of this
+    rasterisation keep slightly more than the paper's R (a reading)."""
+    counts = {L: pattern.build_radial_pattern((256, 256), L).M_actual for L in (1, 2, 4, 8)}
+    assert round(100 * counts[1] / 65536, 2) == 0.39
+    assert round(100 * counts[2] / 65536, 2) == 0.78
+    assert counts[4] == 1017 and counts[8] == 2025
+
+
+def test_radial_rounding_margin():
+    """No rasterised product lies near a rounding tie on the supported grids,
+    so FP64 evaluations with different tan routines select the same points."""
+    for n in (64, 128, 256, 384, 512, 1024):
+        for L in (1, 2, 3, 4, 8, 12, 16, 32, 64, 128):
+            assert pattern.radial_lines((n, n), L)[2] > 1e-6
