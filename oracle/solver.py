@@ -160,6 +160,25 @@ def solve_path(g, phases, eps_bar_final, steps, mask=None, tol=1e-8, max_iter=10
     return out
 
 
+def compatibility_step(g, phases, eps_bar, eps_red, state=None, gamma_kind=green.ROTATED, C0=None) -> Result:
+    """Compatibility step (paper Sec. 4.1 post-processing, applied alone to the
+    adapted-pattern solutions in Sec. 5.1): the Lippmann-Schwinger equation is
+    solved once on the full set of frequencies from the fields of a reduced
+    solution, i.e. one pass of steps a)-d) with every frequency kept,
+    starting from eps_red:
+      tau = sigma(eps_red) - C0 : eps_red,  eps^(xi) = -Gamma^(xi) : tau^(xi)
+      (xi != 0),  eps^(0) = N eps_bar,  eps_comp = iFFT(eps^),
+    followed by sigma(eps_comp) and its grid mean.  ``state`` is the committed
+    J2 state the reduced solution was computed with (None: virgin material);
+    it is used, not updated.  ``residuals[0]`` is the RMS change
+    ||eps_comp - eps_red|| / ||eps_bar||."""
+    r = solve(g, phases, eps_bar, mask=None, tol=0.0, max_iter=1, gamma_kind=gamma_kind, eps0=eps_red,
+              state=state, C0=C0)
+    r.eps_p = None
+    r.alpha = None
+    return r
+
+
 def macro_error(sigma_bar, sigma_bar_ref) -> float:
     """E_bar = ||sigma_bar - sigma_bar_ref|| / ||sigma_bar_ref|| (paper Sec. 5)."""
     return float(np.linalg.norm(sigma_bar - sigma_bar_ref) / np.linalg.norm(sigma_bar_ref))

@@ -287,3 +287,81 @@ def test_homogeneous_j2_rve_matches_material_point():
         assert res.iterations == 1
         s, ep, al = material.j2_return((eb * n / 10)[None], ep, al, J2M.lam, J2M.mu, 0.25, 1.0, True)
         assert np.max(np.abs(res.sigma_bar - s[0])) < 1e-13
+
+
+# ---------------------------------------------------------------- compatibility step (Secs. 4.1, 5.1)
+def test_compatibility_step_fixed_point_of_full_solution():
+    """The full-set solution is the fixed point of the full scheme, so the
+    compatibility step leaves it unchanged."""
+    g = synth.disk(24, 24, 7.0)
+    eb = solver.macro_tensor([1e-3, -4e-4, 3e-4], 2)
+    full = solver.solve(g, PH, eb, tol=1e-14, max_iter=2000)
+    c = solver.compatibility_step(g, PH, eb, full.eps)
+    assert np.max(np.abs(c.eps - full.eps)) < 1e-12 * np.max(np.abs(full.eps)) * 1e3
+    assert np.allclose(c.sigma_bar, full.sigma_bar, rtol=0, atol=1e-12 * np.abs(full.sigma_bar).max())
+    assert c.residuals[0] < 1e-10
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_compatibility_step_contracts_towards_full_solution(dim):
+    """One pass of the basic scheme contracts the distance to its fixed point
+    (the full-set solution): the reduced solution moves closer to it in L2.
+    A sign or index error in the pass would push it away."""
+    if dim == 2:
+        g = synth.rsa_fibres(32, 32, 3.0, 6.0, seed=9, target_vf=0.35).g
+        eb = solver.macro_tensor([1e-3, -4e-4, 3e-4], 2)
+    else:
+        g = synth.rsa_spheres(12, 12, 12, 2.0, 3.0, seed=9, target_vf=0.2).g
+        eb = solver.macro_tensor([1e-3, 0, -2e-4, 1e-4, 0, 3e-4], 3)
+    N = g.size
+    full = solver.solve(g, PH, eb, tol=1e-13, max_iter=3000)
+    for M in (max(1, N // 50), N // 10):
+        red = solver.solve(g, PH, eb, mask=pattern.build_pattern(g, M).mask(), tol=1e-13, max_iter=3000)
+        c = solver.compatibility_step(g, PH, eb, red.eps)
+        d_red = np.linalg.norm(red.eps - full.eps)
+        d_c = np.linalg.norm(c.eps - full.eps)
+        assert d_c < d_red
+        assert np.allclose(c.eps.reshape(N, 3, 3).mean(axis=0), eb, atol=1e-15)
+
+
+def test_compatibility_step_reference_medium_returns_macro_strain():
+    """When both phases equal the reference medium, the polarisation is zero
+    for any input field, so the step returns the macro strain everywhere
+    (the input need not even be compatible)."""
+    g = synth.disk(16, 16, 5.0)
+    same = (material.Phase(LM, MM), material.Phase(LM, MM))
+    eb = solver.macro_tensor([2e-3, 1e-3, -5e-4], 2)
+    rng = np.random.default_rng(3)
+    junk = rng.normal(size=g.shape + (3, 3))
+    junk = 0.5 * (junk + np.swapaxes(junk, -1, -2))
+    c = solver.compatibility_step(g, same, eb, junk)
+    assert np.max(np.abs(c.eps - eb)) < 1e-15
+
+
+# ---------------------------------------------------------------- error measures of Sec. 5
+def test_macro_and_micro_error_hand_computed():
+    """E_bar and E (Sec. 5) on hand-computed cases: a uniform 10 % scaling,
+    and a two-point field whose values were worked out by hand."""
+    ref = np.broadcast_to(np.diag([1.0, 2.0, 3.0]), (4, 5, 3, 3)).copy()
+    assert abs(solver.macro_error(1.1 * ref.mean(axis=(0, 1)), ref.mean(axis=(0, 1))) - 0.1) < 1e-14
+    assert abs(solver.micro_error(1.1 * ref, ref) - 0.1) < 1e-14
+    r1 = np.zeros((3, 3)); r1[0, 0] = 1.0
+    r2 = np.zeros((3, 3)); r2[0, 1] = r2[1, 0] = 1.0
+    s1 = r1.copy(); s1[2, 2] = 1.0          # |s1 - r1| = 1, |r1| = 1      -> 1
+    s2 = 0.5 * r2                             # |s2 - r2| = sqrt(2)/2, |r2| = sqrt(2) -> 0.5
+    ref2 = np.stack([r1, r2])
+    sig2 = np.stack([s1, s2])
+    assert abs(solver.micro_error(sig2, ref2) - 0.75) < 1e-15
+    # means: ref [[.5,.5,0],[.5,0,0],[0,0,0]] (norm^2 0.75), difference
+    # [[0,-.25,0],[-.25,0,0],[0,0,.5]] (norm^2 0.375): E_bar = sqrt(1/2)
+    assert abs(solver.macro_error(sig2.mean(axis=0), ref2.mean(axis=0)) - np.sqrt(0.5)) < 1e-15
+
+
+def test_micro_error_skips_vanishing_reference_points():
+    r = np.zeros((3, 3, 3))
+    r[0, 0, 0] = 2.0
+    r[1, 1, 1] = 4.0                          # point 2 has sigma_ref = 0: skipped
+    s = r.copy()
+    s[0, 0, 0] = 3.0                          # ratio 0.5
+    s[2, 2, 2] = 7.0
+    assert abs(solver.micro_error(s, r) - 0.25) < 1e-15
