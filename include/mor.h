@@ -56,10 +56,30 @@ typedef struct {
 enum { MOR_GAMMA_ROTATED = 0,     /* rotated first-order finite differences (Sec. 3, default) */
        MOR_GAMMA_CONTINUOUS = 1 };/* classic continuous wave vector                            */
 
+/* Kind of sampling pattern:
+ *   MOR_PATTERN_ADAPTED  the geometrically adapted pattern (Sec. 4.2): the M
+ *                        frequencies of highest |FFT(g)| (default)
+ *   MOR_PATTERN_RADIAL   the fixed radial pattern it is compared with (Sec. 4.1,
+ *                        fig. FixedSampling), 2D only: `radial_lines` straight
+ *                        lines through xi = 0 at angles l pi / L (l = 0..L-1)
+ *                        from the axis-1 direction towards axis 0.  A line with
+ *                        angle in [0, pi/4] or [3 pi/4, pi) (4l <= L or 4l >= 3L)
+ *                        takes s1 = -(n1/2-1)..n1/2-1 and s0 = round(s1 tan angle);
+ *                        the others take s0 = -(n0/2-1)..n0/2-1 and
+ *                        s1 = round(s0 tan(pi/2 - angle)); round = nearest,
+ *                        halves away from zero; points with |s_a| > n_a/2 - 1 are
+ *                        dropped.  The pattern does not depend on g and its size
+ *                        follows from L (the M argument is ignored, but must
+ *                        still lie in [1, N]); its rank order is the adapted
+ *                        ranking with equal keys (|s|^2, then lexicographic). */
+enum { MOR_PATTERN_ADAPTED = 0, MOR_PATTERN_RADIAL = 1 };
+
 typedef struct {
-  int32_t gamma_kind; /* MOR_GAMMA_* */
+  int32_t gamma_kind;   /* MOR_GAMMA_* */
+  int32_t pattern_kind; /* MOR_PATTERN_* */
+  void* stream;         /* hipStream_t for the plan kernels, NULL = null stream */
+  int32_t radial_lines; /* MOR_PATTERN_RADIAL: number of lines, 1 <= L <= 4096 */
   int32_t pad_;
-  void* stream;       /* hipStream_t for the plan kernels, NULL = null stream */
 } mor_plan_opts;
 
 typedef struct {
@@ -73,6 +93,8 @@ typedef struct {
   int64_t inclusion_count; /* voxels with g = 1                                 */
   int32_t ncomp;           /* strain components: 3 (2D) or 6 (3D)               */
   int32_t nstress;         /* stress components: 4 (2D) or 6 (3D)               */
+  int32_t pattern_kind;    /* MOR_PATTERN_*                                     */
+  int32_t radial_lines;    /* lines of a radial pattern, else 0                 */
 } mor_plan_info;
 
 /*

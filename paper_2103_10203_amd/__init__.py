@@ -6,6 +6,7 @@ script (``build.py``) and the thin ctypes binding (``_native``).
 """
 from ._native import (  # noqa: F401
     Phase, Plan, SolveResult, MorError, make_plans, solve, solve_multi, solve_path,
+    PATTERN_ADAPTED, PATTERN_RADIAL,
     profile_enable, profile_reset, profile_query, version, lib,
     GAMMA_ROTATED, GAMMA_CONTINUOUS, PREC_FP32, PREC_BF16X3, PREC_FP64,
     TRANSFORM_AUTO, TRANSFORM_FFT, TRANSFORM_DFT,

@@ -45,14 +45,20 @@ class mor_grid(ct.Structure):
     _fields_ = [("ndim", ct.c_int32), ("pad_", ct.c_int32), ("n", ct.c_int64 * 3)]
 
 
+PATTERN_ADAPTED = 0
+PATTERN_RADIAL = 1
+
+
 class mor_plan_opts(ct.Structure):
-    _fields_ = [("gamma_kind", ct.c_int32), ("pad_", ct.c_int32), ("stream", ct.c_void_p)]
+    _fields_ = [("gamma_kind", ct.c_int32), ("pattern_kind", ct.c_int32), ("stream", ct.c_void_p),
+                ("radial_lines", ct.c_int32), ("pad_", ct.c_int32)]
 
 
 class mor_plan_info(ct.Structure):
     _fields_ = [("N", ct.c_int64), ("M", ct.c_int64), ("M_actual", ct.c_int64), ("n_coeff", ct.c_int64),
                 ("n_columns", ct.c_int64), ("n_last", ct.c_int64), ("inclusion_count", ct.c_int64),
-                ("ncomp", ct.c_int32), ("nstress", ct.c_int32)]
+                ("ncomp", ct.c_int32), ("nstress", ct.c_int32), ("pattern_kind", ct.c_int32),
+                ("radial_lines", ct.c_int32)]
 
 
 class mor_phase(ct.Structure):
@@ -190,15 +196,18 @@ def _grid_of(shape):
 
 
 class Plan:
-    """Adapted sampling pattern of one microstructure (mor_plan_create)."""
+    """Sampling pattern of one microstructure (mor_plan_create): the adapted
+    pattern of M frequencies, or with radial_lines=L the fixed radial pattern
+    of L lines (M is then ignored)."""
 
-    def __init__(self, g: np.ndarray, M: int, gamma_kind: int = GAMMA_ROTATED, stream=None, _handle=None):
+    def __init__(self, g: np.ndarray, M: int = 1, gamma_kind: int = GAMMA_ROTATED, stream=None,
+                 radial_lines: int = 0, _handle=None):
         if _handle is not None:  # a plan from mor_plan_create_batch (make_plans)
             self._adopt(_handle, tuple(g))
             return
         g = np.ascontiguousarray(g, dtype=np.uint8)
         grid = _grid_of(g.shape)
-        opts = mor_plan_opts(gamma_kind, 0, _stream_ptr(stream))
+        opts = _plan_opts(gamma_kind, stream, radial_lines)
         h = ct.c_void_p()
         _check(lib.mor_plan_create(ct.byref(grid), _np_ptr(g), int(M), ct.byref(opts), ct.byref(h)))
         self._adopt(h, g.shape)
@@ -264,7 +273,12 @@ class Plan:
             pass
 
 
-def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, stream=None):
+def _plan_opts(gamma_kind, stream, radial_lines):
+    kind = PATTERN_RADIAL if radial_lines else PATTERN_ADAPTED
+    return mor_plan_opts(int(gamma_kind), kind, _stream_ptr(stream), int(radial_lines), 0)
+
+
+def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, stream=None, radial_lines: int = 0):
     """Plans of many microstructures: one mor_plan_create_batch call for all
     maps of the same shape, so the construction runs as a few launches over
     the whole group instead of a chain of small launches per map (the maps
@@ -278,7 +292,7 @@ def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, stream=None):
     for i, g in enumerate(grids):
         groups.setdefault(g.shape, []).append(i)
     out = [None] * len(grids)
-    opts = mor_plan_opts(gamma_kind, 0, _stream_ptr(stream))
+    opts = _plan_opts(gamma_kind, stream, radial_lines)
     for shape, idx in groups.items():
         grid = _grid_of(shape)
         ptrs = (ct.c_void_p * len(idx))(*[grids[i].ctypes.data for i in idx])

@@ -84,6 +84,8 @@ struct mor_plan {
   int n[3] = {1, 1, 1};
   int64_t N = 0, M = 0, M_actual = 0, count = 0;
   int gamma_kind = 0;
+  int pattern_kind = 0;  // MOR_PATTERN_*
+  int radial_lines = 0;  // lines of a radial pattern
   int device = 0;
   // device buffers owned by the plan
   uint8_t* d_g = nullptr;

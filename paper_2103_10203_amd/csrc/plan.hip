@@ -1,8 +1,10 @@
 // Adapted sampling pattern and plan tables (paper Sec. 4.2; reduced scheme of
-// Sec. 4), for one microstructure or a batch of them on one grid.  Every step
-// runs on the device, each as one launch over the batch:
+// Sec. 4), for one microstructure or a batch of them on one grid, and the
+// fixed radial pattern of Sec. 4.1 as the alternative.  Every step runs on
+// the device, each as one launch over the batch:
 //   1. FP64 FFT of the phase indicator g (Stockham along each axis),
-//   2. per-frequency ranking keys and pair representatives,
+//   2. per-frequency ranking keys and pair representatives (radial pattern:
+//      key 1 on the rasterised lines, 0 elsewhere),
 //   3. bitonic sort of the conjugate pairs by (key desc, |s|^2, lexrank), and
 //      the merge of the self-conjugate frequencies into that order,
 //   4. pair-atomic selection of the first M frequencies,
@@ -221,9 +223,41 @@ __global__ void k_fft_axis_f64(cpx<double>* __restrict__ S, int outer, int na, i
 // blockIdx.y = plan: its spectrum at S + b N, its elements at out + b stride.
 constexpr int kSide = 8;
 
+// Fixed radial pattern (Sec. 4.1): L lines through xi = 0 at angles l pi / L
+// from the axis-1 direction.  One thread per (line = blockIdx.y, step u along
+// the line's major axis); the point on the minor axis is the nearest integer
+// (halves away from zero) to u tan(angle).  Marks the frequencies in `mask`
+// (one map for the batch: the pattern does not depend on g).  Rounding ties
+// do not occur (tan(l pi / L) is irrational unless it is 0 or +-1).
+__global__ void k_radial_mark(int n0, int n1, int L, uint8_t* __restrict__ mask) {
+  const int l = blockIdx.y;
+  const int h0 = n0 / 2 - 1, h1 = n1 / 2 - 1;
+  const bool shallow = 4 * l <= L || 4 * l >= 3 * L;  // advances along axis 1
+  const int hmaj = shallow ? h1 : h0, hmin = shallow ? h0 : h1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > 2 * hmaj) return;
+  const int u = t - hmaj;
+  const double ang = shallow ? M_PI * (double)l / (double)L : M_PI * (double)(L - 2 * l) / (2.0 * (double)L);
+  const double x = (double)u * tan(ang);
+  const double v = copysign(floor(fabs(x) + 0.5), x);
+  if (fabs(v) > (double)hmin) return;
+  const int iv = (int)v;
+  const int s0 = shallow ? iv : u, s1 = shallow ? u : iv;
+  mask[(int64_t)((s0 + n0) % n0) * n1 + (s1 + n1) % n1] = 1;
+}
+
+// Number of marked frequencies (integer atomics: exact in any order).
+__global__ void k_mask_count(const uint8_t* __restrict__ mask, int64_t N, unsigned long long* __restrict__ count) {
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    c += mask[i];
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
 __global__ void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N, const unsigned long long* count,
-                       SortEl* __restrict__ out, int64_t stride, unsigned int* nout, SortEl* __restrict__ side,
-                       unsigned int* nside) {
+                       const uint8_t* __restrict__ radial, SortEl* __restrict__ out, int64_t stride,
+                       unsigned int* nout, SortEl* __restrict__ side, unsigned int* nside) {
   const int b = blockIdx.y;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -246,7 +280,11 @@ __global__ void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N, con
     P = v.x * v.x + v.y * v.y;
   }
   float key = 0.0f;
-  if (P0 > 0.0 && !(P <= ldexp(P0, -80))) key = (float)(P / P0);
+  if (radial) {
+    key = radial[i] ? 1.0f : 0.0f;  // every frequency of the fixed pattern ranks alike
+  } else if (P0 > 0.0 && !(P <= ldexp(P0, -80))) {
+    key = (float)(P / P0);
+  }
   const int n[3] = {d.n0, d.n1, d.n2};
   uint32_t s2 = 0;
   for (int a = 0; a < d.nd; ++a) {
@@ -842,6 +880,31 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
   const int nlen = nd == 2 ? P0.n[1] : P0.n[2];
   const unsigned nb = (unsigned)cnt;
 
+  // Radial pattern: the lines do not depend on g, so one map serves the
+  // batch; its size fixes M (whole conjugate pairs by construction).
+  DevBuf<uint8_t> radial;
+  if (P0.pattern_kind == MOR_PATTERN_RADIAL) {
+    DevBuf<unsigned long long> rc;
+    MOR_HIP_TRY(radial.alloc(sc, (size_t)N));
+    MOR_HIP_TRY(rc.alloc(sc, 1));
+    MOR_HIP_TRY(hipMemsetAsync(radial.p, 0, (size_t)N, st));
+    MOR_HIP_TRY(hipMemsetAsync(rc.p, 0, sizeof(unsigned long long), st));
+    const int hmax = std::max(P0.n[0], P0.n[1]) / 2 - 1;
+    k_radial_mark<<<dim3((unsigned)((2 * hmax + 1 + 255) / 256), (unsigned)P0.radial_lines), 256, 0, st>>>(
+        P0.n[0], P0.n[1], P0.radial_lines, radial.p);
+    MOR_LAUNCH_CHECK("radial_mark");
+    k_mask_count<<<(unsigned)std::min<int64_t>(1024, (N + 255) / 256), 256, 0, st>>>(radial.p, N, rc.p);
+    MOR_LAUNCH_CHECK("mask_count");
+    unsigned long long hc = 0;
+    MOR_HIP_TRY(hipMemcpyAsync(&hc, rc.p, sizeof(hc), hipMemcpyDeviceToHost, st));
+    MOR_HIP_TRY(hipStreamSynchronize(st));
+    if (hc < 1 || (int64_t)hc > N) {
+      mor_set_error("mor_plan: radial pattern size outside [1, N]");
+      return MOR_E_DEVICE;
+    }
+    for (int b = 0; b < cnt; ++b) P[b]->M = (int64_t)hc;
+  }
+
   std::vector<PlanPtrs> hp(cnt);
   DevBuf<PlanPtrs> pp;
   DevBuf<uint8_t> G;
@@ -965,8 +1028,8 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
   MOR_HIP_TRY(ranked.alloc(sc, (size_t)cnt * nreps));
   MOR_HIP_TRY(nout.alloc(sc, 2 * (size_t)cnt));
   MOR_HIP_TRY(hipMemsetAsync(nout.p, 0, 2 * cnt * sizeof(unsigned int), st));
-  k_keys<<<dim3((unsigned)((N + 255) / 256), nb), 256, 0, st>>>(S.p, d, N, count.p, el.p, npow2, nout.p, side.p,
-                                                                nout.p + cnt);
+  k_keys<<<dim3((unsigned)((N + 255) / 256), nb), 256, 0, st>>>(S.p, d, N, count.p, radial.p, el.p, npow2, nout.p,
+                                                                side.p, nout.p + cnt);
   MOR_LAUNCH_CHECK("keys");
   if (npow2 > nmain) {
     k_fill_sentinel<<<dim3((unsigned)((npow2 - nmain + 255) / 256), nb), 256, 0, st>>>(el.p, nmain, npow2, npow2);
@@ -1190,6 +1253,22 @@ static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t c
     mor_set_error(std::string(who) + ": unknown gamma_kind");
     return MOR_E_INVALID_ARG;
   }
+  const int pk = opts ? opts->pattern_kind : MOR_PATTERN_ADAPTED;
+  const int lines = opts ? opts->radial_lines : 0;
+  if (pk != MOR_PATTERN_ADAPTED && pk != MOR_PATTERN_RADIAL) {
+    mor_set_error(std::string(who) + ": unknown pattern_kind");
+    return MOR_E_INVALID_ARG;
+  }
+  if (pk == MOR_PATTERN_RADIAL) {
+    if (grid->ndim != 2) {
+      mor_set_error(std::string(who) + ": the radial pattern is defined for 2D grids");
+      return MOR_E_UNSUPPORTED;
+    }
+    if (lines < 1 || lines > 4096) {
+      mor_set_error(std::string(who) + ": radial_lines must lie in [1, 4096]");
+      return MOR_E_INVALID_ARG;
+    }
+  }
   for (int64_t b = 0; b < count; ++b) {
     const uint8_t* g = maps[b];
     if (!g) {
@@ -1225,6 +1304,8 @@ static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t c
     Q->N = N;
     Q->M = Ms[b];
     Q->gamma_kind = gk;
+    Q->pattern_kind = pk;
+    Q->radial_lines = pk == MOR_PATTERN_RADIAL ? lines : 0;
     Q->device = dev;
     P[b] = Q;
   }
@@ -1281,6 +1362,8 @@ extern "C" mor_status mor_plan_get_info(mor_plan_t plan, mor_plan_info* info) {
   info->inclusion_count = plan->count;
   info->ncomp = plan->ndim == 2 ? 3 : 6;
   info->nstress = plan->ndim == 2 ? 4 : 6;
+  info->pattern_kind = plan->pattern_kind;
+  info->radial_lines = plan->radial_lines;
   return MOR_OK;
 }
 
