@@ -26,6 +26,7 @@
 #ifndef MOR_H
 #define MOR_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -240,6 +241,31 @@ typedef struct {
 mor_status mor_solve(mor_plan_t plan, const double* macro_strain, int64_t B,
                      const mor_phase phase[2], double tol, const mor_solve_opts* opts,
                      mor_outputs* out);
+
+/*
+ * mor_solve_noalloc - mor_solve without any device or pinned-memory
+ * allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * Arguments, results and kernels are those of mor_solve.  Every workspace
+ * buffer of the solve (coefficients, transform lines, residual and stress
+ * partials, per-RVE states, the J2 state of Hooke/J2 solves) is carved from
+ * one library-owned device array of MOR_NOALLOC_SCRATCH_BYTES per GPU,
+ * which the GPU holds from the library's load until the process ends.
+ *   - A solve that needs more than the array returns MOR_E_INVALID_ARG
+ *     before any kernel runs (call again with fewer RVEs).
+ *   - opts->use_graph must be 0 (MOR_E_UNSUPPORTED otherwise); per-kernel
+ *     profiling events are not recorded.
+ *   - Every call on one GPU shares that GPU's array and overwrites it:
+ *     calls that overlap on one GPU (other streams or threads) race and give
+ *     undefined results.  Serialise them.
+ *   - Host results (eff_stress, iterations, residual) synchronise the stream
+ *     as in mor_solve.
+ */
+#define MOR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mor_status mor_solve_noalloc(mor_plan_t plan, const double* macro_strain, int64_t B,
+                             const mor_phase phase[2], double tol, const mor_solve_opts* opts,
+                             mor_outputs* out);
 
 /*
  * mor_solve_multi - as mor_solve for B RVEs that may use different plans

@@ -90,6 +90,8 @@ _SIGS = {
     "mor_plan_destroy": (ct.c_int, [ct.c_void_p]),
     "mor_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.POINTER(mor_phase), ct.c_double,
                              ct.POINTER(mor_solve_opts), ct.POINTER(mor_outputs)]),
+    "mor_solve_noalloc": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.POINTER(mor_phase), ct.c_double,
+                                     ct.POINTER(mor_solve_opts), ct.POINTER(mor_outputs)]),
     "mor_solve_multi": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64,
                                    ct.POINTER(mor_phase), ct.c_double, ct.POINTER(mor_solve_opts),
                                    ct.POINTER(mor_outputs)]),
@@ -368,8 +370,10 @@ def _outputs(B, S, eff_rows, want_fields, want_coeffs, nfield_pts, C, ncoef_tota
 def solve(plan: Plan, macro_strain, phases, tol: float, max_iter: int = 0, warm_start=None, stream=None,
           want_fields: bool = False, want_coeffs: bool = False, check_every: int = 0,
           precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO, use_graph: int = 0,
-          schedule: int = SCHED_GRID, allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
-    """mor_solve for B macro strains on one plan; macro_strain [B][ncomp]."""
+          schedule: int = SCHED_GRID, allow=(MOR_E_NOT_CONVERGED,), noalloc: bool = False) -> SolveResult:
+    """mor_solve for B macro strains on one plan; macro_strain [B][ncomp].
+    noalloc=True calls mor_solve_noalloc (workspace from the library's fixed
+    device scratch array instead of allocations)."""
     eb = np.ascontiguousarray(np.atleast_2d(macro_strain), dtype=np.float64)
     B, C = eb.shape
     if C != plan.ncomp:
@@ -379,8 +383,9 @@ def solve(plan: Plan, macro_strain, phases, tol: float, max_iter: int = 0, warm_
     out, eff, its, res, strain, stress, coeffs = _outputs(B, S, B, want_fields, want_coeffs, B * plan.N, C,
                                                           B * C * plan.n_coeff)
     opts = _opts(max_iter, check_every, warm_start, stream, precision, transform, use_graph, schedule)
-    st = _check(lib.mor_solve(plan.handle, _np_ptr(eb), B, _phases(phases), float(tol), ct.byref(opts),
-                              ct.byref(out)), allow)
+    fn = lib.mor_solve_noalloc if noalloc else lib.mor_solve
+    st = _check(fn(plan.handle, _np_ptr(eb), B, _phases(phases), float(tol), ct.byref(opts), ct.byref(out)),
+                allow)
     if strain is not None:
         strain = strain.view(B, C, *plan.shape)
         stress = stress.view(B, S, *plan.shape)

@@ -289,10 +289,38 @@ struct SolveCtx {
   int* d_nact = nullptr;   // [groups] active count per group
   bool fp64 = false;       // FP64 fields and coefficients (generic kernels, Hooke phases)
   MatDev64 mat64{};
+  // mor_solve_noalloc: every buffer is carved from the library's fixed
+  // device scratch array (no workspace, no events, no pinned memory)
+  bool noalloc = false;
+  unsigned char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  unsigned int h_active_local = 0;
   cpx<double>* yl64() const { return reinterpret_cast<cpx<double>*>(d_yl); }
   cpx<double>* yc64() const { return reinterpret_cast<cpx<double>*>(d_yc); }
   cpx<double>* coef64() const { return reinterpret_cast<cpx<double>*>(d_coef); }
 };
+
+// A solve buffer: from the per-stream workspace, or carved from the fixed
+// scratch array of a no-allocation solve (256-byte aligned pieces).
+template <typename T>
+mor_status cx_get(SolveCtx& cx, const char* name, size_t count, T** out) {
+  if (!cx.noalloc) return cx.ws->get(name, count, out);
+  const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+  if (bytes > cx.arena_cap - cx.arena_used) {
+    mor_set_error(std::string("mor_solve_noalloc: the solve needs more than the ") +
+                  std::to_string(cx.arena_cap >> 20) + " MiB scratch array (buffer " + name +
+                  "); use fewer RVEs per call");
+    return MOR_E_INVALID_ARG;
+  }
+  *out = reinterpret_cast<T*>(cx.arena + cx.arena_used);
+  cx.arena_used += bytes;
+  return MOR_OK;
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
 
 // Asynchronous upload from a host copy kept alive until the solve ends.
 template <typename T>
@@ -371,13 +399,13 @@ MatDev64 make_mat64(const mor_phase* ph) {
 }
 
 void ev_begin(SolveCtx& cx, int kind, hipEvent_t* a) {
-  if (!g_prof_on || cx.capturing) return;
+  if (!g_prof_on || cx.capturing || cx.noalloc) return;
   *a = cx.ws->event();
   (void)hipEventRecord(*a, cx.st);
   (void)kind;
 }
 void ev_end(SolveCtx& cx, int kind, hipEvent_t a) {
-  if (!g_prof_on || cx.capturing) return;
+  if (!g_prof_on || cx.capturing || cx.noalloc) return;
   hipEvent_t b = cx.ws->event();
   (void)hipEventRecord(b, cx.st);
   cx.events.push_back({a, b, kind});
@@ -809,7 +837,7 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
                  const double* ebar, int64_t B, const mor_phase* phase, double tol, const mor_solve_opts* opts,
                  float* jstate_user) {
   cx.st = opts ? (hipStream_t)opts->stream : nullptr;
-  cx.ws = workspace_for(cx.st);
+  cx.ws = cx.noalloc ? nullptr : workspace_for(cx.st);
   cx.B = B;
   cx.ndim = plans[0]->ndim;
   cx.C = cx.ndim == 2 ? 3 : 6;
@@ -834,14 +862,13 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     }
   }
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10000;
-  Workspace& ws = *cx.ws;
   mor_status s;
   // plan table
   std::vector<PlanDev> pd(plans.size());
   for (size_t i = 0; i < plans.size(); ++i) pd[i] = plans[i]->dev;
   cx.plan_dev.resize(B);
   for (int64_t b = 0; b < B; ++b) cx.plan_dev[b] = plans[plan_of[b]]->dev;
-  if ((s = ws.get("plans", pd.size(), &cx.d_plans)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "plans", pd.size(), &cx.d_plans)) != MOR_OK) return s;
   if ((s = upload(cx, cx.d_plans, pd)) != MOR_OK) return s;
   // groups by grid
   std::map<std::vector<int>, int> gidx;
@@ -937,7 +964,7 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     nblk[b] = nrb;
   }
   int64_t* d_offs;
-  if ((s = ws.get("offs", offs.size(), &d_offs)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "offs", offs.size(), &d_offs)) != MOR_OK) return s;
   if ((s = upload(cx, d_offs, offs)) != MOR_OK) return s;
   cx.off.yl = d_offs;
   cx.off.yc = d_offs + B;
@@ -946,20 +973,20 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   cx.off.part = d_offs + 4 * B;
   // counts in FP32 complex elements; FP64 complex takes two
   const size_t ew = cx.fp64 ? 2 : 1;
-  if ((s = ws.get("yl", (size_t)yl * ew, &cx.d_yl)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "yl", (size_t)yl * ew, &cx.d_yl)) != MOR_OK) return s;
   if (cx.ndim == 3) {
-    if ((s = ws.get("yc", (size_t)yc * ew, &cx.d_yc)) != MOR_OK) return s;
+    if ((s = cx_get(cx, "yc", (size_t)yc * ew, &cx.d_yc)) != MOR_OK) return s;
   } else {
     cx.d_yc = cx.d_yl;
   }
-  if ((s = ws.get("coef", (size_t)co * ew, &cx.d_coef)) != MOR_OK) return s;
-  if (cx.dft && (s = ws.get("dfte", (size_t)fo * cx.C, &cx.d_dfte)) != MOR_OK) return s;
-  if ((s = ws.get("part", (size_t)pa, &cx.d_part)) != MOR_OK) return s;
-  if ((s = ws.get("sigpart", (size_t)pa * cx.S, &cx.d_sigpart)) != MOR_OK) return s;
-  if ((s = ws.get("eff", (size_t)B * cx.S, &cx.d_eff)) != MOR_OK) return s;
-  if ((s = ws.get("active", 1, &cx.d_active)) != MOR_OK) return s;
-  if ((s = ws.get("ebar", (size_t)B * cx.C, &cx.d_ebar)) != MOR_OK) return s;
-  if ((s = ws.get("state", (size_t)B, &cx.d_st)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "coef", (size_t)co * ew, &cx.d_coef)) != MOR_OK) return s;
+  if (cx.dft && (s = cx_get(cx, "dfte", (size_t)fo * cx.C, &cx.d_dfte)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "part", (size_t)pa, &cx.d_part)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "sigpart", (size_t)pa * cx.S, &cx.d_sigpart)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "eff", (size_t)B * cx.S, &cx.d_eff)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "active", 1, &cx.d_active)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "ebar", (size_t)B * cx.C, &cx.d_ebar)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "state", (size_t)B, &cx.d_st)) != MOR_OK) return s;
   // group lists and final block counts (per group position)
   std::vector<int> lists, nblk_list;
   std::vector<size_t> lstart;
@@ -971,14 +998,14 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     }
   }
   int* d_lists;
-  if ((s = ws.get("lists", lists.size(), &d_lists)) != MOR_OK) return s;
-  if ((s = ws.get("nblk", nblk_list.size(), &cx.d_nblk)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "lists", lists.size(), &d_lists)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "nblk", nblk_list.size(), &cx.d_nblk)) != MOR_OK) return s;
   if ((s = upload(cx, d_lists, lists)) != MOR_OK) return s;
   if ((s = upload(cx, cx.d_nblk, nblk_list)) != MOR_OK) return s;
   for (size_t gi = 0; gi < cx.groups.size(); ++gi) cx.groups[gi].d_list = d_lists + lstart[gi];
   if (cx.persist) {
-    if ((s = ws.get("alist", lists.size(), &cx.d_alist)) != MOR_OK) return s;
-    if ((s = ws.get("nact", cx.groups.size(), &cx.d_nact)) != MOR_OK) return s;
+    if ((s = cx_get(cx, "alist", lists.size(), &cx.d_alist)) != MOR_OK) return s;
+    if ((s = cx_get(cx, "nact", cx.groups.size(), &cx.d_nact)) != MOR_OK) return s;
     for (size_t gi = 0; gi < cx.groups.size(); ++gi) {
       cx.groups[gi].gidx = (int)gi;
       cx.groups[gi].d_alist = cx.d_alist + lstart[gi];
@@ -1015,8 +1042,15 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     if (jstate_user) {
       cx.d_jstate = jstate_user;
     } else {
-      if ((s = ws.get("jstate", (size_t)fo * cx.NST, &cx.d_jstate)) != MOR_OK) return s;
-      MOR_HIP_TRY(hipMemsetAsync(cx.d_jstate, 0, (size_t)fo * cx.NST * sizeof(float), cx.st));
+      if ((s = cx_get(cx, "jstate", (size_t)fo * cx.NST, &cx.d_jstate)) != MOR_OK) return s;
+      if (cx.noalloc) {
+        // the scratch array keeps the previous call's contents: a fill kernel
+        // (no memset node for callers that capture the solve into a graph)
+        k_zero_f32<<<1024, 256, 0, cx.st>>>(cx.d_jstate, (int64_t)fo * cx.NST);
+        MOR_LAUNCH_CHECK("zero J2 state");
+      } else {
+        MOR_HIP_TRY(hipMemsetAsync(cx.d_jstate, 0, (size_t)fo * cx.NST * sizeof(float), cx.st));
+      }
     }
   }
   return MOR_OK;
@@ -1088,9 +1122,10 @@ mor_status run(SolveCtx& cx, const cpx<float>* warm, const mor_solve_opts* opts,
           if ((s = do_iter(cx, g)) != MOR_OK) return s;
     }
     done += check;
-    MOR_HIP_TRY(hipMemcpyAsync(cx.ws->h_active, cx.d_active, sizeof(unsigned int), hipMemcpyDeviceToHost, cx.st));
+    unsigned int* hact = cx.noalloc ? &cx.h_active_local : cx.ws->h_active;
+    MOR_HIP_TRY(hipMemcpyAsync(hact, cx.d_active, sizeof(unsigned int), hipMemcpyDeviceToHost, cx.st));
     MOR_HIP_TRY(hipStreamSynchronize(cx.st));
-    if (*cx.ws->h_active == 0u) break;
+    if (*hact == 0u) break;
     if (done > max_iter + check) {
       mor_set_error("iteration loop did not drain");
       return MOR_E_DEVICE;
@@ -1183,7 +1218,7 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
     }
   }
   cx.events.clear();
-  cx.ws->evnext = 0;
+  if (cx.ws) cx.ws->evnext = 0;
   mor_status worst = MOR_OK;
   for (int64_t b = 0; b < cx.B; ++b) {
     if (out && out->iterations) out->iterations[b] = hs[b].iters;
@@ -1257,9 +1292,15 @@ std::mutex& stream_mutex(void* stream) {
 
 mor_status solve_impl(const std::vector<mor_plan*>& plans, const std::vector<int>& plan_of, const double* ebar,
                       int64_t B, const mor_phase* phase, double tol, const mor_solve_opts* opts, mor_outputs* out,
-                      float* jstate, int eff_stride, std::vector<RveState>* st_out) {
+                      float* jstate, int eff_stride, std::vector<RveState>* st_out,
+                      unsigned char* arena = nullptr, size_t arena_cap = 0) {
   std::lock_guard<std::mutex> lk(stream_mutex(opts ? opts->stream : nullptr));
   SolveCtx cx;
+  if (arena) {
+    cx.noalloc = true;
+    cx.arena = arena;
+    cx.arena_cap = arena_cap;
+  }
   mor_status s = setup(cx, plans, plan_of, ebar, B, phase, tol, opts, jstate);
   if (s != MOR_OK) {
     (void)hipStreamSynchronize(cx.st);
@@ -1291,6 +1332,60 @@ extern "C" mor_status mor_solve(mor_plan_t plan, const double* macro_strain, int
   std::vector<int> plan_of(B, 0);
   return solve_impl(plans, plan_of, macro_strain, B, phase, tol, opts, out, nullptr, plan->ndim == 2 ? 4 : 6,
                     nullptr);
+}
+
+// ------------------------------------------------------------------ no-allocation solve
+// The device scratch array of mor_solve_noalloc.  In host code its name is
+// only a stand-in for the symbol: the device address is looked up once per
+// device with hipGetSymbolAddress (each GPU holds its own copy) and only
+// that address is passed to kernels and copies.
+static __device__ __align__(256) unsigned char scratch[MOR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_ptr;  // device -> address of its scratch array
+
+mor_status scratch_address(unsigned char** out) {
+  int dev = 0;
+  MOR_HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return MOR_OK;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    mor_set_error(std::string("mor_solve_noalloc: hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    return MOR_E_DEVICE;
+  }
+  g_scratch_ptr[dev] = (unsigned char*)ptr;
+  *out = (unsigned char*)ptr;
+  return MOR_OK;
+}
+}  // namespace
+
+extern "C" mor_status mor_solve_noalloc(mor_plan_t plan, const double* macro_strain, int64_t B,
+                                        const mor_phase phase[2], double tol, const mor_solve_opts* opts,
+                                        mor_outputs* out) {
+  if (!plan) {
+    mor_set_error("mor_solve_noalloc: NULL plan");
+    return MOR_E_INVALID_ARG;
+  }
+  const int C = plan->ndim == 2 ? 3 : 6;
+  mor_status s = check_common(macro_strain, B, C, phase, tol, opts, plan->ndim);
+  if (s != MOR_OK) return s;
+  if (opts && opts->use_graph) {
+    mor_set_error("mor_solve_noalloc: use_graph records a graph per call; capture the call instead");
+    return MOR_E_UNSUPPORTED;
+  }
+  unsigned char* base = nullptr;
+  if ((s = scratch_address(&base)) != MOR_OK) return s;
+  std::vector<mor_plan*> plans = {plan};
+  std::vector<int> plan_of(B, 0);
+  return solve_impl(plans, plan_of, macro_strain, B, phase, tol, opts, out, nullptr, plan->ndim == 2 ? 4 : 6,
+                    nullptr, base, MOR_NOALLOC_SCRATCH_BYTES);
 }
 
 extern "C" mor_status mor_solve_multi(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of_rve,
