@@ -293,11 +293,90 @@ mor_status mor_solve_multi(const mor_plan_t* plans, int64_t nplans, const int64_
  *                and 7 in 3D (eps_p 11, 22, 33, 23, 13, 12, accumulated).
  *                Zero it for a virgin material.
  *   out          eff_stress host [steps][nstress], iterations/residual host
- *                [steps]; field outputs hold the last step.
+ *                [steps]; field and coefficient outputs hold the last step.
  */
 mor_status mor_solve_path(mor_plan_t plan, const double* macro_strain, int32_t steps,
                           const mor_phase phase[2], double tol, const mor_solve_opts* opts,
                           float* state, mor_outputs* out);
+
+/*
+ * mor_solve_path_multi - load paths of B RVEs in one call (Secs. 2 and 5.2),
+ * e.g. the integration points of an FE-FFT computation, each with its own
+ * macro strain history and committed J2 state; RVE b uses
+ * plans[plan_of_rve[b]] (host arrays; the plans may differ in grid).  Every
+ * iteration runs one set of launches over all RVEs still iterating, so the
+ * device is filled even when one RVE alone would not fill it.  Step rules as
+ * in mor_solve_path, per RVE.  Per-step results stay on the device until the
+ * call ends (no host synchronisation between steps beyond the convergence
+ * polls).
+ *
+ *   macro_strain host double [B][steps][ncomp].
+ *   state        device float, RVE b's [nstate][N_b] block at element offset
+ *                nstate * (sum of N of RVEs before b); in/out; zero for a
+ *                virgin material.
+ *   out          eff_stress host [B][steps][6] (2D uses the first 4),
+ *                iterations/residual host [B][steps]; strain/stress/coeffs
+ *                packed as in mor_solve_multi, for the last step.
+ */
+mor_status mor_solve_path_multi(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of_rve,
+                                const double* macro_strain, int64_t B, int32_t steps, const mor_phase phase[2],
+                                double tol, const mor_solve_opts* opts, float* state, mor_outputs* out);
+
+/*
+ * mor_compat - compatibility step (Sec. 4.1 post-processing; applied alone to
+ * the adapted-pattern results in Sec. 5.1): the Lippmann-Schwinger equation
+ * solved once on the full set of frequencies from the fields of a reduced
+ * solution.  One pass of steps a)-d) with every frequency kept, from eps_red:
+ *   tau = sigma(eps_red) - C0 : eps_red,  eps^(xi) = -Gamma0^(xi) : tau^(xi)
+ *   (xi != 0), eps^(0) = N eps_bar,  eps_comp = iFFT(eps^),
+ * then sigma(eps_comp) and its FP64 grid mean.  Runs on the solver's kernels
+ * with plan_full's tables (the reduced coefficients are placed at their
+ * frequencies of the full set as the starting field).
+ *
+ *   plan       the plan the reduced solution was computed on.
+ *   plan_full  a plan of the same grid and microstructure holding every
+ *              frequency (mor_plan_create with M = N); MOR_E_INVALID_ARG if
+ *              its grid, inclusion count or size do not fit.
+ *   coeffs     device complex64 [B][ncomp][n_coeff of plan]: the reduced
+ *              strain coefficients (mor_solve's coeffs output).
+ *   macro_strain host double [B][ncomp]; phase as for the solve.
+ *   state      J2 phases: device float [B][nstate][N], the committed state
+ *              the reduced solution was computed with (read only; NULL =
+ *              virgin material).  Ignored for Hooke phases.
+ *   opts       precision/transform/stream as for mor_solve (max_iter,
+ *              warm_start and use_graph are set by the call).
+ *   out        as mor_solve on plan_full: eff_stress = grid mean of
+ *              sigma(eps_comp); strain/stress = eps_comp, sigma(eps_comp);
+ *              iterations = 1; residual = RMS ||eps_comp - eps_red||_F /
+ *              ||eps_bar||_F; coeffs in plan_full's layout.
+ */
+mor_status mor_compat(mor_plan_t plan, mor_plan_t plan_full, const float* coeffs, const double* macro_strain,
+                      int64_t B, const mor_phase phase[2], const float* state, const mor_solve_opts* opts,
+                      mor_outputs* out);
+
+/*
+ * mor_stress_error - the error measures of Sec. 5 of a reduced solution
+ * against a reference solution (the full set of frequencies):
+ *   E_bar[b] = ||sigma_bar - sigma_bar_ref|| / ||sigma_bar_ref||
+ *   E[b]     = mean over the kept grid points x of
+ *              ||sigma(x) - sigma_ref(x)|| / ||sigma_ref(x)||
+ * Norms are Frobenius norms of the full symmetric tensor (shear components
+ * counted twice; sigma_33 included in 2D).  The pointwise quotient needs
+ * ||sigma_ref(x)|| > 0: points with ||sigma_ref(x)|| <= skip_rel * max_x
+ * ||sigma_ref|| are left out of the mean (E = 0 if none is kept).  FP64
+ * arithmetic; fixed summation order.
+ *
+ *   sigma, sigma_ref  device float [B][nstress][N] (mor_solve's stress output
+ *                     layout), needed when E != NULL.
+ *   eff, eff_ref      host double [B][nstress], needed when E_bar != NULL.
+ *   ndim              2 (nstress 4) or 3 (nstress 6).
+ *   E_bar, E          host double [B] or NULL (that measure is skipped).
+ * Synchronises `stream` when E is requested.  Device scratch (a few KB per
+ * RVE) is kept per device and grown on demand.
+ */
+mor_status mor_stress_error(const float* sigma, const float* sigma_ref, const double* eff, const double* eff_ref,
+                            int64_t B, int64_t N, int32_t ndim, double skip_rel, void* stream, double* E_bar,
+                            double* E);
 
 /* ----------------------------------------------------------------------
  * Learned warm start (an addition to the paper's method).  A 3-layer

@@ -97,6 +97,13 @@ _SIGS = {
                                    ct.POINTER(mor_outputs)]),
     "mor_solve_path": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.POINTER(mor_phase), ct.c_double,
                                   ct.POINTER(mor_solve_opts), ct.c_void_p, ct.POINTER(mor_outputs)]),
+    "mor_solve_path_multi": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32,
+                                        ct.POINTER(mor_phase), ct.c_double, ct.POINTER(mor_solve_opts), ct.c_void_p,
+                                        ct.POINTER(mor_outputs)]),
+    "mor_compat": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.POINTER(mor_phase),
+                              ct.c_void_p, ct.POINTER(mor_solve_opts), ct.POINTER(mor_outputs)]),
+    "mor_stress_error": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int64,
+                                    ct.c_int32, ct.c_double, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "mor_profile_enable": (ct.c_int, [ct.c_int32]),
     "mor_profile_reset": (ct.c_int, []),
     "mor_profile_query": (ct.c_int, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64),
@@ -419,22 +426,110 @@ def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int 
 def solve_path(plan: Plan, macro_strains, phases, tol: float, state, max_iter: int = 0, stream=None,
                want_fields: bool = False, check_every: int = 0, use_graph: int = 0,
                precision: int = PREC_FP32, transform: int = TRANSFORM_AUTO, schedule: int = SCHED_GRID,
-               allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
-    """mor_solve_path: macro_strains [steps][ncomp]; state: torch float32 cuda [nstate][N] (in/out)."""
+               allow=(MOR_E_NOT_CONVERGED,), want_coeffs: bool = False) -> SolveResult:
+    """mor_solve_path: macro_strains [steps][ncomp]; state: torch float32 cuda [nstate][N] (in/out).
+    Fields and coefficients (want_coeffs) are those of the last step."""
     eb = np.ascontiguousarray(np.atleast_2d(macro_strains), dtype=np.float64)
     steps, C = eb.shape
     if C != plan.ncomp:
         raise ValueError(f"macro strains need {plan.ncomp} components")
     _check_tensor(state, "state", "float32", (5 if plan.ndim == 2 else 7) * plan.N)
     S = plan.nstress
-    out, eff, its, res, strain, stress, coeffs = _outputs(steps, S, steps, want_fields, False, plan.N, C, 0)
+    out, eff, its, res, strain, stress, coeffs = _outputs(steps, S, steps, want_fields, want_coeffs, plan.N, C,
+                                                          C * plan.n_coeff)
     opts = _opts(max_iter, check_every, None, stream, precision, transform, use_graph, schedule)
     st = _check(lib.mor_solve_path(plan.handle, _np_ptr(eb), steps, _phases(phases), float(tol), ct.byref(opts),
                                    ct.c_void_p(state.data_ptr()), ct.byref(out)), allow)
     if strain is not None:
         strain = strain.view(C, *plan.shape)
         stress = stress.view(S, *plan.shape)
-    return SolveResult(st, eff, its, res, strain, stress, None)
+    if coeffs is not None:
+        coeffs = coeffs.view(C, plan.n_coeff)
+    return SolveResult(st, eff, its, res, strain, stress, coeffs)
+
+
+def solve_path_multi(plans, plan_of, macro_strains, phases, tol: float, state, max_iter: int = 0, stream=None,
+                     want_fields: bool = False, want_coeffs: bool = False, check_every: int = 0,
+                     use_graph: int = 0, schedule: int = SCHED_GRID,
+                     allow=(MOR_E_NOT_CONVERGED,)) -> SolveResult:
+    """mor_solve_path_multi: macro_strains [B][steps][ncomp]; RVE b uses
+    plans[plan_of[b]]; state: float32 CUDA tensor holding every RVE's
+    [nstate][N] block (packed).  eff_stress comes back as [B][steps][6]."""
+    eb = np.ascontiguousarray(macro_strains, dtype=np.float64)
+    if eb.ndim != 3:
+        raise ValueError("macro_strains must be [B][steps][ncomp]")
+    B, steps, C = eb.shape
+    po = np.ascontiguousarray(plan_of, dtype=np.int64)
+    if po.shape != (B,) or po.min() < 0 or po.max() >= len(plans):
+        raise ValueError("plan_of needs one index into plans per RVE")
+    if C != plans[0].ncomp:
+        raise ValueError(f"macro strains need {plans[0].ncomp} components")
+    nst = 5 if plans[0].ndim == 2 else 7
+    npts = int(sum(plans[i].N for i in po))
+    _check_tensor(state, "state", "float32", nst * npts)
+    handles = (ct.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    ncoef = int(sum(plans[i].n_coeff for i in po)) * C
+    out, eff, its, res, strain, stress, coeffs = _outputs(B * steps, 6, B * steps, False, want_coeffs,
+                                                          npts, C, ncoef)
+    if want_fields:  # field outputs hold the last step of each RVE
+        torch = _torch()
+        strain = torch.empty(C * npts, dtype=torch.float32, device="cuda")
+        stress = torch.empty(plans[0].nstress * npts, dtype=torch.float32, device="cuda")
+        out.strain = strain.data_ptr()
+        out.stress = stress.data_ptr()
+    opts = _opts(max_iter, check_every, None, stream, PREC_FP32, TRANSFORM_AUTO, use_graph, schedule)
+    st = _check(lib.mor_solve_path_multi(handles, len(plans), _np_ptr(po), _np_ptr(eb), B, steps, _phases(phases),
+                                         float(tol), ct.byref(opts), ct.c_void_p(state.data_ptr()),
+                                         ct.byref(out)), allow)
+    return SolveResult(st, eff.reshape(B, steps, 6), its.reshape(B, steps), res.reshape(B, steps), strain, stress,
+                       coeffs)
+
+
+def compat(plan: Plan, plan_full: Plan, coeffs, macro_strain, phases, state=None, stream=None,
+           want_fields: bool = True, want_coeffs: bool = False, precision: int = PREC_FP32,
+           transform: int = TRANSFORM_AUTO) -> SolveResult:
+    """mor_compat: one full-set pass from the reduced coefficients `coeffs`
+    (complex64 [B][ncomp][plan.n_coeff]); plan_full holds every frequency of
+    the same microstructure.  Fields and coefficients come back on plan_full."""
+    eb = np.ascontiguousarray(np.atleast_2d(macro_strain), dtype=np.float64)
+    B, C = eb.shape
+    if C != plan.ncomp:
+        raise ValueError(f"macro strain needs {plan.ncomp} components")
+    _check_tensor(coeffs, "coeffs", "complex64", B * C * plan.n_coeff)
+    _check_tensor(state, "state", "float32", B * (5 if plan.ndim == 2 else 7) * plan.N)
+    S = plan.nstress
+    out, eff, its, res, strain, stress, co = _outputs(B, S, B, want_fields, want_coeffs, B * plan.N, C,
+                                                      B * C * plan_full.n_coeff)
+    opts = _opts(1, 1, None, stream, precision, transform)
+    sp = ct.c_void_p(state.data_ptr()) if state is not None else ct.c_void_p(None)
+    st = _check(lib.mor_compat(plan.handle, plan_full.handle, ct.c_void_p(coeffs.data_ptr()), _np_ptr(eb), B,
+                               _phases(phases), sp, ct.byref(opts), ct.byref(out)))
+    if strain is not None:
+        strain = strain.view(B, C, *plan.shape)
+        stress = stress.view(B, S, *plan.shape)
+    if co is not None:
+        co = co.view(B, C, plan_full.n_coeff)
+    return SolveResult(st, eff, its, res, strain, stress, co)
+
+
+def stress_error(sigma, sigma_ref, eff, eff_ref, ndim: int, skip_rel: float = 1e-12, stream=None):
+    """mor_stress_error: (E_bar [B], E [B]) of Sec. 5.  sigma/sigma_ref:
+    float32 CUDA tensors [B][nstress][...grid]; eff/eff_ref: [B][nstress]."""
+    S = 4 if ndim == 2 else 6
+    B = sigma.shape[0]
+    N = sigma.numel() // (B * S)
+    _check_tensor(sigma, "sigma", "float32", B * S * N)
+    _check_tensor(sigma_ref, "sigma_ref", "float32", B * S * N)
+    a = np.ascontiguousarray(np.asarray(eff, dtype=np.float64)[:, :S])
+    r = np.ascontiguousarray(np.asarray(eff_ref, dtype=np.float64)[:, :S])
+    if a.shape != (B, S) or r.shape != (B, S):
+        raise ValueError(f"eff and eff_ref must be [{B}][{S}]")
+    Eb = np.zeros(B)
+    E = np.zeros(B)
+    _check(lib.mor_stress_error(ct.c_void_p(sigma.data_ptr()), ct.c_void_p(sigma_ref.data_ptr()), _np_ptr(a),
+                                _np_ptr(r), B, N, ndim, float(skip_rel), _stream_ptr(stream), _np_ptr(Eb),
+                                _np_ptr(E)))
+    return Eb, E
 
 
 def profile_enable(on: bool = True):

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmor.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["plan.hip", "solve.hip", "mlp.hip"]
+SOURCES = ["plan.hip", "solve.hip", "mlp.hip", "error.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

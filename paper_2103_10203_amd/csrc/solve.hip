@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -832,6 +833,31 @@ mor_status do_final(SolveCtx& cx, Group& g, float* eps, float* sig) {
   return cx.j2 ? launch_final<6, MAT_J2>(cx, g, eps, sig) : launch_final<6, MAT_HOOKE>(cx, g, eps, sig);
 }
 
+// Per-RVE states for the start of a load step: active, no iterations, the
+// residual denominator of that step's macro strain.
+std::vector<RveState> fresh_states(const SolveCtx& cx, const std::vector<mor_plan*>& plans,
+                                   const std::vector<int>& plan_of, const double* ebar, double tol, int max_iter) {
+  std::vector<RveState> hs(cx.B);
+  for (int64_t b = 0; b < cx.B; ++b) {
+    double nrm2 = 0.0;
+    for (int c = 0; c < cx.C; ++c) {
+      const double v = ebar[b * cx.C + c];
+      nrm2 += (c < (cx.C == 3 ? 2 : 3) ? 1.0 : 2.0) * v * v;
+    }
+    RveState& r = hs[b];
+    r.active = 1;
+    r.iters = 0;
+    r.status = MOR_OK;
+    r.plan = plan_of[b];
+    r.resid = 0.0;
+    r.denom = (double)plans[plan_of[b]]->N * (nrm2 > 0.0 ? std::sqrt(nrm2) : 1.0);
+    r.tol = tol;
+    r.max_iter = max_iter;
+    r.warm_ok = 1;
+  }
+  return hs;
+}
+
 // Prepare the context: plan table, groups, offsets, states.
 mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::vector<int>& plan_of,
                  const double* ebar, int64_t B, const mor_phase* phase, double tol, const mor_solve_opts* opts,
@@ -1014,25 +1040,8 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
   // nblk is indexed by group position in k_sig_reduce: shift per group
   // (k_sig_reduce receives the group's list; its nblk pointer is offset below)
   // states
-  std::vector<RveState> hs(B);
+  std::vector<RveState> hs = fresh_states(cx, plans, plan_of, ebar, tol, max_iter);
   std::vector<double> eb(ebar, ebar + B * cx.C);
-  for (int64_t b = 0; b < B; ++b) {
-    double nrm2 = 0.0;
-    for (int c = 0; c < cx.C; ++c) {
-      const double v = ebar[b * cx.C + c];
-      nrm2 += (c < (cx.C == 3 ? 2 : 3) ? 1.0 : 2.0) * v * v;
-    }
-    RveState& r = hs[b];
-    r.active = 1;
-    r.iters = 0;
-    r.status = MOR_OK;
-    r.plan = plan_of[b];
-    r.resid = 0.0;
-    r.denom = (double)plans[plan_of[b]]->N * (nrm2 > 0.0 ? std::sqrt(nrm2) : 1.0);
-    r.tol = tol;
-    r.max_iter = max_iter;
-    r.warm_ok = 1;
-  }
   if ((s = upload(cx, cx.d_st, hs)) != MOR_OK) return s;
   if ((s = upload(cx, cx.d_ebar, eb)) != MOR_OK) return s;
   std::vector<unsigned int> act(1, (unsigned int)B);
@@ -1154,6 +1163,8 @@ __global__ void k_round_c64(const cpx<double>* __restrict__ a, cpx<float>* __res
   if (i < n) o[i] = {(float)a[i].x, (float)a[i].y};
 }
 
+void account(SolveCtx& cx, const std::vector<RveState>& hs, int passes = 1);
+
 mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<RveState>* states_out) {
   std::vector<RveState> hs(cx.B);
   MOR_HIP_TRY(hipMemcpyAsync(hs.data(), cx.d_st, cx.B * sizeof(RveState), hipMemcpyDeviceToHost, cx.st));
@@ -1173,6 +1184,26 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
     }
   }
   MOR_HIP_TRY(hipStreamSynchronize(cx.st));
+  account(cx, hs);
+  mor_status worst = MOR_OK;
+  for (int64_t b = 0; b < cx.B; ++b) {
+    if (out && out->iterations) out->iterations[b] = hs[b].iters;
+    if (out && out->residual) out->residual[b] = hs[b].resid;
+    if (out && out->eff_stress)
+      for (int s = 0; s < cx.S; ++s) out->eff_stress[b * eff_stride + s] = eff[b * cx.S + s];
+    if (hs[b].status == MOR_E_NONFINITE) worst = MOR_E_NONFINITE;
+    else if (hs[b].status == MOR_E_NOT_CONVERGED && worst == MOR_OK) worst = MOR_E_NOT_CONVERGED;
+  }
+  if (states_out) *states_out = hs;
+  if (worst == MOR_E_NONFINITE) mor_set_error("non-finite residual in at least one RVE");
+  if (worst == MOR_E_NOT_CONVERGED) mor_set_error("max_iter reached before tol in at least one RVE");
+  return worst;
+}
+
+// Per-kernel profile of the work of one solve (or one load step): event
+// times of the launches recorded so far, algorithmic bytes from the RVEs'
+// iteration counts.  Clears the recorded events.
+void account(SolveCtx& cx, const std::vector<RveState>& hs, int passes) {
   if (g_prof_on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto& e : cx.events) {
@@ -1211,27 +1242,14 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
         g_prof[PK_MIDI].items += (int64_t)it + 1;
         g_prof[PK_MIDI].bytes += (it + 1.0) * mid;
       }
-      g_prof[PK_FINAL].items += 1;
-      g_prof[PK_FINAL].bytes += fin;
-      g_prof[PK_INIT].items += 1;
-      g_prof[PK_INIT].bytes += d.ncol * 8.0 * ew * C * d.n0 + d.ncoef * (8.0 * ew + 17.0);
+      g_prof[PK_FINAL].items += passes;
+      g_prof[PK_FINAL].bytes += passes * fin;
+      g_prof[PK_INIT].items += passes;
+      g_prof[PK_INIT].bytes += passes * (d.ncol * 8.0 * ew * C * d.n0 + d.ncoef * (8.0 * ew + 17.0));
     }
   }
   cx.events.clear();
   if (cx.ws) cx.ws->evnext = 0;
-  mor_status worst = MOR_OK;
-  for (int64_t b = 0; b < cx.B; ++b) {
-    if (out && out->iterations) out->iterations[b] = hs[b].iters;
-    if (out && out->residual) out->residual[b] = hs[b].resid;
-    if (out && out->eff_stress)
-      for (int s = 0; s < cx.S; ++s) out->eff_stress[b * eff_stride + s] = eff[b * cx.S + s];
-    if (hs[b].status == MOR_E_NONFINITE) worst = MOR_E_NONFINITE;
-    else if (hs[b].status == MOR_E_NOT_CONVERGED && worst == MOR_OK) worst = MOR_E_NOT_CONVERGED;
-  }
-  if (states_out) *states_out = hs;
-  if (worst == MOR_E_NONFINITE) mor_set_error("non-finite residual in at least one RVE");
-  if (worst == MOR_E_NOT_CONVERGED) mor_set_error("max_iter reached before tol in at least one RVE");
-  return worst;
 }
 
 mor_status check_common(const double* ebar, int64_t B, int C, const mor_phase* phase, double tol,
@@ -1281,12 +1299,14 @@ mor_status check_common(const double* ebar, int64_t B, int C, const mor_phase* p
   return MOR_OK;
 }
 
-std::mutex& stream_mutex(void* stream) {
+// One solve at a time per stream (the stream's workspace is shared);
+// recursive so that a call may hold it around the solves it makes.
+std::recursive_mutex& stream_mutex(void* stream) {
   static std::mutex mu;
-  static std::map<void*, std::mutex*> m;
+  static std::map<void*, std::recursive_mutex*> m;
   std::lock_guard<std::mutex> lk(mu);
   auto it = m.find(stream);
-  if (it == m.end()) it = m.emplace(stream, new std::mutex()).first;
+  if (it == m.end()) it = m.emplace(stream, new std::recursive_mutex()).first;
   return *it->second;
 }
 
@@ -1294,7 +1314,7 @@ mor_status solve_impl(const std::vector<mor_plan*>& plans, const std::vector<int
                       int64_t B, const mor_phase* phase, double tol, const mor_solve_opts* opts, mor_outputs* out,
                       float* jstate, int eff_stride, std::vector<RveState>* st_out,
                       unsigned char* arena = nullptr, size_t arena_cap = 0) {
-  std::lock_guard<std::mutex> lk(stream_mutex(opts ? opts->stream : nullptr));
+  std::lock_guard<std::recursive_mutex> lk(stream_mutex(opts ? opts->stream : nullptr));
   SolveCtx cx;
   if (arena) {
     cx.noalloc = true;
@@ -1421,6 +1441,190 @@ extern "C" mor_status mor_solve_multi(const mor_plan_t* plans, int64_t nplans, c
   return solve_impl(pl, plan_of, macro_strain_packed, B, phase, tol, opts, out, nullptr, ndim == 2 ? 4 : 6, nullptr);
 }
 
+// ------------------------------------------------------------------ compatibility step
+// Coefficient index of every stored linear frequency of a plan (-1 where the
+// plan stores none): cleared, then marked.
+__global__ void k_fill_i32(int* __restrict__ p, int64_t n, int v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_mark_coef(const int64_t* __restrict__ coef_lin, int ncoef, int* __restrict__ table) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ncoef) table[coef_lin[e]] = e;
+}
+// Reduced coefficients [B][C][ncr] placed at the same frequencies of the
+// full set's layout [B][C][ncf] (cleared first); blockIdx.y = (b, c).
+__global__ void k_embed_coef(const cpx<float>* __restrict__ in, const int64_t* __restrict__ lin_r, int ncr,
+                             const int* __restrict__ table, int ncf, cpx<float>* __restrict__ out) {
+  const int64_t bc = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ncr) return;
+  const int f = table[lin_r[e]];
+  if (f >= 0) out[bc * ncf + f] = in[bc * ncr + e];
+}
+__global__ void k_zero_c64(cpx<float>* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = {0.f, 0.f};
+}
+
+extern "C" mor_status mor_compat(mor_plan_t plan, mor_plan_t plan_full, const float* coeffs,
+                                 const double* macro_strain, int64_t B, const mor_phase phase[2], const float* state,
+                                 const mor_solve_opts* opts, mor_outputs* out) {
+  if (!plan || !plan_full || !coeffs) {
+    mor_set_error("mor_compat: NULL plan or coefficients");
+    return MOR_E_INVALID_ARG;
+  }
+  if (plan->ndim != plan_full->ndim || plan->n[0] != plan_full->n[0] || plan->n[1] != plan_full->n[1] ||
+      plan->n[2] != plan_full->n[2] || plan->count != plan_full->count) {
+    mor_set_error("mor_compat: plan_full must be a plan of the same grid and microstructure");
+    return MOR_E_INVALID_ARG;
+  }
+  if (plan_full->M_actual != plan_full->N) {
+    mor_set_error("mor_compat: plan_full must hold every frequency (M = N)");
+    return MOR_E_INVALID_ARG;
+  }
+  const int C = plan->ndim == 2 ? 3 : 6;
+  const int NST = plan->ndim == 2 ? 5 : 7;
+  mor_status s = check_common(macro_strain, B, C, phase, 1.0, opts, plan->ndim);
+  if (s != MOR_OK) return s;
+  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  std::lock_guard<std::recursive_mutex> lk(stream_mutex(st));
+  Workspace& ws = *workspace_for(st);
+  const int64_t N = plan->N;
+  const int ncr = plan->dev.ncoef, ncf = plan_full->dev.ncoef;
+  int* table = nullptr;
+  cpx<float>* warm = nullptr;
+  if ((s = ws.get("compat_table", (size_t)N, &table)) != MOR_OK) return s;
+  if ((s = ws.get("compat_warm", (size_t)B * C * ncf, &warm)) != MOR_OK) return s;
+  k_fill_i32<<<(unsigned)std::min<int64_t>(4096, (N + 255) / 256), 256, 0, st>>>(table, N, -1);
+  MOR_LAUNCH_CHECK("compat table");
+  k_mark_coef<<<(ncf + 255) / 256, 256, 0, st>>>(plan_full->d_coef_lin, ncf, table);
+  MOR_LAUNCH_CHECK("compat table");
+  k_zero_c64<<<4096, 256, 0, st>>>(warm, B * C * (int64_t)ncf);
+  MOR_LAUNCH_CHECK("compat clear");
+  if (ncr > 0) {
+    k_embed_coef<<<dim3((ncr + 255) / 256, (unsigned)(B * C)), 256, 0, st>>>((const cpx<float>*)coeffs,
+                                                                              plan->d_coef_lin, ncr, table, ncf, warm);
+    MOR_LAUNCH_CHECK("compat embed");
+  }
+  const bool j2 = phase[0].plastic || phase[1].plastic;
+  float* jst = nullptr;
+  if (j2) {
+    // the committed state is used, not updated: the pass works on a copy
+    if ((s = ws.get("compat_state", (size_t)B * NST * N, &jst)) != MOR_OK) return s;
+    if (state)
+      MOR_HIP_TRY(hipMemcpyAsync(jst, state, (size_t)B * NST * N * sizeof(float), hipMemcpyDeviceToDevice, st));
+    else
+      MOR_HIP_TRY(hipMemsetAsync(jst, 0, (size_t)B * NST * N * sizeof(float), st));
+  }
+  mor_solve_opts o{};
+  if (opts) o = *opts;
+  o.warm_start = (const float*)warm;
+  o.max_iter = 1;
+  o.check_every = 1;
+  o.use_graph = 0;
+  std::vector<mor_plan*> plans = {plan_full};
+  std::vector<int> plan_of(B, 0);
+  // one Green-operator pass: the stop test can only report "not converged"
+  // (or a zero change), both are the intended single pass
+  s = solve_impl(plans, plan_of, macro_strain, B, phase, std::numeric_limits<double>::min(), &o, out, jst,
+                 plan->ndim == 2 ? 4 : 6, nullptr);
+  if (s == MOR_E_NOT_CONVERGED) s = MOR_OK;
+  return s;
+}
+
+namespace {
+// Load paths of B RVEs in one set of launches per iteration (Secs. 2, 5.2):
+// the context is prepared once; each step resets the per-RVE states and the
+// macro strains on the device, starts from the previous step's coefficients
+// (their zero-frequency entry becomes N times the new macro strain, i.e. the
+// previous strain plus the macro increment), iterates every RVE to tolerance
+// with the committed J2 state fixed, and commits the state in the final
+// evaluation.  Effective stresses and states of every step are copied aside
+// on the device and fetched once at the end.
+//   macro: host [B][steps][C]; eff_out host [B][steps][eff_stride];
+//   its/res host [B][steps].
+mor_status path_impl(const std::vector<mor_plan*>& plans, const std::vector<int>& plan_of, const double* macro,
+                     int64_t B, int steps, const mor_phase* phase, double tol, const mor_solve_opts* opts,
+                     float* state, mor_outputs* out, int eff_stride) {
+  std::lock_guard<std::recursive_mutex> lk(stream_mutex(opts ? opts->stream : nullptr));
+  SolveCtx cx;
+  const int C = plans[0]->ndim == 2 ? 3 : 6;
+  std::vector<double> eb((size_t)B * C);
+  auto step_ebar = [&](int n) {
+    for (int64_t b = 0; b < B; ++b)
+      for (int c = 0; c < C; ++c) eb[b * C + c] = macro[((size_t)b * steps + n) * C + c];
+  };
+  step_ebar(0);
+  mor_status s = setup(cx, plans, plan_of, eb.data(), B, phase, tol, opts, state);
+  if (s != MOR_OK) {
+    (void)hipStreamSynchronize(cx.st);
+    return s;
+  }
+  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 10000;
+  double* d_eff_hist = nullptr;
+  RveState* d_st_hist = nullptr;
+  if ((s = cx_get(cx, "eff_hist", (size_t)steps * B * cx.S, &d_eff_hist)) != MOR_OK) return s;
+  if ((s = cx_get(cx, "st_hist", (size_t)steps * B, &d_st_hist)) != MOR_OK) return s;
+  float* eps = out ? out->strain : nullptr;
+  float* sig = out ? out->stress : nullptr;
+  std::vector<std::vector<RveState>> hist((size_t)steps);
+  for (int n = 0; n < steps; ++n) {
+    const bool last = n == steps - 1;
+    if (n > 0) {
+      step_ebar(n);
+      if ((s = upload(cx, cx.d_ebar, eb)) != MOR_OK) return s;
+      if ((s = upload(cx, cx.d_st, fresh_states(cx, plans, plan_of, eb.data(), tol, max_iter))) != MOR_OK) return s;
+      if ((s = upload(cx, cx.d_active, std::vector<unsigned int>(1, (unsigned int)B))) != MOR_OK) return s;
+    }
+    cx.want_eps = last && eps;
+    cx.want_sig = last && sig;
+    // step 0 starts from the caller's warm start (or cold), later steps from
+    // the previous step's coefficients, read and rewritten in place
+    const cpx<float>* warm = n == 0 ? (opts ? (const cpx<float>*)opts->warm_start : nullptr) : cx.d_coef;
+    if ((s = run(cx, warm, opts, last ? eps : nullptr, last ? sig : nullptr)) != MOR_OK) {
+      (void)hipStreamSynchronize(cx.st);
+      return s;
+    }
+    MOR_HIP_TRY(hipMemcpyAsync(d_eff_hist + (size_t)n * B * cx.S, cx.d_eff, (size_t)B * cx.S * sizeof(double),
+                               hipMemcpyDeviceToDevice, cx.st));
+    MOR_HIP_TRY(hipMemcpyAsync(d_st_hist + (size_t)n * B, cx.d_st, (size_t)B * sizeof(RveState),
+                               hipMemcpyDeviceToDevice, cx.st));
+  }
+  std::vector<double> effh((size_t)steps * B * cx.S);
+  std::vector<RveState> sth((size_t)steps * B);
+  MOR_HIP_TRY(hipMemcpyAsync(effh.data(), d_eff_hist, effh.size() * sizeof(double), hipMemcpyDeviceToHost, cx.st));
+  MOR_HIP_TRY(hipMemcpyAsync(sth.data(), d_st_hist, sth.size() * sizeof(RveState), hipMemcpyDeviceToHost, cx.st));
+  if (out && out->coeffs) {
+    int64_t tot = 0;
+    for (int64_t b = 0; b < B; ++b) tot += (int64_t)cx.C * cx.ncoef_h[b];
+    MOR_HIP_TRY(hipMemcpyAsync(out->coeffs, cx.d_coef, tot * sizeof(cpx<float>), hipMemcpyDeviceToDevice, cx.st));
+  }
+  MOR_HIP_TRY(hipStreamSynchronize(cx.st));
+  // profile: the recorded events of all steps, bytes from the summed iterations
+  std::vector<RveState> tot_st(sth.begin(), sth.begin() + B);
+  for (int n = 1; n < steps; ++n)
+    for (int64_t b = 0; b < B; ++b) tot_st[b].iters += sth[(size_t)n * B + b].iters;
+  account(cx, tot_st, steps);
+  mor_status worst = MOR_OK;
+  for (int64_t b = 0; b < B; ++b) {
+    for (int n = 0; n < steps; ++n) {
+      const RveState& r = sth[(size_t)n * B + b];
+      const size_t k = (size_t)b * steps + n;
+      if (out && out->iterations) out->iterations[k] = r.iters;
+      if (out && out->residual) out->residual[k] = r.resid;
+      if (out && out->eff_stress)
+        for (int c = 0; c < cx.S; ++c) out->eff_stress[k * eff_stride + c] = effh[((size_t)n * B + b) * cx.S + c];
+      if (r.status == MOR_E_NONFINITE) worst = MOR_E_NONFINITE;
+      else if (r.status == MOR_E_NOT_CONVERGED && worst == MOR_OK) worst = MOR_E_NOT_CONVERGED;
+    }
+  }
+  if (worst == MOR_E_NONFINITE) mor_set_error("non-finite residual in at least one load step");
+  if (worst == MOR_E_NOT_CONVERGED) mor_set_error("max_iter reached before tol in at least one load step");
+  return worst;
+}
+}  // namespace
+
 extern "C" mor_status mor_solve_path(mor_plan_t plan, const double* macro_strain, int32_t steps,
                                      const mor_phase phase[2], double tol, const mor_solve_opts* opts, float* state,
                                      mor_outputs* out) {
@@ -1436,48 +1640,41 @@ extern "C" mor_status mor_solve_path(mor_plan_t plan, const double* macro_strain
   const int S = plan->ndim == 2 ? 4 : 6;
   mor_status s = check_common(macro_strain, steps, C, phase, tol, opts, plan->ndim);
   if (s != MOR_OK) return s;
-  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
-  // previous-step coefficients seed the next step (warm start with the new mean)
-  cpx<float>* prev = nullptr;
-  const size_t nco = (size_t)C * plan->dev.ncoef;
-  MOR_HIP_TRY(hipMalloc((void**)&prev, std::max<size_t>(nco, 1) * sizeof(cpx<float>)));
   std::vector<mor_plan*> plans = {plan};
   std::vector<int> plan_of(1, 0);
-  mor_status worst = MOR_OK;
-  for (int n = 0; n < steps; ++n) {
-    mor_solve_opts o{};
-    if (opts) o = *opts;
-    o.warm_start = n == 0 ? (opts ? opts->warm_start : nullptr) : (const float*)prev;
-    mor_outputs ostep{};
-    double eff[6];
-    int32_t it = 0;
-    double res = 0.0;
-    ostep.eff_stress = eff;
-    ostep.iterations = &it;
-    ostep.residual = &res;
-    ostep.coeffs = (float*)prev;
-    const bool last = n == steps - 1;
-    ostep.strain = last && out ? out->strain : nullptr;
-    ostep.stress = last && out ? out->stress : nullptr;
-    s = solve_impl(plans, plan_of, macro_strain + (size_t)n * C, 1, phase, tol, &o, &ostep, state, S, nullptr);
-    if (out && out->eff_stress)
-      for (int k = 0; k < S; ++k) out->eff_stress[(size_t)n * S + k] = eff[k];
-    if (out && out->iterations) out->iterations[n] = it;
-    if (out && out->residual) out->residual[n] = res;
-    if (s == MOR_E_NOT_CONVERGED) {
-      worst = s;
-      continue;
-    }
-    if (s != MOR_OK) {
-      (void)hipStreamSynchronize(st);
-      (void)hipFree(prev);
-      return s;
-    }
+  return path_impl(plans, plan_of, macro_strain, 1, steps, phase, tol, opts, state, out, S);
+}
+
+extern "C" mor_status mor_solve_path_multi(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of_rve,
+                                           const double* macro_strain, int64_t B, int32_t steps,
+                                           const mor_phase phase[2], double tol, const mor_solve_opts* opts,
+                                           float* state, mor_outputs* out) {
+  if (!plans || nplans < 1 || !plan_of_rve || !state) {
+    mor_set_error("mor_solve_path_multi: NULL or empty plan list, or NULL state");
+    return MOR_E_INVALID_ARG;
   }
-  (void)hipStreamSynchronize(st);
-  (void)hipFree(prev);
-  if (worst != MOR_OK) mor_set_error("max_iter reached before tol in at least one load step");
-  return worst;
+  if (steps < 1 || B < 1) {
+    mor_set_error("mor_solve_path_multi: steps and B must be >= 1");
+    return MOR_E_INVALID_ARG;
+  }
+  for (int64_t i = 0; i < nplans; ++i)
+    if (!plans[i] || plans[i]->ndim != plans[0]->ndim) {
+      mor_set_error("mor_solve_path_multi: NULL plan, or plans of different ndim");
+      return MOR_E_INVALID_ARG;
+    }
+  std::vector<int> plan_of(B);
+  for (int64_t b = 0; b < B; ++b) {
+    if (plan_of_rve[b] < 0 || plan_of_rve[b] >= nplans) {
+      mor_set_error("mor_solve_path_multi: plan_of_rve out of range");
+      return MOR_E_INVALID_ARG;
+    }
+    plan_of[b] = (int)plan_of_rve[b];
+  }
+  const int C = plans[0]->ndim == 2 ? 3 : 6;
+  mor_status s = check_common(macro_strain, B * (int64_t)steps, C, phase, tol, opts, plans[0]->ndim);
+  if (s != MOR_OK) return s;
+  std::vector<mor_plan*> pl(plans, plans + nplans);
+  return path_impl(pl, plan_of, macro_strain, B, steps, phase, tol, opts, state, out, 6);
 }
 
 extern "C" mor_status mor_profile_enable(int32_t on) {

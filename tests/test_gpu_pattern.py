@@ -31,6 +31,11 @@ def _cases():
     yield "c3_384", synth.rsa_fibres(384, 384, 12, 24, seed=33, target_vf=0.35).g, [7373]
     yield "rand3d", (rng.random((8, 12, 6)) < 0.4).astype(np.uint8), [1, 5, 57, 576]
     yield "sphere32", synth.sphere(32, 32, 32, 9.0), [656]
+    # the configured full sizes: 512^2 J2 fibres at M = 1, 5, 20 % and the
+    # 128^3 spheres at M = 2 % (same recipes as the full-size fixtures)
+    from tests.golden.make_golden import c2_geometry, c4_geometry
+    yield "c2_512", c2_geometry(), [2622, 13108, 52429]
+    yield "c4_128cube", c4_geometry(), [41944]
 
 
 @pytest.mark.parametrize("name,g,Ms", list(_cases()), ids=[c[0] for c in _cases()])
