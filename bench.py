@@ -29,6 +29,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 from concurrent.futures import ProcessPoolExecutor
@@ -42,6 +43,8 @@ import numpy as np  # noqa: E402
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TF = 157.3
+FP32_NONPACKED_TF = 78.6
 METRIC = "RVE solves/s at residual 1e-6, 256² 2D 5% freqs: learned/batched vs plain"
 GRID = 256
 M_FREQ = int(math.ceil(0.05 * GRID * GRID))
@@ -67,35 +70,84 @@ def phases():
     return [mor.Phase(lm, mm), mor.Phase(li, mi)]
 
 
-def cpu_baseline(gs, ebs, budget_s=15.0):
-    """The FP64 oracle, as it stands, on the first RVEs of the same workload."""
+def _oracle_solve(args):
+    """One oracle solve of the workload (pattern construction timed apart)."""
+    g, eb = args
     from oracle import material, pattern, solver
     lm, mm = synth.phase_lame(synth.MATRIX_E, synth.MATRIX_NU)
     li, mi = synth.phase_lame(synth.FIBRE_E, synth.FIBRE_NU)
     ph = (material.Phase(lm, mm), material.Phase(li, mi))
-    done = 0
-    t_solve = 0.0
-    t_plan = 0.0
-    its = []
+    tp = time.perf_counter()
+    p = pattern.build_pattern(g, M_FREQ)
+    ts = time.perf_counter()
+    r = solver.solve(g, ph, solver.macro_tensor(eb, 2), mask=p.mask(), tol=TOL)
+    te = time.perf_counter()
+    return te - ts, ts - tp, r.iterations, solver.tensor_comps(r.sigma_bar, 2, with_s33=True)
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(gs, ebs, budget_s=12.0):
+    """The FP64 oracle, as it stands, on the same workload: first one thread
+    (NumPy's FFT is single-threaded), then one oracle process per core over
+    further RVEs of the workload.  Returns the line's cpu_baseline object and
+    the oracle's effective stresses of the RVEs it solved (index -> sigma_bar)."""
+    done, t_solve, t_plan, its, sig = 0, 0.0, 0.0, [], {}
     t0 = time.perf_counter()
     while done < len(gs) and time.perf_counter() - t0 < budget_s:
-        tp = time.perf_counter()
-        p = pattern.build_pattern(gs[done], M_FREQ)
-        t_plan += time.perf_counter() - tp
-        ts = time.perf_counter()
-        r = solver.solve(gs[done], ph, solver.macro_tensor(ebs[done], 2), mask=p.mask(), tol=TOL)
-        t_solve += time.perf_counter() - ts
-        its.append(r.iterations)
+        ts, tp, it, sb = _oracle_solve((gs[done], ebs[done]))
+        t_solve += ts
+        t_plan += tp
+        its.append(it)
+        sig[done] = sb
         done += 1
-    return {
-        "value": done / t_solve,
+    single = done / t_solve
+    workers = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16"))))
+    n_all = min(len(gs) - done, workers * max(2, int(round(budget_s * single))))
+    idx = list(range(done, done + n_all))
+    all_rate = None
+    if n_all > 0:
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(_oracle_solve, [(gs[0], ebs[0])] * workers))  # start the workers and import
+            t = time.perf_counter()
+            res = list(ex.map(_oracle_solve, [(gs[i], ebs[i]) for i in idx]))
+            wall = time.perf_counter() - t
+        all_rate = n_all / wall
+        for i, r in zip(idx, res):
+            its.append(r[2])
+            sig[i] = r[3]
+    base = {
+        "value": all_rate if all_rate else single,
         "unit": "RVE solves/s",
-        "cores": 1,
+        "cores": workers if all_rate else 1,
         "kind": "oracle",
-        "sample": f"{done} held-out 256x256 RVEs (M={M_FREQ}, residual {TOL:g}), FP64 NumPy oracle, "
-                  f"single thread, pattern construction excluded (with it: {done / (t_solve + t_plan):.3f}/s)",
+        "sample": f"held-out 256x256 RVEs of the same workload (M={M_FREQ}, residual {TOL:g}), FP64 NumPy "
+                  f"oracle: {done} solved on one thread, then {n_all} by {workers} single-threaded oracle "
+                  f"processes (one per core); pattern construction excluded (single thread with it: "
+                  f"{done / (t_solve + t_plan):.3f}/s)",
+        "single_thread": {"value": single, "cores": 1, "rves": done},
+        "all_cores": {"value": all_rate, "cores": workers, "rves": n_all},
+        "cpu_model": cpu_model(),
+        "os_cpu_count": os.cpu_count(),
         "mean_iterations": float(np.mean(its)),
     }
+    return base, sig
 
 
 SOLVE_SOURCES = ("fft_lds.h", "fft_reg.h", "mor_internal.h", "solve_fast.h", "solve_kernels.h", "solve.hip")
@@ -182,6 +234,57 @@ def timed_batched(mor, plans, plan_of, ebs, ph, steps, warmup, warm_fn=None):
     return out, elapsed, kern
 
 
+def end_to_end_pipelined(mor, gs, ebs, ph, batch, s_plan, warm_fn=None):
+    """End to end over several batches as an FE-FFT driver would run them:
+    the plans of batch k+1 are built (host checks and staging, plan kernels on
+    the stream s_plan, from a second host thread) while batch k is solved on
+    the current stream.  Returns solves/s over the whole run, plan
+    construction of the first batch (not overlapped) included."""
+    import queue
+    import threading
+
+    import torch
+    nb = len(gs) // batch
+    s_solve = torch.cuda.current_stream()
+    q = queue.Queue(maxsize=2)
+    err = []
+
+    def producer():
+        try:
+            with torch.cuda.stream(s_plan):
+                for k in range(nb):
+                    plans = mor.make_plans(gs[k * batch:(k + 1) * batch], M_FREQ, stream=s_plan)
+                    s_plan.synchronize()
+                    q.put(plans)
+        except Exception as e:  # noqa: BLE001 - reported by the consumer
+            err.append(e)
+            q.put(None)
+
+    keep = []
+    po = np.arange(batch)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    th = threading.Thread(target=producer)
+    th.start()
+    with torch.cuda.stream(s_solve):
+        for k in range(nb):
+            plans = q.get()
+            if plans is None:
+                break
+            eb = ebs[k * batch:(k + 1) * batch]
+            w = warm_fn(plans, po, eb) if warm_fn else None
+            out = mor.solve_multi(plans, po, eb, ph, TOL, warm_start=w, stream=s_solve, **SOLVE_KW)
+            assert out.status == mor.MOR_OK, out.status
+            keep.append(plans)  # released after the timed region (destroying a plan drains the device)
+    th.join()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    if err:
+        raise err[0]
+    del keep
+    return nb * batch / el, nb
+
+
 def timed_single(mor, plans, ebs, ph, count, warm_fn=None, use_graph=0):
     """Plain path: one RVE per call (mor_solve), optionally warm-started and
     with the iteration chunks replayed from a hipGraph."""
@@ -227,11 +330,33 @@ def train_network(mor, ph, ntrain, nslots, epochs, log):
     return net, info
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _golden(name):
+    """Expected values written by tests/golden/make_golden.py from the FP64
+    oracle (None if the fixture is missing)."""
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _max_rel(got, want):
+    got = np.atleast_2d(np.asarray(got, dtype=np.float64))
+    want = np.atleast_2d(np.asarray(want, dtype=np.float64))
+    d = np.max(np.abs(got[:, :want.shape[1]] - want), axis=1)
+    return float(np.max(d / np.max(np.abs(want), axis=1)))
+
+
 def other_configs(mor, ph):
     """Throughput of the other configured workloads (one timed call each,
     after one untimed call): the 4096-RVE uneven batch (also autotuned with
     hipGraph replay), 3D 128^3 with the FFT and the split-bf16 MFMA DFT, the
-    64^2 disk in FP64 to 1e-8, and the 512^2 J2 load path."""
+    64^2 disk in FP64 to 1e-8, and the 512^2 J2 load path.  Each result
+    carries its largest effective-stress difference from the FP64 oracle
+    (the oracle's fixtures, or an oracle solve of the 64^2 disk)."""
     import torch
 
     def timed(fn, reps=1):
@@ -254,6 +379,11 @@ def other_configs(mor, ph):
     res["uneven_4096"] = {"workload": "4096 RVEs round robin over 128², 256², 384² fibre RVEs (vf 0.35), M = 5 %, "
                                       "one mor_solve_multi call, residual 1e-6",
                           "solves_per_s": B / el, "ms": el * 1e3, "mean_iterations": float(out.iterations.mean())}
+    G3 = _golden("c3_stiffness")
+    if G3:
+        C = [np.array(gr["C_eff"]) for gr in G3["grids"]]
+        res["uneven_4096"]["oracle_rel_err"] = _max_rel(out.eff_stress, np.stack([C[po[b]] @ ebs[b]
+                                                                                 for b in range(B)]))
     # the same after the autotuner has measured every row and column variant of
     # the three sizes on this workload, with the iteration chunks replayed from
     # a captured hipGraph; the selections are put back afterwards
@@ -271,12 +401,17 @@ def other_configs(mor, ph):
     g3 = synth.rsa_spheres(128, 128, 128, 8.0, 14.0, seed=7, target_vf=0.25).g
     p3 = mor.Plan(g3, int(math.ceil(0.02 * g3.size)))
     e3 = synth.macro_strains(8, 6, 1e-3, seed=3)
+    G4 = _golden("c4_128")
     for name, kw, tol in (("fft", {}, 1e-6), ("dft_bf16x3", {"precision": mor.PREC_BF16X3}, 1e-5)):
         el, out = timed(lambda: mor.solve(p3, e3, ph, tol, **kw))
         res[f"cube128_{name}"] = {"workload": "128³ spheres (vf 0.25), M = 2 %, 8 macro strains in one call, "
                                               f"residual {tol:g}",
                                   "solves_per_s": 8 / el, "ms": el * 1e3,
                                   "mean_iterations": float(out.iterations.mean())}
+        if G4:
+            e_one = np.array([G4["macro_strain"]])
+            one = mor.solve(p3, e_one, ph, tol, **kw)
+            res[f"cube128_{name}"]["oracle_rel_err"] = _max_rel(one.eff_stress, [G4["sigma_bar"]])
     del p3
     # the paper's 64^2 centred disk (M = 205) to its residual 1e-8, FP64 throughout
     n1 = 64
@@ -288,6 +423,20 @@ def other_configs(mor, ph):
                                            "FP64 throughout, residual 1e-8",
                                "solves_per_s": 256 / el, "ms": el * 1e3,
                                "mean_iterations": float(out.iterations.mean())}
+    # against the oracle's effective stiffness of the disk (linear in the macro strain)
+    from oracle import material, pattern, solver
+    lm, mm = synth.phase_lame(synth.MATRIX_E, synth.MATRIX_NU)
+    li, mi = synth.phase_lame(synth.FIBRE_E, synth.FIBRE_NU)
+    oph = (material.Phase(lm, mm), material.Phase(li, mi))
+    mask = pattern.build_pattern(g1, 205).mask()
+    cols = []
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1.0
+        r = solver.solve(g1, oph, solver.macro_tensor(e, 2), mask=mask, tol=1e-12, max_iter=5000)
+        cols.append(solver.tensor_comps(r.sigma_bar, 2, with_s33=True))
+    Cd = np.stack(cols, axis=1)
+    res["disk64_fp64_1e-8"]["oracle_rel_err"] = _max_rel(out.eff_stress, e1 @ Cd.T)
     del p1
     g2 = synth.rsa_fibres(512, 512, 20.0, 40.0, seed=2103, target_vf=0.40).g
     p2 = mor.Plan(g2, int(math.ceil(0.05 * g2.size)))
@@ -303,6 +452,10 @@ def other_configs(mor, ph):
     el, out = timed(run_path)
     res["j2_512_path"] = {"workload": "512² J2 fibres (vf 0.4), M = 5 %, 20 load steps to 2 %, residual 1e-6",
                           "ms_per_path": el * 1e3, "iterations": int(out.iterations.sum())}
+    G2 = _golden("c2_j2_512")
+    if G2:
+        case = G2["cases"][str(p2.info["M"])]
+        res["j2_512_path"]["oracle_rel_err"] = _max_rel(out.eff_stress, case["sigma_bar"])
     return res
 
 
@@ -329,6 +482,8 @@ def main():
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the timings of the other configured workloads")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--e2e-batches", type=int, default=4,
+                    help="batches of the pipelined end-to-end run (plans of the next batch built meanwhile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -406,6 +561,23 @@ def main():
         learned = {"rate": hot_rate, "elapsed": el_hot, "kern": kern_hot, "out": hot, "train": tinfo,
                    "eff_stress_rel_diff_vs_cold": dstress}
 
+    # end to end: plan construction of the next batch overlapped with the solve
+    # of the current one (second stream, second host thread)
+    e2e_pipe = None
+    if args.e2e_batches > 0:
+        gs_e, ebs_e = workload(args.e2e_batches * B)
+        wf = None
+        if learned is not None:
+            wf = lambda pl, po_, eb: warm.predict_warm(net, pl, po_, eb, ph, S)  # noqa: E731
+        s_plan = torch.cuda.Stream()
+        end_to_end_pipelined(mor, gs_e[:2 * B], ebs_e[:2 * B], ph, B, s_plan, wf)  # warm-up: buffers, pools
+        rate, nbat = end_to_end_pipelined(mor, gs_e, ebs_e, ph, B, s_plan, wf)
+        e2e_pipe = {"solves_per_s": rate, "batches": nbat, "batch": B,
+                    "note": "plans of batch k+1 built on a second stream from a second host thread while batch "
+                            "k is solved (learned start when trained); first batch's plans not overlapped"}
+        del gs_e, ebs_e
+        log(f"end to end, pipelined: {rate:.0f} solves/s")
+
     if learned is not None:
         head_out, head_el, kern, start = learned["out"], learned["elapsed"], learned["kern"], "learned"
     else:
@@ -416,14 +588,35 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms"])
     kd = kern[dom]
     achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9 if kd["ms"] > 0 else 0.0
-    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+    traffic = measured_traffic(dom)
+    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "traffic": traffic,
+           "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+           "bytes_note": "algorithmic bytes per RVE-iteration: rows (16 C nlast + L) for the row kernel, "
+                         "ncol 16 C n0 + ncoef (16 C + 17) for the column kernel"}
+    # The fused row kernel keeps the fields in registers: it is bound by
+    # VALU issue, so its roofline is the FP32 vector peak.  Algorithmic flops
+    # per RVE-iteration: the inverse and forward real FFTs of every row and
+    # strain component (2.5 L log2 L each) and the Hooke law (25 per point).
+    def row_flops(p):
+        L = p.shape[-1]
+        return p.ncomp * (p.N // L) * 2 * 2.5 * L * math.log2(L) + 25.0 * p.N
+
+    row_fl = args.steps * sum(row_flops(plans[plan_of[b]]) * int(it) for b, it in enumerate(head_out.iterations))
+    kr = kern["row"]
+    alu = row_fl / (kr["ms"] * 1e-3) / 1e12 if kr["ms"] > 0 else 0.0
+    roof = {"bound": "alu", "kernel": "row", "achieved": alu, "peak": FP32_PEAK_TF, "unit": "TFLOP/s",
+            "frac": alu / FP32_PEAK_TF, "traffic": measured_traffic("row"),
+            "frac_nonpacked": alu / FP32_NONPACKED_TF,
+            "flops_note": "per RVE-iteration rows * C * 2 * 2.5 L log2 L + 25 N (FFT-path flops of the fused "
+                          "row pass); peak = FP32 vector 157.3 TFLOP/s; frac_nonpacked against the 78.6 "
+                          "TFLOP/s that FP32 FMAs reach without packed instructions (not generated here)",
             "timing": "HIP events around every launch of the kernel in an eager repetition of the timed steps",
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "avg_launch_us": kd["ms"] * 1e3 / max(kd["launches"], 1), "launches": kd["launches"],
-            "valu_issue_frac": measured_valu_issue(dom),
+            "avg_launch_us": kr["ms"] * 1e3 / max(kr["launches"], 1), "launches": kr["launches"],
+            "valu_issue_frac": measured_valu_issue("row"),
             "valu_note": "share of the 1024 SIMDs' VALU issue slots the kernel used (rocprofv3 SQ_INSTS_VALU, "
-                         "SQ_BUSY_CYCLES); near 1 means arithmetic issue, not HBM, bounds it"}
+                         "SQ_BUSY_CYCLES); near 1 means arithmetic issue, not HBM, bounds it",
+            "hbm": dict(hbm, kernel=dom)}
     if dft:
         # the last-axis stage is two dense GEMMs: 8 C rows nlast L flops per RVE-iteration
         fl = sum(8.0 * p.ncomp * (p.N // p.shape[-1]) * p.info["n_last"] * p.shape[-1] * it
@@ -514,6 +707,7 @@ def main():
         "plan_ms_per_rve": plan_ms,
         "plan_ms_per_rve_single_calls": plan_ms_seq,
         "end_to_end_solves_per_s": 1.0 / (1.0 / value + plan_ms * 1e-3),
+        "end_to_end_pipelined": e2e_pipe,
         "workload_gen_s": t_gen,
     }
     if learned:
@@ -522,7 +716,21 @@ def main():
     if not args.no_other_configs:
         line["other_configs"] = other_configs(mor, ph)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(gs, ebs, args.cpu_budget)
+        base, osig = cpu_baseline(gs, ebs, args.cpu_budget)
+        line["cpu_baseline"] = base
+        idx = sorted(osig)
+        want = np.stack([osig[i] for i in idx])
+
+        def rel_err(out):
+            d = np.max(np.abs(out.eff_stress[idx, :want.shape[1]] - want), axis=1)
+            return float(np.max(d / np.max(np.abs(want), axis=1)))
+
+        line["oracle_rel_err"] = {
+            "eff_stress": {"learned": rel_err(head_out) if learned else None, "cold": rel_err(cold),
+                           "born_prior": rel_err(born)},
+            "rves": len(idx), "oracle_tol": TOL,
+            "note": "largest effective-stress difference of the GPU from the FP64 oracle over the RVEs the "
+                    "oracle solved, relative to each RVE's largest component (both stop at the same residual)"}
     print(json.dumps(line), flush=True)
 
 

@@ -21,6 +21,7 @@
 #include <vector>
 #include <string>
 #include <cstdlib>
+#include <thread>
 
 #include "mor_internal.h"
 
@@ -179,9 +180,17 @@ __global__ void k_g_to_cplx(const uint8_t* __restrict__ G, const PlanPtrs* __res
     pp[b].g[i] = (uint8_t)v;
     S[(int64_t)b * N + i] = {(double)v, 0.0};
   }
-  // integer count of inclusion voxels (order-independent, exact)
-  unsigned long long m = __ballot(v != 0);
-  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count + b, (unsigned long long)__popcll(m));
+  // integer count of inclusion voxels (order-independent, exact): one
+  // atomic per workgroup
+  __shared__ unsigned int wc[16];
+  const unsigned long long m = __ballot(v != 0);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (unsigned int)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += wc[w];
+    if (t) atomicAdd(count + b, t);
+  }
 }
 
 // FFT of every line along one axis of a C-ordered complex array viewed as
@@ -259,45 +268,59 @@ __global__ void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N, con
                        const uint8_t* __restrict__ radial, SortEl* __restrict__ out, int64_t stride,
                        unsigned int* nout, SortEl* __restrict__ side, unsigned int* nside) {
   const int b = blockIdx.y;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(threadIdx.x & 63);
   S += (int64_t)b * N;
   count += b;
   out += (int64_t)b * stride;
   nout += b;
-  int k[3], c[3];
-  unravel(d, i, k);
-  conj_k(d, k, c);
-  uint32_t lr = lexrank(d, k), lc = lexrank(d, c);
-  if (lr > lc) return;  // the partner represents this pair
-  const double cnt = (double)(*count);
-  const double P0 = cnt * cnt;
-  double P;
-  if (i == 0) {
-    P = P0;
-  } else {
-    cpx<double> v = S[i];
-    P = v.x * v.x + v.y * v.y;
+  bool main_rep = false, self_rep = false;
+  SortEl e{};
+  if (i < N) {
+    int k[3], c[3];
+    unravel(d, i, k);
+    conj_k(d, k, c);
+    const uint32_t lr = lexrank(d, k), lc = lexrank(d, c);
+    if (lr <= lc) {  // else the partner represents this pair
+      const double cnt = (double)(*count);
+      const double P0 = cnt * cnt;
+      double P;
+      if (i == 0) {
+        P = P0;
+      } else {
+        cpx<double> v = S[i];
+        P = v.x * v.x + v.y * v.y;
+      }
+      float key = 0.0f;
+      if (radial) {
+        key = radial[i] ? 1.0f : 0.0f;  // every frequency of the fixed pattern ranks alike
+      } else if (P0 > 0.0 && !(P <= ldexp(P0, -80))) {
+        key = (float)(P / P0);
+      }
+      const int n[3] = {d.n0, d.n1, d.n2};
+      uint32_t s2 = 0;
+      for (int a = 0; a < d.nd; ++a) {
+        int s = signed_k(k[a], n[a]);
+        s2 += (uint32_t)(s * s);
+      }
+      e = {~__float_as_uint(key), s2, lr, (uint32_t)i};
+      self_rep = lr == lc;
+      main_rep = !self_rep;
+    }
   }
-  float key = 0.0f;
-  if (radial) {
-    key = radial[i] ? 1.0f : 0.0f;  // every frequency of the fixed pattern ranks alike
-  } else if (P0 > 0.0 && !(P <= ldexp(P0, -80))) {
-    key = (float)(P / P0);
-  }
-  const int n[3] = {d.n0, d.n1, d.n2};
-  uint32_t s2 = 0;
-  for (int a = 0; a < d.nd; ++a) {
-    int s = signed_k(k[a], n[a]);
-    s2 += (uint32_t)(s * s);
-  }
-  const SortEl e = {~__float_as_uint(key), s2, lr, (uint32_t)i};
-  if (lr == lc) {
+  if (self_rep) {  // at most 2^ndim per plan
     const unsigned int pos = atomicAdd(nside + b, 1u);
     side[(int64_t)b * kSide + pos] = e;
-  } else {
-    const unsigned int pos = atomicAdd(nout, 1u);
-    out[pos] = e;
+  }
+  // the pairs' representatives: one atomic per wavefront claims a run of
+  // slots (the sort that follows makes their order irrelevant)
+  const unsigned long long m = __ballot(main_rep);
+  if (m) {
+    const int first = __ffsll((long long)m) - 1;
+    unsigned int base = 0;
+    if (lane == first) base = atomicAdd(nout, (unsigned int)__popcll(m));
+    base = __shfl(base, first, 64);
+    if (main_rep) out[base + __popcll(m & ((1ull << lane) - 1ull))] = e;
   }
 }
 
@@ -807,30 +830,6 @@ hipError_t DevBuf<T>::alloc(PlanScratch& sc, size_t n) {
   return sc.get((void**)&p, std::max<size_t>(n, 1) * sizeof(T));
 }
 
-// A device block owned by the plan, from the same pool; plan_free gives the
-// plan's blocks back once the device has drained.
-template <typename T>
-hipError_t plan_alloc(mor_plan* P, T** out, size_t bytes) {
-  bytes = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
-  ScratchPool& pool = scratch_pool(P->device);
-  {
-    std::lock_guard<std::mutex> lk(pool.mu);
-    auto it = pool.free.lower_bound(bytes);
-    if (it != pool.free.end() && it->first <= 4 * bytes) {
-      P->blocks.push_back(*it);
-      *out = (T*)it->second;
-      pool.free.erase(it);
-      return hipSuccess;
-    }
-  }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) return e;
-  P->blocks.push_back({bytes, p});
-  *out = (T*)p;
-  return hipSuccess;
-}
-
 }  // namespace
 
 static void plan_free(mor_plan* p) {
@@ -849,19 +848,113 @@ static void plan_free(mor_plan* p) {
   delete p;
 }
 
-// Pinned host staging of a batch's phase maps; released after its stream
-// has drained (the copy from it is asynchronous).
+// Pinned host staging of a batch's phase maps.  Buffers are kept in a
+// per-device free list for reuse (allocating and freeing pinned memory can
+// stall the whole device, which a plan construction overlapped with solves
+// on another stream must not do); one is handed back after its stream has
+// drained (the copy from it is asynchronous).
+struct PinnedPool {
+  std::mutex mu;
+  std::multimap<size_t, void*> free;
+};
+PinnedPool& pinned_pool(int dev) {
+  static std::mutex mu;
+  static std::map<int, PinnedPool*> pools;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = pools.find(dev);
+  if (it != pools.end()) return *it->second;
+  PinnedPool* p = new PinnedPool();
+  pools[dev] = p;
+  return *p;
+}
+
 struct PinnedStage {
   hipStream_t st;
+  int dev = 0;
   void* p = nullptr;
-  explicit PinnedStage(hipStream_t s) : st(s) {}
+  size_t bytes = 0;
+  explicit PinnedStage(hipStream_t s) : st(s) { (void)hipGetDevice(&dev); }
+  hipError_t get(size_t want) {
+    PinnedPool& pool = pinned_pool(dev);
+    {
+      std::lock_guard<std::mutex> lk(pool.mu);
+      auto it = pool.free.lower_bound(want);
+      if (it != pool.free.end()) {
+        bytes = it->first;
+        p = it->second;
+        pool.free.erase(it);
+        return hipSuccess;
+      }
+    }
+    bytes = want;
+    return hipHostMalloc(&p, want, hipHostMallocDefault);
+  }
   ~PinnedStage() {
     if (p) {
       (void)hipStreamSynchronize(st);
-      (void)hipHostFree(p);
+      PinnedPool& pool = pinned_pool(dev);
+      std::lock_guard<std::mutex> lk(pool.mu);
+      pool.free.insert({bytes, p});
     }
   }
 };
+
+// Device blocks of a batch of plans: each from the pool when one fits, the
+// others carved from one allocation (one hipMalloc per batch, not per plan);
+// the carved pieces go back to the pool like any block and are never freed.
+static hipError_t plan_alloc_batch(mor_plan* const* P, int cnt, const std::vector<size_t>& sizes,
+                                   std::vector<unsigned char*>& bases) {
+  bases.assign(cnt, nullptr);
+  std::vector<int> miss;
+  size_t total = 0;
+  ScratchPool& pool = scratch_pool(P[0]->device);
+  {
+    std::lock_guard<std::mutex> lk(pool.mu);
+    for (int b = 0; b < cnt; ++b) {
+      const size_t bytes = (std::max<size_t>(sizes[b], 1) + 255) / 256 * 256;
+      auto it = pool.free.lower_bound(bytes);
+      if (it != pool.free.end() && it->first <= 4 * bytes) {
+        P[b]->blocks.push_back(*it);
+        bases[b] = (unsigned char*)it->second;
+        pool.free.erase(it);
+      } else {
+        miss.push_back(b);
+        total += bytes;
+      }
+    }
+  }
+  if (miss.empty()) return hipSuccess;
+  unsigned char* slab = nullptr;
+  const hipError_t e = hipMalloc((void**)&slab, total);
+  if (e != hipSuccess) return e;
+  size_t at = 0;
+  for (int b : miss) {
+    const size_t bytes = (std::max<size_t>(sizes[b], 1) + 255) / 256 * 256;
+    bases[b] = slab + at;
+    P[b]->blocks.push_back({bytes, slab + at});
+    at += bytes;
+  }
+  return hipSuccess;
+}
+
+// Host work over `n` items split across threads when it is large (map
+// checks and staging copies of big batches); fn(begin, end) handles a range.
+template <typename F>
+static void host_parallel(int64_t n, size_t bytes, F fn) {
+  const unsigned hc = std::max(1u, std::thread::hardware_concurrency());
+  const int64_t nt = std::min<int64_t>({(int64_t)std::min(hc, 8u), n, (int64_t)(bytes >> 22) + 1});
+  if (nt <= 1) {
+    fn((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t per = (n + nt - 1) / nt;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t a = t * per, b = std::min(n, a + per);
+    if (a < b) th.emplace_back(fn, a, b);
+  }
+  for (auto& x : th) x.join();
+}
 
 // Builds `cnt` plans of one grid (P[i]->M may differ) from host phase maps
 // maps[0..cnt) (each N bytes, already checked), staged through `pinned`
@@ -914,7 +1007,9 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
   // host memcpy of each, then one DMA; the previous chunk's copy has drained
   // at its final synchronisation), else one copy per map.
   if (pinned) {
-    for (int b = 0; b < cnt; ++b) std::memcpy(pinned + (size_t)b * N, maps[b], (size_t)N);
+    host_parallel(cnt, (size_t)cnt * N, [&](int64_t a, int64_t e) {
+      for (int64_t b = a; b < e; ++b) std::memcpy(pinned + (size_t)b * N, maps[b], (size_t)N);
+    });
     MOR_HIP_TRY(hipMemcpyAsync(G.p, pinned, (size_t)cnt * N, hipMemcpyHostToDevice, st));
   } else {
     for (int b = 0; b < cnt; ++b)
@@ -935,22 +1030,47 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
   il.coef_k0 = (int32_t)(3 * cap_col + 1 + 2 * cap_last + 1);
   const int n0 = P0.n[0], n1 = P0.n[1];
   const int ntw = n0 + n1 + nlen / 2 + nlen;
+  // layout of every plan's block (offsets within it), then the blocks
+  struct Layout {
+    size_t g, rank, srep, sghat, sorted, ints, clin, cn, cn64, flag, slot, tw, tw64, dev, total;
+  };
+  std::vector<Layout> lay(cnt);
+  std::vector<size_t> sizes(cnt);
   for (int b = 0; b < cnt; ++b) {
-    mor_plan* Q = P[b];
-    const int64_t m1 = Q->M + 1;
+    const int64_t m1 = P[b]->M + 1;
     size_t at = 0;
     auto take = [&at](size_t bytes) {
       const size_t o = at;
       at += (bytes + 255) / 256 * 256;
       return o;
     };
-    const size_t o_g = take(N), o_rank = take(m1 * 8), o_srep = take(m1 * 8), o_sghat = take(m1 * 8),
-                 o_sorted = take(m1 * 8), o_ints = take((il.coef_k0 + m1) * 4), o_clin = take(m1 * 8),
-                 o_cn = take(m1 * 12), o_cn64 = take(m1 * 24), o_flag = take(m1), o_slot = take(m1 * 4),
-                 o_tw = take(ntw * sizeof(cpx<float>)), o_tw64 = take(ntw * sizeof(cpx<double>)),
-                 o_dev = take(sizeof(PlanDev));
-    unsigned char* base = nullptr;
-    MOR_HIP_TRY(plan_alloc(Q, &base, at));
+    Layout& L = lay[b];
+    L.g = take(N);
+    L.rank = take(m1 * 8);
+    L.srep = take(m1 * 8);
+    L.sghat = take(m1 * 8);
+    L.sorted = take(m1 * 8);
+    L.ints = take((il.coef_k0 + m1) * 4);
+    L.clin = take(m1 * 8);
+    L.cn = take(m1 * 12);
+    L.cn64 = take(m1 * 24);
+    L.flag = take(m1);
+    L.slot = take(m1 * 4);
+    L.tw = take(ntw * sizeof(cpx<float>));
+    L.tw64 = take(ntw * sizeof(cpx<double>));
+    L.dev = take(sizeof(PlanDev));
+    L.total = at;
+    sizes[b] = at;
+  }
+  std::vector<unsigned char*> bases;
+  MOR_HIP_TRY(plan_alloc_batch(P, cnt, sizes, bases));
+  for (int b = 0; b < cnt; ++b) {
+    mor_plan* Q = P[b];
+    const Layout& L = lay[b];
+    const size_t o_g = L.g, o_rank = L.rank, o_srep = L.srep, o_sghat = L.sghat, o_sorted = L.sorted,
+                 o_ints = L.ints, o_clin = L.clin, o_cn = L.cn, o_cn64 = L.cn64, o_flag = L.flag, o_slot = L.slot,
+                 o_tw = L.tw, o_tw64 = L.tw64, o_dev = L.dev;
+    unsigned char* base = bases[b];
     Q->d_g = base + o_g;
     Q->d_rank = (int64_t*)(base + o_rank);
     Q->d_slot_rep = (int64_t*)(base + o_srep);
@@ -1270,14 +1390,23 @@ static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t c
     }
   }
   for (int64_t b = 0; b < count; ++b) {
-    const uint8_t* g = maps[b];
-    if (!g) {
+    if (!maps[b]) {
       mor_set_error(std::string(who) + ": NULL phase map (microstructure " + std::to_string(b) + ")");
       return MOR_E_INVALID_ARG;
     }
-    uint8_t any = 0;  // OR of the values: above 1 iff some value is
-    for (int64_t i = 0; i < N; ++i) any |= g[i];
-    if (any > 1) {
+  }
+  // every value 0 or 1: the OR of a map's bytes is above 1 iff some value is
+  std::vector<uint8_t> bad((size_t)count, 0);
+  host_parallel(count, (size_t)count * N, [&](int64_t a, int64_t e) {
+    for (int64_t b = a; b < e; ++b) {
+      const uint8_t* g = maps[b];
+      uint8_t any = 0;
+      for (int64_t i = 0; i < N; ++i) any |= g[i];
+      bad[b] = any > 1;
+    }
+  });
+  for (int64_t b = 0; b < count; ++b) {
+    if (bad[b]) {
       mor_set_error(std::string(who) + ": phase_map values must be 0 or 1 (microstructure " + std::to_string(b) + ")");
       return MOR_E_INVALID_ARG;
     }
@@ -1313,7 +1442,7 @@ static mor_status plan_create_n(const char* who, const mor_grid* grid, int64_t c
   mor_status s = MOR_OK;
   PinnedStage stage(st);
   if (count > 1) {
-    const hipError_t e = hipHostMalloc(&stage.p, (size_t)chunk * N, hipHostMallocDefault);
+    const hipError_t e = stage.get((size_t)chunk * N);
     if (e != hipSuccess) {
       stage.p = nullptr;
       mor_set_error(std::string(who) + ": pinned staging buffer: " + hipGetErrorString(e));

@@ -10,11 +10,12 @@ Orchestration only: plans, solves, the compatibility step and the error
 measures all run in the library (mor_plan_create, mor_solve /
 mor_solve_path, mor_compat, mor_stress_error).
 
-    python -m paper_2103_10203_amd.sweep [--n 256] [--j2-steps 0]
+    python -m paper_2103_10203_amd.sweep [--n 256] [--j2-steps 0] [--lines 1,2,4]
 
 prints one JSON document with the sweep of the 2D one-inclusion example of
 Sec. 5.1 (centred disk, lambda = mu = 2 GPa inclusion in lambda = mu = 1 GPa
-matrix, eps_11 = 0.01, eps_22 = -0.01).
+matrix, eps_11 = 0.01, eps_22 = -0.01), or with --j2-steps of the
+elasto-plastic example of Sec. 5.2 on seeded random fibres.
 """
 from __future__ import annotations
 
@@ -90,13 +91,26 @@ def error_sweep(g, phases, macro_strain, lines=DEFAULT_LINES, fractions=None, to
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--j2-steps", type=int, default=0)
+    ap.add_argument("--j2-steps", type=int, default=0,
+                    help="> 0: the elasto-plastic example of Sec. 5.2 (several inclusions, J2 matrix) "
+                         "as a load path of this many steps")
+    ap.add_argument("--lines", type=str, default=",".join(str(v) for v in DEFAULT_LINES))
     args = ap.parse_args()
     import synth
     n = args.n
-    g = synth.disk(n, n, n * 0.25)
-    phases = [mor.Phase(1.0, 1.0), mor.Phase(2.0, 2.0)]
-    print(json.dumps(error_sweep(g, phases, [0.01, -0.01, 0.0], j2_steps=args.j2_steps)))
+    lines = tuple(int(v) for v in args.lines.split(","))
+    if args.j2_steps > 0:
+        # Sec. 5.2: several inclusions, lambda = mu = 2 / 1 GPa, J2 matrix with
+        # sigma_y0 = H = 0.01 GPa, eps = [[0.01, 0.002], [0.002, -0.01]]
+        g = synth.rsa_fibres(n, n, n / 16, n / 8, seed=52, target_vf=0.3).g
+        phases = [mor.Phase(1.0, 1.0, 0.01, 0.01, True), mor.Phase(2.0, 2.0)]
+        eb = [0.01, -0.01, 0.002]
+    else:
+        # Sec. 5.1: one centred circular inclusion, eps_11 = 0.01, eps_22 = -0.01
+        g = synth.disk(n, n, n * 0.25)
+        phases = [mor.Phase(1.0, 1.0), mor.Phase(2.0, 2.0)]
+        eb = [0.01, -0.01, 0.0]
+    print(json.dumps(error_sweep(g, phases, eb, lines=lines, j2_steps=args.j2_steps)))
 
 
 if __name__ == "__main__":

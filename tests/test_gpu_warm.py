@@ -165,7 +165,13 @@ def test_zero_correction_is_the_first_cold_iterate(S):
 
 def test_trained_network_gain_small_grid():
     """Train on 64^2 fibre RVEs (the headline recipe scaled by 1/4) and compare
-    held-out iterations and effective stress with the cold start."""
+    held-out iterations and effective stress with the cold start and with the
+    Born prior alone.  This test documents the measured gain rather than
+    pinning one: the start saves the prior's iteration over the cold start,
+    and the learned correction adds no measurable gain over the prior (held-
+    out means within 0.1 iteration; the analysis is in the design notes), so
+    the assertions are that the network start beats the cold start and is
+    not worse than the prior."""
     import torch
     from paper_2103_10203_amd import warm
     mor = _mor()
@@ -190,7 +196,8 @@ def test_trained_network_gain_small_grid():
     print(f"mean iterations: cold {cold.iterations.mean():.3f} born {born.iterations.mean():.3f} "
           f"network {hot.iterations.mean():.3f}; held-out correction error "
           f"{warm.relative_error(net, held):.3f}")
-    assert hot.iterations.mean() < cold.iterations.mean()
+    assert hot.iterations.mean() < cold.iterations.mean() - 0.5
+    assert hot.iterations.mean() <= born.iterations.mean() + 0.1
     rel = np.max(np.abs(hot.eff_stress - cold.eff_stress)) / np.max(np.abs(cold.eff_stress))
     assert rel < 2e-5
 
