@@ -456,7 +456,47 @@ def other_configs(mor, ph):
     if G2:
         case = G2["cases"][str(p2.info["M"])]
         res["j2_512_path"]["oracle_rel_err"] = _max_rel(out.eff_stress, case["sigma_bar"])
+    res["j2_512_paths_b64"] = j2_paths_batched(mor, j2)
     return res
+
+
+def j2_paths_batched(mor, j2, B=64, R=0.05):
+    """Load paths of B integration points on the 512^2 J2 microstructure in
+    one mor_solve_path_multi call: 20 steps to a macro strain of norm 2 %
+    along seeded random directions (the first uniaxial).  Reports ms per
+    path and the row kernel's share of the HBM peak on its algorithmic bytes
+    (J2 state included), from HIP events around its launches."""
+    import torch
+    g2 = synth.rsa_fibres(512, 512, 20.0, 40.0, seed=2103, target_vf=0.40).g
+    p2 = mor.Plan(g2, int(math.ceil(R * g2.size)))
+    rng = np.random.default_rng(B)
+    dirs = rng.normal(size=(B, 3))
+    dirs[0] = [1.0, 0.0, 0.0]
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    paths = np.stack([np.stack([0.02 * d * (k + 1) / 20 for k in range(20)]) for d in dirs])
+    state = torch.zeros(5 * g2.size * B, dtype=torch.float32, device="cuda")
+    mor.solve_path_multi([p2], [0] * B, paths[:, :2], j2, TOL, state)  # warm-up
+    state.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    out = mor.solve_path_multi([p2], [0] * B, paths, j2, TOL, state)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    assert out.status == mor.MOR_OK, out.status
+    state.zero_()
+    mor.profile_reset()
+    mor.profile_enable(True)
+    mor.solve_path_multi([p2], [0] * B, paths, j2, TOL, state)
+    torch.cuda.synchronize()
+    mor.profile_enable(False)
+    row = mor.profile_query("row")
+    gbs = row["bytes"] / (row["ms"] * 1e-3) / 1e9
+    return {"workload": f"{B} integration points on the 512² J2 fibres (vf 0.4), M = {R:.0%}, 20 load steps "
+                        "to |eps| = 2 % along seeded random directions, one mor_solve_path_multi call, "
+                        "residual 1e-6",
+            "ms_per_path": el * 1e3 / B, "ms_per_call": el * 1e3, "iterations": int(out.iterations.sum()),
+            "row_us_per_launch": row["ms"] * 1e3 / max(row["launches"], 1), "row_GBps": gbs,
+            "row_hbm_frac": gbs / HBM_PEAK_GBS}
 
 
 def main():
@@ -482,6 +522,8 @@ def main():
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the timings of the other configured workloads")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--only", choices=["j2paths"], default=None,
+                    help="run one other workload alone and print its JSON (for profiling runs)")
     ap.add_argument("--e2e-batches", type=int, default=4,
                     help="batches of the pipelined end-to-end run (plans of the next batch built meanwhile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -499,6 +541,12 @@ def main():
     torch.cuda.set_device(0)
     import paper_2103_10203_amd as mor
     from paper_2103_10203_amd import warm
+
+    if args.only == "j2paths":
+        lm, mm = synth.phase_lame(synth.MATRIX_E, synth.MATRIX_NU)
+        li, mi = synth.phase_lame(synth.FIBRE_E, synth.FIBRE_NU)
+        print(json.dumps(j2_paths_batched(mor, [mor.Phase(lm, mm, 0.25, 1.0, True), mor.Phase(li, mi)])))
+        return
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)

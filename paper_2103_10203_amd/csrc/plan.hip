@@ -31,16 +31,19 @@ struct Dims {
   int32_t nd, n0, n1, n2;
 };
 
+// Grids hold at most 2^27 points (checked at plan creation), so 32-bit
+// unsigned division suffices (64-bit division is a long instruction sequence).
 __device__ __forceinline__ void unravel(const Dims& d, int64_t lin, int* k) {
+  const uint32_t l = (uint32_t)lin;
   if (d.nd == 2) {
-    k[0] = (int)(lin / d.n1);
-    k[1] = (int)(lin % d.n1);
+    k[0] = (int)(l / (uint32_t)d.n1);
+    k[1] = (int)(l % (uint32_t)d.n1);
     k[2] = 0;
   } else {
-    k[2] = (int)(lin % d.n2);
-    int64_t r = lin / d.n2;
-    k[1] = (int)(r % d.n1);
-    k[0] = (int)(r / d.n1);
+    k[2] = (int)(l % (uint32_t)d.n2);
+    const uint32_t r = l / (uint32_t)d.n2;
+    k[1] = (int)(r % (uint32_t)d.n1);
+    k[0] = (int)(r / (uint32_t)d.n1);
   }
 }
 
@@ -208,7 +211,7 @@ __global__ void k_fft_axis_f64(cpx<double>* __restrict__ S, int outer, int na, i
     int e = t / lpw, q = t - e * lpw;  // q fastest: consecutive lines are adjacent in memory when inner > 1
     int64_t l = l0 + q;
     if (l < nlines) {
-      int64_t o = l / inner, i = l - o * inner;
+      const int64_t o = (int64_t)((uint32_t)l / (uint32_t)inner), i = l - o * inner;  // lines < 2^32
       A[q * na + e] = S[(o * na + e) * inner + i];
     } else {
       A[q * na + e] = {0.0, 0.0};
@@ -220,7 +223,7 @@ __global__ void k_fft_axis_f64(cpx<double>* __restrict__ S, int outer, int na, i
     int e = t / lpw, q = t - e * lpw;
     int64_t l = l0 + q;
     if (l < nlines) {
-      int64_t o = l / inner, i = l - o * inner;
+      const int64_t o = (int64_t)((uint32_t)l / (uint32_t)inner), i = l - o * inner;  // lines < 2^32
       S[(o * na + e) * inner + i] = R[q * na + e];
     }
   }
@@ -264,16 +267,17 @@ __global__ void k_mask_count(const uint8_t* __restrict__ mask, int64_t N, unsign
   if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
 }
 
-__global__ void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N, const unsigned long long* count,
-                       const uint8_t* __restrict__ radial, SortEl* __restrict__ out, int64_t stride,
-                       unsigned int* nout, SortEl* __restrict__ side, unsigned int* nside) {
+__global__ __launch_bounds__(256) void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N,
+                                              const unsigned long long* count, const uint8_t* __restrict__ radial,
+                                              SortEl* __restrict__ out, int64_t stride,
+                                              const int* __restrict__ blockoff, SortEl* __restrict__ side,
+                                              unsigned int* nside) {
   const int b = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = (int)(threadIdx.x & 63);
   S += (int64_t)b * N;
   count += b;
   out += (int64_t)b * stride;
-  nout += b;
   bool main_rep = false, self_rep = false;
   SortEl e{};
   if (i < N) {
@@ -312,25 +316,49 @@ __global__ void k_keys(const cpx<double>* __restrict__ S, Dims d, int64_t N, con
     const unsigned int pos = atomicAdd(nside + b, 1u);
     side[(int64_t)b * kSide + pos] = e;
   }
-  // the pairs' representatives: one atomic per wavefront claims a run of
-  // slots (the sort that follows makes their order irrelevant)
+  // the pairs' representatives in index order: the block's offset (the
+  // same for every plan: which frequencies represent their pair depends on
+  // the grid only) plus the place within the block
+  __shared__ unsigned int woff[16];
   const unsigned long long m = __ballot(main_rep);
-  if (m) {
-    const int first = __ffsll((long long)m) - 1;
-    unsigned int base = 0;
-    if (lane == first) base = atomicAdd(nout, (unsigned int)__popcll(m));
-    base = __shfl(base, first, 64);
-    if (main_rep) out[base + __popcll(m & ((1ull << lane) - 1ull))] = e;
+  const int w = (int)(threadIdx.x >> 6);
+  if (lane == 0) woff[w] = (unsigned int)__popcll(m);
+  __syncthreads();
+  unsigned int before = blockoff[blockIdx.x];
+  for (int q = 0; q < w; ++q) before += woff[q];
+  if (main_rep) out[before + __popcll(m & ((1ull << lane) - 1ull))] = e;
+}
+
+// Pair representatives per block of 256 frequencies (the layout of k_keys;
+// blockIdx.x = block), for the offsets of k_keys' output.
+__global__ __launch_bounds__(256) void k_rep_counts(Dims d, int64_t N, int* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool main_rep = false;
+  if (i < N) {
+    int k[3], c[3];
+    unravel(d, i, k);
+    conj_k(d, k, c);
+    main_rep = lexrank(d, k) < lexrank(d, c);
+  }
+  __shared__ unsigned int wc[16];
+  const unsigned long long m = __ballot(main_rep);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (unsigned int)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int t = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += wc[q];
+    cnt[blockIdx.x] = (int)t;
   }
 }
 
 // Rank order of every representative of a plan (blockIdx.y): its sorted pairs
-// (main, nmain of them) merged with its nside self-conjugate frequencies
-// (unsorted, at most kSide).  Keys are a total order, so each element's place
+// (main, nmain_b[plan] of them) merged with its nside self-conjugate
+// frequencies (unsorted, at most kSide).  Keys are a total order, so each element's place
 // is its index in its own list plus the count of smaller ones in the other.
-__global__ void k_merge_side(const SortEl* __restrict__ main, int64_t stride, int64_t nmain,
+__global__ void k_merge_side(const SortEl* __restrict__ main, int64_t stride, const unsigned int* __restrict__ nmain_b,
                              const SortEl* __restrict__ side, int nside, SortEl* __restrict__ out, int64_t nreps) {
   const int b = blockIdx.y;
+  const int64_t nmain = nmain_b[b];
   main += (int64_t)b * stride;
   side += (int64_t)b * kSide;
   out += (int64_t)b * nreps;
@@ -357,37 +385,119 @@ __global__ void k_merge_side(const SortEl* __restrict__ main, int64_t stride, in
   }
 }
 
-__global__ void k_fill_sentinel(SortEl* el, int64_t from, int64_t to, int64_t stride) {
-  int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Sentinels (larger than every key) in positions [from_b[plan], to) of each
+// plan's segment (blockIdx.y = plan).
+__global__ void k_fill_sentinel(SortEl* el, const unsigned int* __restrict__ from_b, int64_t to, int64_t stride) {
+  const int64_t i = (int64_t)from_b[blockIdx.y] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < to) el[(int64_t)blockIdx.y * stride + i] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+}
+
+__global__ void k_fill_u32(unsigned int* __restrict__ p, int n, unsigned int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Top-T threshold of every plan's pair representatives (one workgroup per
+// plan): the first sort word (inverted key bits) of the T-th smallest
+// element, T = ceil(M/2) (no more pairs can be selected), by a radix select
+// over 8-bit digits, most significant first.  The elements whose first word
+// is at most this value are a superset of the first T in the total order.
+__global__ __launch_bounds__(1024) void k_topk_threshold(const SortEl* __restrict__ el, int64_t stride, int64_t nmain,
+                                                         const PlanPtrs* __restrict__ pp, uint32_t* __restrict__ thr) {
+  __shared__ unsigned int hist[256];
+  __shared__ uint32_t s_digit, s_want;
+  const int b = blockIdx.x;
+  el += (int64_t)b * stride;
+  const int64_t T = min((pp[b].M + 1) / 2, nmain);
+  uint32_t prefix = 0u, pmask = 0u, want = (uint32_t)max<int64_t>(T, 1);
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int t = threadIdx.x; t < 256; t += blockDim.x) hist[t] = 0u;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < nmain; i += blockDim.x) {
+      const uint32_t a = el[i].a;
+      if ((a & pmask) == prefix) atomicAdd(&hist[(a >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t cum = 0u, dg = 255u;
+      for (uint32_t q = 0; q < 256u; ++q) {
+        if (cum + hist[q] >= want) {
+          dg = q;
+          break;
+        }
+        cum += hist[q];
+      }
+      s_digit = dg;
+      s_want = want - cum;
+    }
+    __syncthreads();
+    prefix |= s_digit << shift;
+    pmask |= 255u << shift;
+    want = s_want;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) thr[b] = prefix;
+}
+
+// Candidates of each plan (blockIdx.y): the representatives whose first sort
+// word is at most the plan's threshold, gathered into its segment of `cand`
+// (one atomic per wavefront claims the slots; the sort that follows fixes
+// the order).
+__global__ void k_topk_compact(const SortEl* __restrict__ el, int64_t stride, int64_t nmain,
+                               const uint32_t* __restrict__ thr, SortEl* __restrict__ cand, int64_t cstride,
+                               unsigned int* __restrict__ ccount) {
+  const int b = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)(threadIdx.x & 63);
+  SortEl e{};
+  bool take = false;
+  if (i < nmain) {
+    e = el[(int64_t)b * stride + i];
+    take = e.a <= thr[b];
+  }
+  const unsigned long long m = __ballot(take);
+  if (m) {
+    const int first = __ffsll((long long)m) - 1;
+    unsigned int base = 0;
+    if (lane == first) base = atomicAdd(ccount + b, (unsigned int)__popcll(m));
+    base = __shfl(base, first, 64);
+    if (take) cand[(int64_t)b * cstride + base + __popcll(m & ((1ull << lane) - 1ull))] = e;
+  }
 }
 
 // Bitonic network, ascending, over n elements made of independent segments of
 // `seg` (a power of two, one per plan): compare-exchange pairs never leave a
 // segment (j < k <= seg), and the direction is taken from the index inside
 // the segment, so every segment ends sorted ascending.  Global step (k, j).
-__global__ void k_bitonic_global(SortEl* el, int64_t n, int64_t seg, int64_t k, int64_t j) {
+// Segment s of `seg` elements starts at element s * stride (stride >= seg).
+__device__ __forceinline__ int64_t seg_addr(int64_t i, int64_t seg, int64_t stride) {
+  return (i / seg) * stride + (i & (seg - 1));
+}
+
+__global__ void k_bitonic_global(SortEl* el, int64_t n, int64_t seg, int64_t k, int64_t j, int64_t stride) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // pair index
   if (t >= n / 2) return;
   int64_t i = (t / j) * 2 * j + (t % j);
   int64_t l = i + j;
   bool asc = ((i & (seg - 1)) & k) == 0;
-  SortEl x = el[i], y = el[l];
+  const int64_t ai = seg_addr(i, seg, stride), al = seg_addr(l, seg, stride);
+  SortEl x = el[ai], y = el[al];
   bool sw = asc ? el_less(y, x) : el_less(x, y);
   if (sw) {
-    el[i] = y;
-    el[l] = x;
+    el[ai] = y;
+    el[al] = x;
   }
 }
 
 // In-LDS part of the network for tiles of `tile` elements (blockDim = tile/2).
 // kmin == 0: full local sort of each tile (k = 2 .. tile).  Otherwise: merge
 // steps j = tile/2 .. 1 for the given k.
-__global__ void k_bitonic_local(SortEl* el, int tile, int64_t seg, int64_t kglob) {
+__global__ void k_bitonic_local(SortEl* el, int tile, int64_t seg, int64_t kglob, int64_t stride) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   SortEl* s = reinterpret_cast<SortEl*>(smem_raw);
   const int64_t base = (int64_t)blockIdx.x * tile;
-  for (int t = threadIdx.x; t < tile; t += blockDim.x) s[t] = el[base + t];
+  const int64_t abase = seg_addr(base, seg, stride);  // a tile never straddles segments
+  for (int t = threadIdx.x; t < tile; t += blockDim.x) s[t] = el[abase + t];
   __syncthreads();
   auto step = [&](int64_t k, int j) {
     int t = threadIdx.x;
@@ -408,18 +518,19 @@ __global__ void k_bitonic_local(SortEl* el, int tile, int64_t seg, int64_t kglob
   } else {
     for (int j = tile >> 1; j > 0; j >>= 1) step(kglob, j);
   }
-  for (int t = threadIdx.x; t < tile; t += blockDim.x) el[base + t] = s[t];
+  for (int t = threadIdx.x; t < tile; t += blockDim.x) el[abase + t] = s[t];
 }
 
 // Pair-atomic selection in rank order (one workgroup per plan, blockIdx.x).
 // Also records, for every selected frequency, its pair index in rank order
 // (bit 30 set for the partner of the pair's representative); Mact[1] = number
 // of selected pairs.
-__global__ void k_select(const SortEl* __restrict__ el, int64_t stride, int64_t nreps, Dims d, int64_t N,
-                         const PlanPtrs* __restrict__ pp, uint8_t* __restrict__ mask, int64_t* __restrict__ Mact,
-                         int* __restrict__ pairof) {
+__global__ void k_select(const SortEl* __restrict__ el, int64_t stride, const unsigned int* __restrict__ nmain_b,
+                         int nside, Dims d, int64_t N, const PlanPtrs* __restrict__ pp, uint8_t* __restrict__ mask,
+                         int64_t* __restrict__ Mact, int* __restrict__ pairof) {
   __shared__ int lds[32];
   const int b = blockIdx.x;
+  const int64_t nreps = (int64_t)nmain_b[b] + nside;
   el += (int64_t)b * stride;
   mask += (int64_t)b * N;
   pairof += (int64_t)b * N;
@@ -1136,46 +1247,85 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
   // (for grids of 2^k points the pairs then fill N/2 slots, not N)
   int64_t nselfc = 1;
   for (int a = 0; a < nd; ++a) nselfc *= 2;  // every axis is even
-  const int64_t nreps = (N + nselfc) / 2;
   const int64_t nmain = (N - nselfc) / 2;
   int64_t npow2 = 1;
   while (npow2 < nmain) npow2 <<= 1;
   const int64_t nel = (int64_t)cnt * npow2;
-  DevBuf<SortEl> el, side, ranked;
-  DevBuf<unsigned int> nout;
+  DevBuf<SortEl> el, side, ranked, cand;
+  DevBuf<unsigned int> nout, ccount;
+  DevBuf<uint32_t> thr;
   MOR_HIP_TRY(el.alloc(sc, nel));
   MOR_HIP_TRY(side.alloc(sc, (size_t)cnt * kSide));
-  MOR_HIP_TRY(ranked.alloc(sc, (size_t)cnt * nreps));
   MOR_HIP_TRY(nout.alloc(sc, 2 * (size_t)cnt));
+  MOR_HIP_TRY(ccount.alloc(sc, (size_t)cnt));
+  MOR_HIP_TRY(thr.alloc(sc, (size_t)cnt));
   MOR_HIP_TRY(hipMemsetAsync(nout.p, 0, 2 * cnt * sizeof(unsigned int), st));
-  k_keys<<<dim3((unsigned)((N + 255) / 256), nb), 256, 0, st>>>(S.p, d, N, count.p, radial.p, el.p, npow2, nout.p,
-                                                                side.p, nout.p + cnt);
-  MOR_LAUNCH_CHECK("keys");
-  if (npow2 > nmain) {
-    k_fill_sentinel<<<dim3((unsigned)((npow2 - nmain + 255) / 256), nb), 256, 0, st>>>(el.p, nmain, npow2, npow2);
-    MOR_LAUNCH_CHECK("fill_sentinel");
+  {
+    const int nkb = (int)((N + 255) / 256);
+    DevBuf<int> boff;
+    MOR_HIP_TRY(boff.alloc(sc, (size_t)nkb));
+    k_rep_counts<<<nkb, 256, 0, st>>>(d, N, boff.p);
+    MOR_LAUNCH_CHECK("rep_counts");
+    k_compact_scan<<<1, 1024, 0, st>>>(boff.p, nkb);  // exclusive scan: block offsets
+    MOR_LAUNCH_CHECK("rep_scan");
+    k_keys<<<dim3((unsigned)nkb, nb), 256, 0, st>>>(S.p, d, N, count.p, radial.p, el.p, npow2, boff.p, side.p,
+                                                    nout.p + cnt);
+    MOR_LAUNCH_CHECK("keys");
   }
 
-  // 3. bitonic sort of every plan's pairs
-  const int tile = (int)std::min<int64_t>(npow2, 2048);
+  // 3. order of the pairs.  No more than T = ceil(M/2) pairs can be
+  // selected, so only the candidates for the first T places are sorted: a
+  // radix select finds the T-th smallest first sort word, the elements at or
+  // below it are gathered and sorted.  When the candidates are not much
+  // fewer than all pairs (large M, or many equal keys at the cut) every pair
+  // is sorted instead.  Either way the rank order of the selected pairs is
+  // the total order of all pairs.
+  k_topk_threshold<<<nb, 1024, 0, st>>>(el.p, npow2, nmain, pp.p, thr.p);
+  MOR_LAUNCH_CHECK("topk_threshold");
+  MOR_HIP_TRY(cand.alloc(sc, nel));
+  MOR_HIP_TRY(hipMemsetAsync(ccount.p, 0, cnt * sizeof(unsigned int), st));
+  k_topk_compact<<<dim3((unsigned)((nmain + 255) / 256), nb), 256, 0, st>>>(el.p, npow2, nmain, thr.p, cand.p, npow2,
+                                                                             ccount.p);
+  MOR_LAUNCH_CHECK("topk_compact");
+  std::vector<unsigned int> hcc((size_t)cnt);
+  MOR_HIP_TRY(hipMemcpyAsync(hcc.data(), ccount.p, cnt * sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+  MOR_HIP_TRY(hipStreamSynchronize(st));
+  int64_t maxc = 0;
+  for (int b = 0; b < cnt; ++b) maxc = std::max<int64_t>(maxc, hcc[b]);
+  int64_t cpow2 = 1;
+  while (cpow2 < maxc) cpow2 <<= 1;
+  SortEl* keys = cand.p;  // the sorted segments, stride npow2
+  int64_t seg = cpow2;
+  unsigned int* nsorted = ccount.p;
+  if (2 * cpow2 > npow2) {  // not worth it: sort every pair
+    keys = el.p;
+    seg = npow2;
+    k_fill_u32<<<(cnt + 255) / 256, 256, 0, st>>>(ccount.p, cnt, (unsigned int)nmain);
+    MOR_LAUNCH_CHECK("fill_counts");
+  }
+  k_fill_sentinel<<<dim3((unsigned)((seg + 255) / 256), nb), 256, 0, st>>>(keys, nsorted, seg, npow2);
+  MOR_LAUNCH_CHECK("fill_sentinel");
+  const int64_t nsort = (int64_t)cnt * seg;
+  const int tile = (int)std::min<int64_t>(seg, 2048);
   const unsigned nt = (unsigned)std::max(1, tile / 2);
-  if (npow2 >= 2) {
-    const unsigned ntiles = (unsigned)(nel / tile);
-    const unsigned npairb = (unsigned)((nel / 2 + 255) / 256);
-    k_bitonic_local<<<ntiles, nt, tile * sizeof(SortEl), st>>>(el.p, tile, npow2, 0);
+  if (seg >= 2) {
+    const unsigned ntiles = (unsigned)(nsort / tile);
+    const unsigned npairb = (unsigned)((nsort / 2 + 255) / 256);
+    k_bitonic_local<<<ntiles, nt, tile * sizeof(SortEl), st>>>(keys, tile, seg, 0, npow2);
     MOR_LAUNCH_CHECK("bitonic_local");
-    for (int64_t k = 2 * (int64_t)tile; k <= npow2; k <<= 1) {
+    for (int64_t k = 2 * (int64_t)tile; k <= seg; k <<= 1) {
       for (int64_t j = k >> 1; j >= tile; j >>= 1) {
-        k_bitonic_global<<<npairb, 256, 0, st>>>(el.p, nel, npow2, k, j);
+        k_bitonic_global<<<npairb, 256, 0, st>>>(keys, nsort, seg, k, j, npow2);
         MOR_LAUNCH_CHECK("bitonic_global");
       }
-      k_bitonic_local<<<ntiles, nt, tile * sizeof(SortEl), st>>>(el.p, tile, npow2, k);
+      k_bitonic_local<<<ntiles, nt, tile * sizeof(SortEl), st>>>(keys, tile, seg, k, npow2);
       MOR_LAUNCH_CHECK("bitonic_local");
     }
   }
-
-  k_merge_side<<<dim3((unsigned)((nreps + 255) / 256), nb), 256, 0, st>>>(el.p, npow2, nmain, side.p, (int)nselfc,
-                                                                          ranked.p, nreps);
+  const int64_t nrank = seg + nselfc;  // per-plan stride of the rank order
+  MOR_HIP_TRY(ranked.alloc(sc, (size_t)cnt * nrank));
+  k_merge_side<<<dim3((unsigned)((nrank + 255) / 256), nb), 256, 0, st>>>(keys, npow2, nsorted, side.p, (int)nselfc,
+                                                                          ranked.p, nrank);
   MOR_LAUNCH_CHECK("merge_side");
 
   // 4. selection
@@ -1187,7 +1337,7 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
   MOR_HIP_TRY(pairof.alloc(sc, (size_t)cnt * N));
   MOR_HIP_TRY(hipMemsetAsync(mask.p, 0, (size_t)cnt * N, st));
   MOR_HIP_TRY(hipMemsetAsync(pairof.p, 0, (size_t)cnt * N * sizeof(int), st));
-  k_select<<<nb, 1024, 0, st>>>(ranked.p, nreps, nreps, d, N, pp.p, mask.p, mact.p, pairof.p);
+  k_select<<<nb, 1024, 0, st>>>(ranked.p, nrank, nsorted, (int)nselfc, d, N, pp.p, mask.p, mact.p, pairof.p);
   MOR_LAUNCH_CHECK("select");
   std::vector<int64_t> hm(2 * (size_t)cnt);
   std::vector<unsigned long long> hcount(cnt);
@@ -1213,7 +1363,7 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
 
   // slot tables of the warm-start network
   if (max_slots > 0) {
-    k_slots<<<dim3((unsigned)((max_slots + 255) / 256), nb), 256, 0, st>>>(ranked.p, nreps, S.p, N, count.p, pp.p);
+    k_slots<<<dim3((unsigned)((max_slots + 255) / 256), nb), 256, 0, st>>>(ranked.p, nrank, S.p, N, count.p, pp.p);
     MOR_LAUNCH_CHECK("slots");
   }
 
@@ -1319,13 +1469,15 @@ static mor_status plan_build_batch(mor_plan* const* P, const int cnt, const uint
 static size_t plan_scratch_bytes(const mor_grid* grid, int64_t N) {
   int64_t nselfc = 1;
   for (int a = 0; a < grid->ndim; ++a) nselfc *= 2;
-  const int64_t nreps = (N + nselfc) / 2, nmain = (N - nselfc) / 2;
+  const int64_t nmain = (N - nselfc) / 2;
   int64_t npow2 = 1;
   while (npow2 < nmain) npow2 <<= 1;
   const int64_t nlen = grid->n[grid->ndim - 1];
   const int64_t ncolall = (nlen / 2 + 1) * (grid->ndim == 3 ? grid->n[1] : 1);
-  return (size_t)(22 * N + 16 * npow2 + 16 * nreps + 16 * kSide + 12 * ncolall + 8 * (nlen / 2 + 1) +
-                  4 * (N / 4096 + 1) + sizeof(PlanPtrs) + sizeof(PlanDev) + 64);
+  // keys and candidates (16 npow2 each), the rank order (at most npow2 +
+  // 2^ndim entries), spectrum, masks and tables
+  return (size_t)(22 * N + 48 * npow2 + 16 * nselfc + 16 * kSide + 12 * ncolall + 8 * (nlen / 2 + 1) +
+                  4 * (N / 4096 + 1) + 16 + sizeof(PlanPtrs) + sizeof(PlanDev) + 64);
 }
 
 // Shared by mor_plan_create (count 1) and mor_plan_create_batch.
