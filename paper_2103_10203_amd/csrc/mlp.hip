@@ -128,10 +128,13 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 // C[m][n] = act(sum_k A[m][k] Bt[n][k] + bias[n]) with A bf16 [M][Kp] and Bt
 // bf16 [N][Kp] (K padded with zeros to a multiple of 32), FP32 accumulation
 // on v_mfma_f32_32x32x8_bf16.  Workgroup = 4 wavefronts on a 128 x 128
-// output tile (2 x 2 wavefronts of 64 x 64, each 2 x 2 MFMA blocks); K is
-// staged 32 at a time through LDS, the next stage's global loads issued
-// before the current stage's MFMAs.  Output FP32 or bf16.
-constexpr int MM_T = 128, MM_K = 32, MM_LD = MM_K + 8;
+// output tile (2 x 2 wavefronts of 64 x 64, each 2 x 2 MFMA blocks).  K is
+// staged 128 at a time through LDS, the next stage's global loads issued
+// before the current stage's MFMAs: at the inference batch (1024 rows) the
+// grid is small, and a stage of 64 MFMAs per wavefront is what it takes to
+// cover the load latency of the next one.  A last, partial stage reads zeros
+// past Kp.  Output FP32 or bf16.
+constexpr int MM_T = 128, MM_K = 128, MM_LD = MM_K + 8;
 
 template <int EPI, bool OUT_BF16>
 __global__ __launch_bounds__(256) void k_mm_bf16(int M, int N, int Kp, const unsigned short* __restrict__ A,
@@ -142,21 +145,25 @@ __global__ __launch_bounds__(256) void k_mm_bf16(int M, int N, int Kp, const uns
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int wm = (wave / 2) * 64, wn = (wave % 2) * 64;
   const int m0 = blockIdx.y * MM_T, n0 = blockIdx.x * MM_T;
-  // staging: thread t moves 16 bf16 (two 16-byte vectors) of A and of B:
-  // row t / 2, k half (t % 2) * 16
-  const int srow = tid / 2, sk = (tid % 2) * 16;
+  // staging: thread t moves 64 bf16 (eight 16-byte vectors) of A and of B:
+  // row t / 2, k half (t % 2) * 64
+  constexpr int SV = MM_K / 16;  // vectors per thread and matrix
+  const int srow = tid / 2, sk = (tid % 2) * (MM_K / 2);
   const bool a_ok = m0 + srow < M, b_ok = n0 + srow < N;
   const uint4* ag = reinterpret_cast<const uint4*>(A + (int64_t)(m0 + srow) * Kp + sk);
   const uint4* bg = reinterpret_cast<const uint4*>(Bt + (int64_t)(n0 + srow) * Kp + sk);
-  uint4 ra[2], rb[2];
+  uint4 ra[SV], rb[SV];
   const uint4 z = {0u, 0u, 0u, 0u};
-  auto fetch = [&](int k0) {
-    const int o = k0 / 8;  // uint4 = 8 bf16
-    ra[0] = a_ok ? ag[o] : z;
-    ra[1] = a_ok ? ag[o + 1] : z;
-    rb[0] = b_ok ? bg[o] : z;
-    rb[1] = b_ok ? bg[o + 1] : z;
-  };
+#define MM_FETCH(K0)                                                    \
+  _Pragma("unroll") for (int q = 0; q < SV; ++q) {                      \
+    /* Kp is a multiple of 8: a vector lies wholly inside or outside K */ \
+    const bool kin = (K0) + sk + 8 * q < Kp;                            \
+    /* plain branches, not ?: (which would select between addresses) */ \
+    ra[q] = z;                                                          \
+    rb[q] = z;                                                          \
+    if (a_ok && kin) ra[q] = ag[(K0) / 8 + q];                          \
+    if (b_ok && kin) rb[q] = bg[(K0) / 8 + q];                          \
+  }
   f32x16 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -164,15 +171,18 @@ __global__ __launch_bounds__(256) void k_mm_bf16(int M, int N, int Kp, const uns
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-  fetch(0);
+  MM_FETCH(0)
   for (int k0 = 0; k0 < Kp; k0 += MM_K) {
     __syncthreads();  // previous stage's fragment reads are done
-    *reinterpret_cast<uint4*>(&As[srow][sk]) = ra[0];
-    *reinterpret_cast<uint4*>(&As[srow][sk + 8]) = ra[1];
-    *reinterpret_cast<uint4*>(&Bs[srow][sk]) = rb[0];
-    *reinterpret_cast<uint4*>(&Bs[srow][sk + 8]) = rb[1];
+#pragma unroll
+    for (int q = 0; q < SV; ++q) {
+      *reinterpret_cast<uint4*>(&As[srow][sk + 8 * q]) = ra[q];
+      *reinterpret_cast<uint4*>(&Bs[srow][sk + 8 * q]) = rb[q];
+    }
     __syncthreads();
-    if (k0 + MM_K < Kp) fetch(k0 + MM_K);
+    if (k0 + MM_K < Kp) {
+      MM_FETCH(k0 + MM_K)
+    }
     const int r = lane % 32, kq = (lane / 32) * 4;
 #pragma unroll
     for (int ks = 0; ks < MM_K; ks += 8) {
@@ -188,6 +198,7 @@ __global__ __launch_bounds__(256) void k_mm_bf16(int M, int N, int Kp, const uns
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
+#undef MM_FETCH
   // D layout (32x32 block): lane -> column lane % 32; element e -> row
   // (e / 4) * 8 + (lane / 32) * 4 + e % 4
 #pragma unroll
