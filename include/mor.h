@@ -232,7 +232,8 @@ typedef struct {
  * (denominator 1 if eps_bar = 0); r is evaluated in FP64 from the
  * coefficients (Parseval).  Then sigma(eps_final) and its FP64 grid mean.
  *
- *   macro_strain host double [B][ncomp].
+ *   macro_strain host double [B][ncomp], B >= 1 (an empty batch is
+ *                rejected with MOR_E_INVALID_ARG before any device work).
  *   phase        host [2].
  *   tol > 0.
  * Returns MOR_E_NOT_CONVERGED (outputs = last iterate) if an RVE hits

@@ -91,6 +91,29 @@ def test_invalid_solve_arguments():
         assert ei.value.status == mor.MOR_E_INVALID_ARG
 
 
+def test_empty_batch_rejected():
+    """B = 0 is an argument error at every batched entry point; the library
+    stays usable afterwards."""
+    import torch
+    import paper_2103_10203_amd as mor
+    plan = _plan(mor, n=32, seed=606)
+    ph = native_phases()
+    empty = np.zeros((0, 3))
+    calls = [lambda: mor.solve(plan, empty, ph, 1e-6),
+             lambda: mor.solve(plan, empty, ph, 1e-6, noalloc=True),
+             lambda: mor.solve_multi([plan], np.zeros(0, dtype=np.int64), empty, ph, 1e-6)]
+    for call in calls:
+        with pytest.raises(mor.MorError) as ei:
+            call()
+        assert ei.value.status == mor.MOR_E_INVALID_ARG
+    state = torch.zeros(0, dtype=torch.float32, device="cuda")
+    with pytest.raises((mor.MorError, ValueError)):
+        mor.solve_path_multi([plan], np.zeros(0, dtype=np.int64), np.zeros((0, 2, 3)), native_phases(j2=True),
+                             1e-6, state)
+    out = mor.solve(plan, np.array([[1e-3, 0.0, 0.0]]), ph, 1e-6)
+    assert out.status == mor.MOR_OK
+
+
 def test_overflow_reports_nonfinite():
     import paper_2103_10203_amd as mor
     plan = _plan(mor, seed=605)

@@ -374,3 +374,22 @@ def test_ragged_row_tiles(shape):
             assert rel_l2(out.strain[0].cpu().numpy(), e_ref) < 1e-4, v
     finally:
         mor.tune_set(2, n1, keep)
+
+
+@pytest.mark.parametrize("shape,R", [((4, 4), 0.5), ((6, 1024), 0.05), ((1024, 6), 0.05), ((4, 96), 0.2),
+                                     ((1024, 1024), 0.005)])
+def test_extreme_grid_shapes(shape, R):
+    """The smallest and largest grids the plan accepts (every n even,
+    2^a 3^b, 4..1024) and the most elongated ones, against the oracle."""
+    rng = np.random.default_rng(sum(shape))
+    if shape == (1024, 1024):
+        g = synth.rsa_fibres(1024, 1024, 32.0, 64.0, seed=1024, target_vf=0.35).g
+    else:
+        # a smooth two-phase map, so the pattern keeps meaningful frequencies
+        x = np.linspace(0.0, 2.0 * np.pi, shape[0], endpoint=False)[:, None]
+        y = np.linspace(0.0, 2.0 * np.pi, shape[1], endpoint=False)[None, :]
+        f = np.sin(x + rng.uniform(0, 6)) + np.cos(2 * y + rng.uniform(0, 6)) + 0.3 * rng.standard_normal(shape)
+        g = (f > 0.2).astype(np.uint8)
+    assert 0 < g.sum() < g.size
+    M = max(1, int(math.ceil(R * g.size)))
+    _check_against_oracle(g, [1.5e-3, -5e-4, 8e-4], M, check_fields=True, iters=shape != (1024, 1024))
