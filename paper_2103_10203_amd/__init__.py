@@ -12,5 +12,5 @@ from ._native import (  # noqa: F401
     TRANSFORM_AUTO, TRANSFORM_FFT, TRANSFORM_DFT,
     MOR_OK, MOR_E_INVALID_ARG, MOR_E_NOT_CONVERGED, MOR_E_NONFINITE, MOR_E_UNSUPPORTED,
     MLP, MLP_FP32, MLP_BF16, warm_features, warm_targets, warm_apply,
-    KERNEL_ROW, KERNEL_COL, SCHED_GRID, SCHED_PERSISTENT, tune_variants, tune_get, tune_set, autotune,
+    KERNEL_ROW, KERNEL_COL, SCHED_GRID, SCHED_PERSISTENT, tune_variants, tune_get, tune_set, tune_subbatch, autotune,
 )

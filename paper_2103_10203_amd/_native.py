@@ -126,6 +126,7 @@ _SIGS = {
     "mor_tune_variants": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "mor_tune_get": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "mor_tune_set": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32]),
+    "mor_tune_subbatch": (ct.c_int, [ct.c_int64, ct.POINTER(ct.c_int64)]),
     "mor_autotune": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p,
                                 ct.c_double, ct.c_int32, ct.c_void_p]),
     "mor_last_error": (ct.c_char_p, []),
@@ -692,6 +693,14 @@ def tune_get(ndim: int, length: int, kernel: int = KERNEL_ROW) -> int:
 
 def tune_set(ndim: int, length: int, variant: int, kernel: int = KERNEL_ROW) -> None:
     _check(lib.mor_tune_set(kernel, ndim, length, variant))
+
+
+def tune_subbatch(nbytes: int = -1) -> int:
+    """Set the sub-batch limit of the batched solves (bytes of transform
+    lines; 0 = one sub-batch per grid; -1 = query only); returns the old value."""
+    prev = ct.c_int64()
+    _check(lib.mor_tune_subbatch(int(nbytes), ct.byref(prev)))
+    return prev.value
 
 
 def autotune(plans, plan_of, macro_strain, phases, tol: float, reps: int = 2, stream=None) -> None:

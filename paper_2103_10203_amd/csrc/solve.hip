@@ -5,8 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -858,6 +860,23 @@ std::vector<RveState> fresh_states(const SolveCtx& cx, const std::vector<mor_pla
   return hs;
 }
 
+// Working-set limit of one sub-batch (bytes of transform lines): MI355X's
+// 256 MB Infinity Cache less room for the coefficients, tables and phase
+// maps the passes also stream.  MOR_SUBBATCH_MIB in the environment sets the
+// start value, mor_tune_subbatch changes it (0: one sub-batch per grid).
+std::atomic<int64_t>& subbatch_limit() {
+  static std::atomic<int64_t> v{[] {
+    if (const char* e = getenv("MOR_SUBBATCH_MIB")) {
+      char* end = nullptr;
+      const long long m = strtoll(e, &end, 10);
+      if (end != e && m >= 0 && m < (1LL << 40)) return (int64_t)m << 20;
+    }
+    return (int64_t)192 << 20;
+  }()};
+  return v;
+}
+size_t subbatch_bytes() { return (size_t)subbatch_limit().load(); }
+
 // Prepare the context: plan table, groups, offsets, states.
 mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::vector<int>& plan_of,
                  const double* ebar, int64_t B, const mor_phase* phase, double tol, const mor_solve_opts* opts,
@@ -960,6 +979,43 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
     }
     g.xb = g.ndim == 3 ? cols_per_block(cx.C, g.n1, es) : 1;
     if (!g.fast_row && !cx.dft) g.rb = std::min(g.rb, rows);
+  }
+  // Sub-batches: a group's RVEs are cut into runs whose transform lines fit
+  // in the device's last-level cache, and the iteration loop runs the chunk
+  // of iterations of one sub-batch before the next, so the lines the row
+  // pass writes are still cached when the column pass reads them and vice
+  // versa (a batch of 1024 256^2 RVEs streams 350 MB of lines per pass).
+  {
+    const size_t limit = subbatch_bytes();
+    const size_t es = cx.fp64 ? sizeof(cpx<double>) : sizeof(cpx<float>);
+    std::vector<Group> split;
+    for (const Group& g : cx.groups) {
+      std::vector<size_t> yb(g.rves.size());
+      size_t total = 0;
+      for (size_t q = 0; q < g.rves.size(); ++q) {
+        const mor_plan* p = plans[plan_of[g.rves[q]]];
+        yb[q] = (size_t)cx.C * p->dev.nlast * p->dev.rows * es;
+        if (cx.ndim == 3) yb[q] += (size_t)cx.C * p->dev.ncol * p->n[0] * es;
+        total += yb[q];
+      }
+      // as few sub-batches as the limit allows, of about equal size (cut
+      // where the running sum passes the next multiple of total / parts)
+      const size_t parts = limit > 0 ? std::max<size_t>(1, (total + limit - 1) / limit) : 1;
+      Group cur = g;
+      cur.rves.clear();
+      size_t run = 0, cut = 1;
+      for (size_t q = 0; q < g.rves.size(); ++q) {
+        if (cut < parts && !cur.rves.empty() && (long double)run >= (long double)total * cut / parts) {
+          split.push_back(cur);
+          cur.rves.clear();
+          ++cut;
+        }
+        cur.rves.push_back(g.rves[q]);
+        run += yb[q];
+      }
+      split.push_back(cur);
+    }
+    cx.groups.swap(split);
   }
   std::vector<int> gof(B);
   for (size_t gi = 0; gi < cx.groups.size(); ++gi)
@@ -1080,8 +1136,8 @@ struct GraphChunk {
     mor_status s = MOR_OK;
     hipError_t e = hipStreamBeginCapture(cx.st, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      for (int k = 0; k < check && s == MOR_OK; ++k)
-        for (auto& g : cx.groups)
+      for (auto& g : cx.groups)
+        for (int k = 0; k < check && s == MOR_OK; ++k)
           if ((s = do_iter(cx, g)) != MOR_OK) break;
       hipError_t e2 = hipStreamEndCapture(cx.st, &graph);
       if (e2 != hipSuccess && s == MOR_OK) e = e2;
@@ -1126,8 +1182,9 @@ mor_status run(SolveCtx& cx, const cpx<float>* warm, const mor_solve_opts* opts,
     if (gc.exec) {
       MOR_HIP_TRY(hipGraphLaunch(gc.exec, cx.st));
     } else {
-      for (int k = 0; k < check; ++k)
-        for (auto& g : cx.groups)
+      // sub-batch outermost: its lines stay cached across its iterations
+      for (auto& g : cx.groups)
+        for (int k = 0; k < check; ++k)
           if ((s = do_iter(cx, g)) != MOR_OK) return s;
     }
     done += check;
@@ -1781,6 +1838,16 @@ extern "C" mor_status mor_tune_set(int32_t kernel, int32_t ndim, int32_t length,
 // batched solves of the given workload with each variant (the other sizes
 // keep their current choice) and keep the fastest.  The workload's results
 // are discarded; the tuned choice applies to later solves in this process.
+extern "C" mor_status mor_tune_subbatch(int64_t bytes, int64_t* previous) {
+  if (bytes < -1) {
+    mor_set_error("mor_tune_subbatch: bytes must be >= 0 (or -1 to query)");
+    return MOR_E_INVALID_ARG;
+  }
+  const int64_t old = bytes < 0 ? subbatch_limit().load() : subbatch_limit().exchange(bytes);
+  if (previous) *previous = old;
+  return MOR_OK;
+}
+
 extern "C" mor_status mor_autotune(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of_rve,
                                    const double* macro_strain_packed, int64_t B, const mor_phase phase[2],
                                    double tol, int32_t reps, void* stream) {

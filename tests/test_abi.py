@@ -126,6 +126,13 @@ def test_tune_api_host_side():
         mor.tune_variants(2, 100, mor.KERNEL_COL)
     with pytest.raises(mor.MorError):
         mor.tune_variants(2, 256, 7)
+    # sub-batch limit: query, set, restore, reject
+    start = mor.tune_subbatch()
+    assert start >= 0 and mor.tune_subbatch() == start
+    assert mor.tune_subbatch(1 << 20) == start
+    assert mor.tune_subbatch(start) == 1 << 20
+    with pytest.raises(mor.MorError):
+        mor.tune_subbatch(-2)
 
 
 def test_precision_constants_match_header():

@@ -393,3 +393,61 @@ def test_extreme_grid_shapes(shape, R):
     assert 0 < g.sum() < g.size
     M = max(1, int(math.ceil(R * g.size)))
     _check_against_oracle(g, [1.5e-3, -5e-4, 8e-4], M, check_fields=True, iters=shape != (1024, 1024))
+
+
+def test_subbatches_match_one_batch():
+    """Cutting the batch into cache-sized sub-batches (iterated one after the
+    other) changes no result: uneven grids with different iteration counts,
+    fields, 3D, the persistent schedule, hipGraph replay and batched J2 paths,
+    each bit for bit against the same call with the limit off; the split
+    runs also match the oracle."""
+    import torch
+    mor = _mor()
+    gs = [synth.fibre_rve_256(90 + i, n).g for i, n in enumerate((64, 128, 256, 128, 64))]
+    Ms = [int(math.ceil(0.05 * g.size)) for g in gs]
+    plans = [mor.Plan(g, M) for g, M in zip(gs, Ms)]
+    po = np.array([0, 1, 2, 3, 4, 2, 1, 0, 3, 2, 2])
+    ebs = synth.macro_strains(len(po), 3, 5e-3, seed=23)
+    ebs[4] = 0.0  # converges at once
+    g3 = synth.rsa_spheres(16, 32, 64, r_lo=3.0, r_hi=5.0, seed=5, target_vf=0.2).g
+    p3 = mor.Plan(g3, int(math.ceil(0.03 * g3.size)))
+    e3 = synth.macro_strains(4, 6, 1e-3, seed=3)
+    g2 = synth.rsa_fibres(64, 64, 5.0, 10.0, seed=76, target_vf=0.4).g
+    plan2 = mor.Plan(g2, 205)
+    paths = np.stack([np.stack([[0.004 * k * (1 + r), -0.001 * k, 0.0] for k in range(1, 4)]) for r in range(5)])
+
+    def run_all():
+        res = {"multi": mor.solve_multi(plans, po, ebs, native_phases(), 1e-6, want_fields=True),
+               "pers": mor.solve_multi(plans, po, ebs, native_phases(), 1e-6, schedule=mor.SCHED_PERSISTENT),
+               "graph": mor.solve_multi(plans, po, ebs, native_phases(), 1e-6, use_graph=1),
+               "3d": mor.solve(p3, e3, native_phases(), 1e-6)}
+        state = torch.zeros(5 * 5 * g2.size, dtype=torch.float32, device="cuda")
+        res["j2"] = mor.solve_path_multi([plan2], np.zeros(5, dtype=np.int64), paths, native_phases(j2=True), 1e-6,
+                                         state)
+        res["j2state"] = state.cpu().numpy()
+        return res
+
+    keep = mor.tune_subbatch(0)
+    try:
+        whole = run_all()
+        mor.tune_subbatch(1)  # every RVE its own sub-batch
+        ones = run_all()
+        mor.tune_subbatch(600 << 10)  # a few RVEs per sub-batch
+        some = run_all()
+    finally:
+        mor.tune_subbatch(keep)
+    for split in (ones, some):
+        for key in ("multi", "pers", "graph", "3d", "j2"):
+            assert np.array_equal(split[key].eff_stress, whole[key].eff_stress), key
+            assert np.array_equal(split[key].iterations, whole[key].iterations), key
+        assert bool(torch.equal(split["multi"].strain, whole["multi"].strain))
+        assert bool(torch.equal(split["multi"].stress, whole["multi"].stress))
+        assert np.array_equal(split["j2state"], whole["j2state"])
+    assert len(set(whole["multi"].iterations.tolist())) > 1
+    for b in (0, 2, 4):
+        _, ref = oracle_reduced(gs[po[b]], list(ebs[b]), Ms[po[b]], tol=1e-12)
+        sref = stress_comps(ref.sigma_bar, 2)
+        if np.max(np.abs(sref)) > 0:
+            assert np.max(np.abs(ones["multi"].eff_stress[b] - sref)) / np.max(np.abs(sref)) < 1e-5
+        else:
+            assert np.max(np.abs(ones["multi"].eff_stress[b])) == 0.0
