@@ -26,6 +26,7 @@ the FP64 CPU oracle on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -61,6 +62,20 @@ def workload(count, workers=8):
     gs = [g for g, _ in items]
     ebs = np.stack([e for _, e in items])
     return gs, ebs
+
+
+def settle_heap():
+    """Collect the Python heap and exempt what is left from later
+    collections: the workload, training and evaluation stages leave millions
+    of long-lived objects, and a full collection over them (tens of ms) must
+    not land inside a timed region."""
+    gc.collect()
+    gc.freeze()
+
+
+def itstats(it):
+    return {"mean": float(np.mean(it)), "p50": float(np.percentile(it, 50)),
+            "p95": float(np.percentile(it, 95)), "max": int(np.max(it))}
 
 
 def phases():
@@ -261,6 +276,7 @@ def end_to_end_pipelined(mor, gs, ebs, ph, batch, s_plan, warm_fn=None):
             q.put(None)
 
     keep = []
+    marks = []
     po = np.arange(batch)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -276,13 +292,14 @@ def end_to_end_pipelined(mor, gs, ebs, ph, batch, s_plan, warm_fn=None):
             out = mor.solve_multi(plans, po, eb, ph, TOL, warm_start=w, stream=s_solve, **SOLVE_KW)
             assert out.status == mor.MOR_OK, out.status
             keep.append(plans)  # released after the timed region (destroying a plan drains the device)
+            marks.append(time.perf_counter() - t)
     th.join()
     torch.cuda.synchronize()
     el = time.perf_counter() - t
     if err:
         raise err[0]
     del keep
-    return nb * batch / el, nb
+    return nb * batch / el, nb, [round(1e3 * (b - a), 2) for a, b in zip([0.0] + marks[:-1], marks)]
 
 
 def timed_single(mor, plans, ebs, ph, count, warm_fn=None, use_graph=0):
@@ -587,6 +604,7 @@ def main():
     plan_of = np.arange(B)
 
     # cold start, batched
+    settle_heap()
     cold, el_cold, kern_cold = timed_batched(mor, plans, plan_of, ebs, ph, args.steps, args.warmup)
     cold_rate = B * args.steps / el_cold
     log(f"cold batched: {cold_rate:.0f} solves/s, mean iterations {cold.iterations.mean():.2f}")
@@ -602,12 +620,33 @@ def main():
     if args.train > 0:
         net, tinfo = train_network(mor, ph, args.train, S, args.epochs, log)
         warm_fn = lambda: warm.predict_warm(net, plans, plan_of, ebs, ph, S)  # noqa: E731
+        settle_heap()
         hot, el_hot, kern_hot = timed_batched(mor, plans, plan_of, ebs, ph, args.steps, args.warmup, warm_fn)
         hot_rate = B * args.steps / el_hot
         log(f"learned batched: {hot_rate:.0f} solves/s, mean iterations {hot.iterations.mean():.2f}")
         dstress = float(np.max(np.abs(hot.eff_stress - cold.eff_stress)) / np.max(np.abs(cold.eff_stress)))
         learned = {"rate": hot_rate, "elapsed": el_hot, "kern": kern_hot, "out": hot, "train": tinfo,
                    "eff_stress_rel_diff_vs_cold": dstress}
+
+    # iterations on 2 batches of held-out RVEs (the timed batch and the next
+    # one): cold, prior alone and learned start on the same microstructures
+    heldout = None
+    if learned is not None:
+        gs_n, ebs_n = workload(2 * B)
+        gs_n, ebs_n = gs_n[B:], ebs_n[B:]
+        plans_n = mor.make_plans(gs_n, M_FREQ)
+        its = {"cold": [cold.iterations], "born_prior": [born.iterations], "learned": [learned["out"].iterations]}
+        starts = {"cold": None,
+                  "born_prior": lambda: warm.born_warm(plans_n, plan_of, ebs_n, ph, S),
+                  "learned": lambda: warm.predict_warm(net, plans_n, plan_of, ebs_n, ph, S)}
+        for key, fn in starts.items():
+            o = mor.solve_multi(plans_n, plan_of, ebs_n, ph, TOL, warm_start=fn() if fn else None, **SOLVE_KW)
+            assert o.status == mor.MOR_OK, o.status
+            its[key].append(o.iterations)
+        heldout = {"rves": 2 * B, "iterations": {k: itstats(np.concatenate(v)) for k, v in its.items()}}
+        del plans_n, gs_n, ebs_n
+        log(f"held-out {2 * B}: mean iterations cold {heldout['iterations']['cold']['mean']:.3f}, "
+            f"learned {heldout['iterations']['learned']['mean']:.3f}")
 
     # end to end: plan construction of the next batch overlapped with the solve
     # of the current one (second stream, second host thread)
@@ -618,9 +657,10 @@ def main():
         if learned is not None:
             wf = lambda pl, po_, eb: warm.predict_warm(net, pl, po_, eb, ph, S)  # noqa: E731
         s_plan = torch.cuda.Stream()
+        settle_heap()
         end_to_end_pipelined(mor, gs_e[:2 * B], ebs_e[:2 * B], ph, B, s_plan, wf)  # warm-up: buffers, pools
-        rate, nbat = end_to_end_pipelined(mor, gs_e, ebs_e, ph, B, s_plan, wf)
-        e2e_pipe = {"solves_per_s": rate, "batches": nbat, "batch": B,
+        rate, nbat, bms = end_to_end_pipelined(mor, gs_e, ebs_e, ph, B, s_plan, wf)
+        e2e_pipe = {"solves_per_s": rate, "batches": nbat, "batch": B, "batch_done_ms": bms,
                     "note": "plans of batch k+1 built on a second stream from a second host thread while batch "
                             "k is solved (learned start when trained); first batch's plans not overlapped"}
         del gs_e, ebs_e
@@ -698,10 +738,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def itstats(it):
-        return {"mean": float(np.mean(it)), "p50": float(np.percentile(it, 50)),
-                "p95": float(np.percentile(it, 95)), "max": int(np.max(it))}
-
     start_desc = ("learned warm start (Born prior + MLP correction, BF16 MFMA inference inside the timed step)"
                   if start == "learned" else "cold start")
     line = {
@@ -752,6 +788,7 @@ def main():
             "born_prior": itstats(born.iterations),
             "learned": itstats(learned["out"].iterations) if learned else None,
         },
+        "heldout_iterations": heldout,
         "plan_ms_per_rve": plan_ms,
         "plan_ms_per_rve_single_calls": plan_ms_seq,
         "end_to_end_solves_per_s": 1.0 / (1.0 / value + plan_ms * 1e-3),

@@ -25,7 +25,7 @@ LM, MM = synth.phase_lame(synth.MATRIX_E, synth.MATRIX_NU)
 LI, MI = synth.phase_lame(synth.FIBRE_E, synth.FIBRE_NU)
 PH = (material.Phase(LM, MM), material.Phase(LI, MI))
 PH_J2 = (material.Phase(LM, MM, sigma_y0=0.25, H=1.0, plastic=True), material.Phase(LI, MI))
-NSAMPLE = 256
+NSAMPLE = 4096
 
 
 def sample_points(shape, seed):
@@ -58,12 +58,16 @@ def _c2_case(R):
     M = int(math.ceil(R * g.size))
     p = pattern.build_pattern(g, M)
     t = time.perf_counter()
-    steps = solver.solve_path(g, PH_J2, solver.macro_tensor([0.02, 0.0, 0.0], 2), 20, mask=p.mask(), tol=1e-8)
+    steps = solver.solve_path(g, PH_J2, solver.macro_tensor([0.02, 0.0, 0.0], 2), 20, mask=p.mask(), tol=1e-10,
+                              max_iter=5000)
     sig = [solver.tensor_comps(s.sigma_bar, 2, with_s33=True).tolist() for s in steps]
     alpha = steps[-1].alpha.reshape(-1)
+    ep11 = steps[-1].eps_p[..., 0, 0].reshape(-1)
     print(f"c2 M={M}: {time.perf_counter() - t:.0f} s, iterations {[s.iterations for s in steps]}", flush=True)
     return str(M), {"R": R, "M": M, "sigma_bar": sig, "alpha_sample": alpha[pts].tolist(),
-                    "alpha_mean": float(alpha.mean()), "alpha_max": float(alpha.max())}
+                    "eps_p11_sample": ep11[pts].tolist(),
+                    "alpha_mean": float(alpha.mean()), "alpha_max": float(alpha.max()),
+                    "plastic_count": int(np.count_nonzero(alpha > 0.0))}
 
 
 def make_c2():
@@ -73,8 +77,9 @@ def make_c2():
     from concurrent.futures import ProcessPoolExecutor
     g = c2_geometry()
     res = {"recipe": "synth.rsa_fibres(512, 512, 20, 40, seed=2103, target_vf=0.40); J2 matrix sigma_y0 0.25 GPa, "
-                     "H 1 GPa; 20 equal steps to eps_11 = 0.02; oracle tol 1e-8",
+                     "H 1 GPa; 20 equal steps to eps_11 = 0.02; oracle tol 1e-10",
            "cite": "Sec. 2 (J2 plasticity), Sec. 4 steps a-d, Sec. 5.2 (load steps)",
+           "oracle_tol": 1e-10,
            "vf": float(g.mean()), "sample_points": sample_points(g.shape, 77).tolist(), "cases": {}}
     with ProcessPoolExecutor(max_workers=3) as ex:
         for key, case in ex.map(_c2_case, (0.01, 0.05, 0.20)):
@@ -110,12 +115,12 @@ def make_c4():
     M = int(math.ceil(0.02 * g.size))
     p = pattern.build_pattern(g, M)
     t = time.perf_counter()
-    r = solver.solve(g, PH, solver.macro_tensor(eb, 3), mask=p.mask(), tol=1e-9)
+    r = solver.solve(g, PH, solver.macro_tensor(eb, 3), mask=p.mask(), tol=1e-10, max_iter=5000)
     pts = sample_points(g.shape, 78)
     eps = solver.tensor_comps(r.eps, 3).reshape(-1, 6)
     print(f"c4: {time.perf_counter() - t:.0f} s, {r.iterations} iterations", flush=True)
     return {"recipe": "synth.rsa_spheres(128, 128, 128, 8, 14, seed=7, target_vf=0.25); macro strain "
-                      "synth.macro_strains(1, 6, 1e-3, seed=4); M = ceil(0.02 N); oracle tol 1e-9",
+                      "synth.macro_strains(1, 6, 1e-3, seed=4); M = ceil(0.02 N); oracle tol 1e-10",
             "cite": "Sec. 4 steps a-d, 3D", "vf": float(g.mean()), "M": M, "macro_strain": eb.tolist(),
             "sigma_bar": solver.tensor_comps(r.sigma_bar, 3, with_s33=True).tolist(),
             "sample_points": pts.tolist(), "eps_sample": eps[pts].tolist()}
@@ -128,5 +133,6 @@ if __name__ == "__main__":
     for name in names:
         data = MAKERS[name]()
         with open(os.path.join(HERE, name + ".json"), "w") as fh:
-            json.dump(data, fh, indent=1)
+            json.dump(data, fh, separators=(",", ":"))
+            fh.write("\n")
         print("wrote", name, flush=True)

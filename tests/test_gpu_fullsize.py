@@ -50,8 +50,9 @@ def test_c3_uneven_batch_4096_against_effective_stiffness():
     assert out.status == mor.MOR_OK
     C = [np.array(grid["C_eff"]) for grid in G["grids"]]
     want = np.stack([C[po[b]] @ ebs[b] for b in range(B)])
-    err = np.max(np.abs(out.eff_stress - want)) / np.max(np.abs(want))
-    assert err < 1e-5, err
+    # every RVE against its own largest stress component
+    err = np.max(np.abs(out.eff_stress[:, :4] - want), axis=1) / np.max(np.abs(want), axis=1)
+    assert np.max(err) < 1e-5, (int(np.argmax(err)), float(np.max(err)))
 
 
 @pytest.mark.parametrize("path", ["fft", "dft_fp32", "dft_bf16x3"])
@@ -77,6 +78,11 @@ def test_c4_128cube(path):
 
 @pytest.mark.parametrize("R", [0.01, 0.05, 0.20])
 def test_c2_j2_512_load_path(R):
+    """The J2 iteration contracts slowly (hundreds of iterations per step), so
+    its stopping error is about a hundred times the residual: the fields are
+    compared after solving to 3e-7 (measured: accumulated plastic strain
+    2e-5 to 3e-5 from the oracle's fixed point, against 4e-5 to 1.0e-4 at
+    1e-6); the effective stresses meet 1e-5 either way."""
     import torch
     import paper_2103_10203_amd as mor
     G = _golden("c2_j2_512")
@@ -87,7 +93,7 @@ def test_c2_j2_512_load_path(R):
     plan = mor.Plan(g, M)
     path = np.stack([[0.02 * (k + 1) / 20, 0.0, 0.0] for k in range(20)])
     state = torch.zeros(5 * g.size, dtype=torch.float32, device="cuda")
-    out = mor.solve_path(plan, path, native_phases(j2=True), 1e-6, state)
+    out = mor.solve_path(plan, path, native_phases(j2=True), 3e-7, state)
     assert out.status == mor.MOR_OK
     want = np.array(case["sigma_bar"])
     for k in range(20):
@@ -98,3 +104,8 @@ def test_c2_j2_512_load_path(R):
     assert case["alpha_max"] > 0.0
     assert _rel_l2(alpha[pts], case["alpha_sample"]) < 1e-4
     assert abs(alpha.mean() - case["alpha_mean"]) < 1e-5 * case["alpha_mean"]
+    if "eps_p11_sample" in case:
+        ep = state.view(5, -1)[0].double().cpu().numpy()
+        assert _rel_l2(ep[pts], case["eps_p11_sample"]) < 1e-4
+    if "plastic_count" in case:
+        assert abs(int(np.count_nonzero(alpha > 0.0)) - case["plastic_count"]) <= 0.001 * g.size
