@@ -493,7 +493,6 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ int coff[CB + 1];
   __shared__ double cwt[CB];  // Parseval weight of each column of the block (1 or 2)
-  __shared__ uint32_t pmask[CB][N0 / 32];  // pattern frequencies k0 of each column of the block
   if (MODE == MODE_ITER && !st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
   const int ncol = P.ncol;
@@ -506,7 +505,6 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
   cpx<float>* buf = tw + pad16(N0 - 1) + 1;
   for (int t = tid; t < N0; t += NT) tw[pad16(t)] = P.tw0[t];
   if (tid <= CB) coff[tid] = P.col_off[j0 + min(tid, ncb)];
-  for (int t = tid; t < CB * (N0 / 32); t += NT) (&pmask[0][0])[t] = 0u;
   if (MODE == MODE_ITER && tid < ncb) {
     const int kl = P.last_k[P.col_last[j0 + tid]];
     cwt[tid] = (kl == 0 || 2 * kl == P.nlen) ? 1.0 : 2.0;
@@ -551,15 +549,17 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
     __syncthreads();
   }
   // step c): Green operator on the block's pattern entries.  A thread
-  // handles at most EPT entries.  Only the thread of an entry reads its
-  // positions of tau^, so it overwrites them in place with the new
-  // coefficients; the positions outside the pattern are cleared afterwards
-  // (the entries mark theirs in pmask).
+  // handles at most EPT entries and keeps their new coefficients in
+  // registers; once every entry has read tau^, the whole buffer is cleared
+  // (unconditional stores) and the entries write their coefficients.
   constexpr int EPT = (CB * N0 + NT - 1) / NT;
   const float invN = P.inv_N;
   double dsum = 0.0;
+  int kpos[EPT];
+  float kre[EPT][C], kim[EPT][C];
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
+    kpos[u] = -1;
     const int e = ebeg + tid + u * NT;
     if (e >= eend) continue;
     int jj = 0;
@@ -626,16 +626,16 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
       }
       dsum += wcol * d2;
     }
-    const int pos = jj * SS + pad16(k0);
+    kpos[u] = jj * SS + pad16(k0);
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       co[(int64_t)c * ncoef + e] = {nr_[c], ni_[c]};
-      buf[c * CB * SS + pos] = {nr_[c] * invN, ni_[c] * invN};
+      kre[u][c] = nr_[c] * invN;
+      kim[u][c] = ni_[c] * invN;
     }
-    atomicOr(&pmask[jj][k0 >> 5], 1u << (k0 & 31));
   }
-  __syncthreads();  // the pattern marks are complete
-  // clear the other positions of every sequence (pad slots are never read):
+  __syncthreads();  // every entry has read its tau^
+  // clear every position of every sequence (pad slots are never read):
   // thread (s, i) of the transform takes positions i + m TS of its sequence,
   // so the offsets are compile-time strides from one per-thread base
   {
@@ -643,12 +643,15 @@ __device__ __forceinline__ void col_tile(const PlanDev* __restrict__ plans, cons
     const int t2 = opaque_tid();
     const int s2 = t2 / TS, i2 = t2 % TS;
     cpx<float>* seqb = buf + s2 * SS;
-    const uint32_t* pm = pmask[s2 % CB];
 #pragma unroll
-    for (int m = 0; m < RF; ++m) {
-      const int k = i2 + m * TS;
-      if (!((pm[k >> 5] >> (k & 31)) & 1u)) seqb[pad16(k)] = {0.f, 0.f};
-    }
+    for (int m = 0; m < RF; ++m) seqb[pad16(i2 + m * TS)] = {0.f, 0.f};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    if (kpos[u] < 0) continue;
+#pragma unroll
+    for (int c = 0; c < C; ++c) buf[c * CB * SS + kpos[u]] = {kre[u][c], kim[u][c]};
   }
   __syncthreads();
   // step d), axis 0: inverse passes, the last one straight to global memory
