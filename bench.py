@@ -660,7 +660,11 @@ def main():
         settle_heap()
         end_to_end_pipelined(mor, gs_e[:2 * B], ebs_e[:2 * B], ph, B, s_plan, wf)  # warm-up: buffers, pools
         rate, nbat, bms = end_to_end_pipelined(mor, gs_e, ebs_e, ph, B, s_plan, wf)
+        steady = (B * (len(bms) - 2) / (sum(bms[2:]) * 1e-3)) if len(bms) > 2 else None
         e2e_pipe = {"solves_per_s": rate, "batches": nbat, "batch": B, "batch_done_ms": bms,
+                    "steady_solves_per_s": steady,
+                    "steady_note": "batches after the first two (the pipeline is full: plans of the next batch "
+                                   "overlap the solve of this one)",
                     "note": "plans of batch k+1 built on a second stream from a second host thread while batch "
                             "k is solved (learned start when trained); first batch's plans not overlapped"}
         del gs_e, ebs_e
