@@ -460,15 +460,17 @@ enum { MOR_KERNEL_ROW = 0, MOR_KERNEL_COL = 1 };
 mor_status mor_tune_variants(int32_t kernel, int32_t ndim, int32_t length, int32_t* count);
 mor_status mor_tune_get(int32_t kernel, int32_t ndim, int32_t length, int32_t* variant);
 mor_status mor_tune_set(int32_t kernel, int32_t ndim, int32_t length, int32_t variant);
-/* Sub-batch limit of the batched solves: the RVEs of one grid are cut into
- * runs of at most `bytes` of transform lines (at least one RVE each), and the
- * iteration loop runs each run's chunk of iterations before the next, so the
- * lines stay in the last-level cache between the row and column passes.
- * Results do not depend on it (every RVE iterates on its own).  Default
- * 192 MiB (MOR_SUBBATCH_MIB in the environment, in MiB, sets the start
- * value); 0 keeps each grid's RVEs together; -1 only queries.  *previous
- * (may be NULL) receives the value before the call.  Process-wide. */
-mor_status mor_tune_subbatch(int64_t bytes, int64_t* previous);
+/* Sub-batches of the batched solves: the RVEs of one grid are cut into the
+ * fewest runs of about equal size whose transform lines fit `bytes`, but
+ * into no runs of fewer than `min_rves` RVEs, and the iteration loop runs
+ * each run's chunk of iterations before the next, so the lines stay in the
+ * last-level cache between the row and column passes.  Results do not
+ * depend on the cut (every RVE iterates on its own).  Defaults: 192 MiB
+ * (MOR_SUBBATCH_MIB in the environment, in MiB, sets the start value) and
+ * 128 RVEs; bytes = 0 keeps each grid's RVEs together; -1 keeps a value.
+ * *prev_bytes, *prev_min (may be NULL) receive the values before the call.
+ * Process-wide. */
+mor_status mor_tune_subbatch(int64_t bytes, int64_t min_rves, int64_t* prev_bytes, int64_t* prev_min);
 /* Autotuner: for every row and column length present among `plans`, runs the batched
  * solve (mor_solve_multi arguments) once untimed and `reps` times timed with
  * each variant, keeps the fastest (minimum wall time) and leaves it selected.

@@ -126,7 +126,7 @@ _SIGS = {
     "mor_tune_variants": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "mor_tune_get": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "mor_tune_set": (ct.c_int, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32]),
-    "mor_tune_subbatch": (ct.c_int, [ct.c_int64, ct.POINTER(ct.c_int64)]),
+    "mor_tune_subbatch": (ct.c_int, [ct.c_int64, ct.c_int64, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64)]),
     "mor_autotune": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p,
                                 ct.c_double, ct.c_int32, ct.c_void_p]),
     "mor_last_error": (ct.c_char_p, []),
@@ -695,12 +695,13 @@ def tune_set(ndim: int, length: int, variant: int, kernel: int = KERNEL_ROW) -> 
     _check(lib.mor_tune_set(kernel, ndim, length, variant))
 
 
-def tune_subbatch(nbytes: int = -1) -> int:
-    """Set the sub-batch limit of the batched solves (bytes of transform
-    lines; 0 = one sub-batch per grid; -1 = query only); returns the old value."""
-    prev = ct.c_int64()
-    _check(lib.mor_tune_subbatch(int(nbytes), ct.byref(prev)))
-    return prev.value
+def tune_subbatch(nbytes: int = -1, min_rves: int = -1):
+    """Set the sub-batch limits of the batched solves (bytes of transform
+    lines, 0 = one sub-batch per grid; fewest RVEs per sub-batch; -1 keeps a
+    value); returns the previous (bytes, min_rves)."""
+    pb, pm = ct.c_int64(), ct.c_int64()
+    _check(lib.mor_tune_subbatch(int(nbytes), int(min_rves), ct.byref(pb), ct.byref(pm)))
+    return pb.value, pm.value
 
 
 def autotune(plans, plan_of, macro_strain, phases, tol: float, reps: int = 2, stream=None) -> None:

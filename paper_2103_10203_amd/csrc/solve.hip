@@ -876,6 +876,13 @@ std::atomic<int64_t>& subbatch_limit() {
   return v;
 }
 size_t subbatch_bytes() { return (size_t)subbatch_limit().load(); }
+// Fewest RVEs of a sub-batch: below this the per-launch cost of the extra
+// launches outweighs the cache hits (3D RVEs of 128^3 lose 3 % when cut into
+// runs of two).
+std::atomic<int64_t>& subbatch_min_rves() {
+  static std::atomic<int64_t> v{128};
+  return v;
+}
 
 // Prepare the context: plan table, groups, offsets, states.
 mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::vector<int>& plan_of,
@@ -1000,7 +1007,10 @@ mor_status setup(SolveCtx& cx, const std::vector<mor_plan*>& plans, const std::v
       }
       // as few sub-batches as the limit allows, of about equal size (cut
       // where the running sum passes the next multiple of total / parts)
-      const size_t parts = limit > 0 ? std::max<size_t>(1, (total + limit - 1) / limit) : 1;
+      const size_t minr = (size_t)std::max<int64_t>(1, subbatch_min_rves().load());
+      const size_t parts = limit > 0 ? std::max<size_t>(1, std::min((total + limit - 1) / limit,
+                                                                    g.rves.size() / minr))
+                                     : 1;
       Group cur = g;
       cur.rves.clear();
       size_t run = 0, cut = 1;
@@ -1838,13 +1848,15 @@ extern "C" mor_status mor_tune_set(int32_t kernel, int32_t ndim, int32_t length,
 // batched solves of the given workload with each variant (the other sizes
 // keep their current choice) and keep the fastest.  The workload's results
 // are discarded; the tuned choice applies to later solves in this process.
-extern "C" mor_status mor_tune_subbatch(int64_t bytes, int64_t* previous) {
-  if (bytes < -1) {
-    mor_set_error("mor_tune_subbatch: bytes must be >= 0 (or -1 to query)");
+extern "C" mor_status mor_tune_subbatch(int64_t bytes, int64_t min_rves, int64_t* prev_bytes, int64_t* prev_min) {
+  if (bytes < -1 || min_rves < -1 || min_rves == 0) {
+    mor_set_error("mor_tune_subbatch: bytes must be >= 0 and min_rves >= 1 (or -1 to keep)");
     return MOR_E_INVALID_ARG;
   }
-  const int64_t old = bytes < 0 ? subbatch_limit().load() : subbatch_limit().exchange(bytes);
-  if (previous) *previous = old;
+  const int64_t ob = bytes < 0 ? subbatch_limit().load() : subbatch_limit().exchange(bytes);
+  const int64_t om = min_rves < 0 ? subbatch_min_rves().load() : subbatch_min_rves().exchange(min_rves);
+  if (prev_bytes) *prev_bytes = ob;
+  if (prev_min) *prev_min = om;
   return MOR_OK;
 }
 

@@ -126,13 +126,15 @@ def test_tune_api_host_side():
         mor.tune_variants(2, 100, mor.KERNEL_COL)
     with pytest.raises(mor.MorError):
         mor.tune_variants(2, 256, 7)
-    # sub-batch limit: query, set, restore, reject
+    # sub-batch limits: query, set, restore, reject
     start = mor.tune_subbatch()
-    assert start >= 0 and mor.tune_subbatch() == start
-    assert mor.tune_subbatch(1 << 20) == start
-    assert mor.tune_subbatch(start) == 1 << 20
-    with pytest.raises(mor.MorError):
-        mor.tune_subbatch(-2)
+    assert start[0] >= 0 and start[1] >= 1 and mor.tune_subbatch() == start
+    assert mor.tune_subbatch(1 << 20, 4) == start
+    assert mor.tune_subbatch(start[0], start[1]) == (1 << 20, 4)
+    assert mor.tune_subbatch(-1, -1) == start
+    for bad in ((-2, -1), (-1, 0), (-1, -2)):
+        with pytest.raises(mor.MorError):
+            mor.tune_subbatch(*bad)
 
 
 def test_precision_constants_match_header():

@@ -430,12 +430,12 @@ def test_subbatches_match_one_batch():
     keep = mor.tune_subbatch(0)
     try:
         whole = run_all()
-        mor.tune_subbatch(1)  # every RVE its own sub-batch
+        mor.tune_subbatch(1, 1)  # every RVE its own sub-batch
         ones = run_all()
-        mor.tune_subbatch(600 << 10)  # a few RVEs per sub-batch
+        mor.tune_subbatch(600 << 10, 1)  # a few RVEs per sub-batch
         some = run_all()
     finally:
-        mor.tune_subbatch(keep)
+        mor.tune_subbatch(*keep)
     for split in (ones, some):
         for key in ("multi", "pers", "graph", "3d", "j2"):
             assert np.array_equal(split[key].eff_stress, whole[key].eff_stress), key
