@@ -373,7 +373,7 @@ def other_configs(mor, ph):
     hipGraph replay), 3D 128^3 with the FFT and the split-bf16 MFMA DFT, the
     64^2 disk in FP64 to 1e-8, and the 512^2 J2 load path.  Each result
     carries its largest effective-stress difference from the FP64 oracle
-    (the oracle's fixtures, or an oracle solve of the 64^2 disk)."""
+    (from the oracle's fixtures under tests/golden)."""
     import torch
 
     def timed(fn, reps=1):
@@ -441,20 +441,11 @@ def other_configs(mor, ph):
                                "solves_per_s": 256 / el, "ms": el * 1e3,
                                "mean_iterations": float(out.iterations.mean())}
     # against the oracle's effective stiffness of the disk (linear in the macro strain)
-    from oracle import material, pattern, solver
-    lm, mm = synth.phase_lame(synth.MATRIX_E, synth.MATRIX_NU)
-    li, mi = synth.phase_lame(synth.FIBRE_E, synth.FIBRE_NU)
-    oph = (material.Phase(lm, mm), material.Phase(li, mi))
-    mask = pattern.build_pattern(g1, 205).mask()
-    cols = []
-    for k in range(3):
-        e = np.zeros(3)
-        e[k] = 1.0
-        r = solver.solve(g1, oph, solver.macro_tensor(e, 2), mask=mask, tol=1e-12, max_iter=5000)
-        cols.append(solver.tensor_comps(r.sigma_bar, 2, with_s33=True))
-    Cd = np.stack(cols, axis=1)
-    res["disk64_fp64_1e-8"]["oracle_rel_err"] = _max_rel(out.eff_stress, e1 @ Cd.T)
+    G1 = _golden("disk64_stiffness")
+    if G1:
+        res["disk64_fp64_1e-8"]["oracle_rel_err"] = _max_rel(out.eff_stress, e1 @ np.array(G1["C_eff"]).T)
     del p1
+    res["radial_vs_adapted_256"] = radial_and_compat(mor, ph, timed)
     g2 = synth.rsa_fibres(512, 512, 20.0, 40.0, seed=2103, target_vf=0.40).g
     p2 = mor.Plan(g2, int(math.ceil(0.05 * g2.size)))
     path = np.stack([[0.02 * (k + 1) / 20, 0.0, 0.0] for k in range(20)])
@@ -475,6 +466,35 @@ def other_configs(mor, ph):
         res["j2_512_path"]["oracle_rel_err"] = _max_rel(out.eff_stress, case["sigma_bar"])
     res["j2_512_paths_b64"] = j2_paths_batched(mor, j2)
     return res
+
+
+def radial_and_compat(mor, ph, timed, L=16, B=256):
+    """The fixed radial pattern of L lines (Sec. 4.1) against the adapted
+    pattern of the same size and the full set, on one 256^2 fibre
+    microstructure with B macro strains, and the compatibility step (one
+    full-set pass) from the radial solution: solves/s of each, and the
+    largest effective-stress difference from the full-set solution."""
+    g, _ = synth.metric_rve(0)
+    eb = synth.macro_strains(B, 3, 5e-3, seed=5)
+    rad = mor.Plan(g, 1, radial_lines=L)
+    ada = mor.Plan(g, rad.info["M_actual"])
+    full = mor.Plan(g, g.size)
+    el_f, out_f = timed(lambda: mor.solve(full, eb, ph, TOL))
+    el_r, out_r = timed(lambda: mor.solve(rad, eb, ph, TOL, want_coeffs=True))
+    el_a, out_a = timed(lambda: mor.solve(ada, eb, ph, TOL))
+    el_c, out_c = timed(lambda: mor.compat(rad, full, out_r.coeffs, eb, ph, want_fields=False))
+    ref = out_f.eff_stress
+    return {"workload": f"256² fibre RVE, {B} macro strains in one call, residual {TOL:g}; radial pattern of {L} "
+                        f"lines (M = {rad.info['M_actual']}, {100 * rad.info['M_actual'] / g.size:.2f} %) vs the "
+                        "adapted pattern of the same size vs the full set; compatibility step from the radial "
+                        "solution",
+            "solves_per_s": {"radial": B / el_r, "adapted": B / el_a, "full_set": B / el_f,
+                             "compat_step": B / el_c},
+            "mean_iterations": {"radial": float(out_r.iterations.mean()), "adapted": float(out_a.iterations.mean()),
+                                "full_set": float(out_f.iterations.mean())},
+            "eff_stress_rel_diff_vs_full": {"radial": _max_rel(out_r.eff_stress, ref),
+                                            "adapted": _max_rel(out_a.eff_stress, ref),
+                                            "radial_then_compat": _max_rel(out_c.eff_stress, ref)}}
 
 
 def j2_paths_batched(mor, j2, B=64, R=0.05):

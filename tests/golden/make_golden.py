@@ -4,7 +4,7 @@ This script calls only the oracle (``oracle/``) and the seeded generators
 (``synth/``); nothing here comes from the HIP path.  Each fixture states the
 workload recipe and the passage of the paper it exercises.  Usage:
 
-    python tests/golden/make_golden.py [c2_j2_512] [c3_stiffness] [c4_128]
+    python tests/golden/make_golden.py [c2_j2_512] [c3_stiffness] [c4_128] [disk64_stiffness]
 """
 import json
 import math
@@ -126,7 +126,24 @@ def make_c4():
             "sample_points": pts.tolist(), "eps_sample": eps[pts].tolist()}
 
 
-MAKERS = {"c2_j2_512": make_c2, "c3_stiffness": make_c3, "c4_128": make_c4}
+def make_disk64():
+    """Effective stiffness of the 64^2 centred disk (vf 0.3), M = 205 (Sec. 4
+    reduced scheme, linear elastic; the paper's single-inclusion example)."""
+    n = 64
+    g = synth.disk(n, n, math.sqrt(0.3 * n * n / math.pi))
+    p = pattern.build_pattern(g, 205)
+    cols = []
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1.0
+        r = solver.solve(g, PH, solver.macro_tensor(e, 2), mask=p.mask(), tol=1e-12, max_iter=5000)
+        cols.append(solver.tensor_comps(r.sigma_bar, 2, with_s33=True))
+    return {"recipe": "synth.disk(64, 64, sqrt(0.3 * 64^2 / pi)); M = 205; oracle tol 1e-12",
+            "cite": "Sec. 4 steps a-d, Sec. 5.1 (single inclusion)", "M": 205,
+            "C_eff": np.stack(cols, axis=1).tolist()}
+
+
+MAKERS = {"c2_j2_512": make_c2, "c3_stiffness": make_c3, "c4_128": make_c4, "disk64_stiffness": make_disk64}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(MAKERS)
