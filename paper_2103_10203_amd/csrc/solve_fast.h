@@ -169,6 +169,7 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
   constexpr int KH = NH / 2 + 1;
   static_assert(NT % 64 == 0, "workgroups are whole wavefronts");
   static_assert(NT % RB == 0, "row block divides the workgroup");
+  __builtin_assume(tid >= 0 && tid < NT);  // the launch has NT threads
   extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   __shared__ int lk[NH + 1];    // last-axis frequency of spectrum entry j
   __shared__ uint32_t kofs[NH + 1];  // byte offset j * rows * 8 of the entry j of last-axis frequency k,
@@ -220,7 +221,7 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
       const int t = tid + u * NT;  // t % RB == rg
-      if (GT % NT == 0 || t < GT) {
+      if (u < GT / NT || t < GT) {  // only the last, partial round checks
         const int k = t / RB;
         xa[u] = load_or_zero(rs, kofs[k] + rowb);
         xb[u] = load_or_zero(rs, kofs[NH - k] + rowb);
@@ -241,7 +242,7 @@ __device__ __forceinline__ void row_tile(const PlanDev* __restrict__ plans, cons
 #pragma unroll
     for (int u = 0; u < GU; ++u) {
       const int t = tid + u * NT;
-      if (t < GT) {
+      if (u < GT / NT || t < GT) {
         const int k = t / RB;
         cpx<float>* x = buf + rg * SS;
         const cpx<float> Xk = xa[u], Xm = xb[u];
