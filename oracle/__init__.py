@@ -14,7 +14,7 @@ wave-vector component and strains set to zero), every float is FP64, and
 steps follow the paper's order:
 
 * ``pattern``   - adapted sampling pattern: spectrum of g, top-R% amplitudes
-                  (Sec. 4.2), with the tie/pair rules fixed in the design doc.
+                  (Sec. 4.2), with the tie and pair rules stated in pattern.py.
 * ``green``     - Green operator Gamma^0 from its definition (Sec. 3, eq. Gamma),
                   continuous and rotated finite-difference wave vectors.
 * ``material``  - Hooke and J2 with linear isotropic hardening (Sec. 2).

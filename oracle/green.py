@@ -6,8 +6,8 @@ wave vector k, the acoustic tensor is K_ik = C0_ijkl k_j k_l, its inverse is
 G^_ik, and the Green operator is the symmetrised product
     Gamma^_ijkl = 1/4 (G^_jk k_l k_i + G^_ik k_l k_j + G^_jl k_k k_i + G^_il k_k k_j),
 so that eps^ = -Gamma^ : tau^ for k != 0 and eps^(0) = N * eps_bar.
-(The paper's comma notation is read as this standard form; the design doc lists the
-reading.)  Gamma^ is homogeneous of degree 0 in k, so only the unit direction
+(The paper's comma notation is read as this standard form, a reading of the
+paper's garbled index notation.)  Gamma^ is homogeneous of degree 0 in k, so only the unit direction
 n = k/|k| matters.
 
 Wave vectors (paper Sec. 3, last paragraph, first-order finite differences):

@@ -5,7 +5,7 @@ fixed radial pattern it is compared with (Sec. 4.1, fig. FixedSampling):
 straight lines through xi = 0 at equally spaced angles, independent of g.
 
 The paper is silent on ties, conjugate pairs, xi = 0, the rounding of R*N and
-floating-point noise.  The oracle fixes them as follows (listed in the design doc):
+floating-point noise.  The oracle fixes them as follows (readings, not the paper's statements):
 
 1. M = ceil(R*N) is passed in directly as an integer.
 2. P(m) = |FFT(g)(m)|^2 in FP64 (unnormalised forward DFT, e^{-2 pi i m.x/N}),

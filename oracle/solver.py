@@ -7,7 +7,7 @@ Per iteration i (all in FP64, full 3x3 tensors, unnormalised forward FFT):
   c) eps^(m) = -Gamma^(m) : tau^(m) for m in the pattern, m != 0;
      eps^(0) = N eps_bar; eps^ = 0 off the pattern,
   d) eps^{i+1} = Re iFFT(eps^).
-Convergence (readings listed in the design doc): after producing eps^{i+1},
+Convergence (a reading: the paper's loop condition and norms disagree): after producing eps^{i+1},
   r = sqrt(mean_x ||eps^{i+1} - eps^i||_F^2) / ||eps_bar||_F
 (denominator 1 if eps_bar = 0), stop at the first r < tol; the iteration count
 is the number of Green-operator applications.  Finally sigma = sigma(eps_final)
