@@ -41,44 +41,64 @@ __device__ __forceinline__ float dft_bf2f(unsigned short h) { return __uint_as_f
 
 constexpr int DFT_T = 64;   // output tile edge
 constexpr int DFT_KC = 32;  // K staged per LDS round
-constexpr int DFT_LD = DFT_KC + 4;
+constexpr int DFT_LD = DFT_KC + 4;  // FP32 staging row (floats)
+constexpr int DFT_LH = DFT_KC + 8;  // split-bf16 staging row (bf16 values, 16-byte aligned rows)
 
-// Accumulate the wave's 32x32 block over one staged K chunk.  As[m][k],
-// Bs[n][k] (k contiguous).
+// Staged operand tiles of one K chunk: FP32 for PREC_F32; for PREC_X3 every
+// value is split once, when it is staged, into its bf16 high part and the
+// bf16 rounding of the remainder (no conversions in the MFMA loop).
 template <int PREC>
-__device__ __forceinline__ void dft_mfma_chunk(const float (*As)[DFT_LD], const float (*Bs)[DFT_LD], int wm, int wn,
-                                               int lane, dft_f32x16& acc) {
-  const int r = lane % 32;
-  if (PREC == DFT_F32) {
-    const int kq = lane / 32;
+struct DftTiles;
+// Values are staged four consecutive k at a time (k a multiple of 4), so
+// every LDS store is 16 bytes (FP32) or two of 8 bytes (bf16 high and low).
+template <>
+struct DftTiles<DFT_F32> {
+  float A[DFT_T][DFT_LD], B[DFT_T][DFT_LD];
+  __device__ __forceinline__ void put_a(int m, int k, float4 v) { *reinterpret_cast<float4*>(&A[m][k]) = v; }
+  __device__ __forceinline__ void put_b(int n, int k, float4 v) { *reinterpret_cast<float4*>(&B[n][k]) = v; }
+};
+template <>
+struct DftTiles<DFT_X3> {
+  unsigned short Ah[DFT_T][DFT_LH], Al[DFT_T][DFT_LH], Bh[DFT_T][DFT_LH], Bl[DFT_T][DFT_LH];
+  __device__ __forceinline__ static void split(float4 v, unsigned short (*H)[DFT_LH], unsigned short (*Lo)[DFT_LH],
+                                               int r, int k) {
+    const float a[4] = {v.x, v.y, v.z, v.w};
+    dft_bf16x4 h, l;
 #pragma unroll
-    for (int ks = 0; ks < DFT_KC; ks += 2) {
-      const float a = As[wm + r][ks + kq];
-      const float b = Bs[wn + r][ks + kq];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) {
+      const unsigned short hi = dft_f2bf(a[i]);
+      h[i] = (short)hi;
+      l[i] = (short)dft_f2bf(a[i] - dft_bf2f(hi));
     }
-  } else {
-    const int kq = (lane / 32) * 4;
+    *reinterpret_cast<dft_bf16x4*>(&H[r][k]) = h;
+    *reinterpret_cast<dft_bf16x4*>(&Lo[r][k]) = l;
+  }
+  __device__ __forceinline__ void put_a(int m, int k, float4 v) { split(v, Ah, Al, m, k); }
+  __device__ __forceinline__ void put_b(int n, int k, float4 v) { split(v, Bh, Bl, n, k); }
+};
+
+// Accumulate the wave's 32x32 block over one staged K chunk (A[m][k],
+// B[n][k], k contiguous).
+__device__ __forceinline__ void dft_mfma_chunk(const DftTiles<DFT_F32>& t, int wm, int wn, int lane,
+                                               dft_f32x16& acc) {
+  const int r = lane % 32, kq = lane / 32;
 #pragma unroll
-    for (int ks = 0; ks < DFT_KC; ks += 8) {
-      const float4 av = *reinterpret_cast<const float4*>(&As[wm + r][ks + kq]);
-      const float4 bv = *reinterpret_cast<const float4*>(&Bs[wn + r][ks + kq]);
-      const float aa[4] = {av.x, av.y, av.z, av.w};
-      const float bb[4] = {bv.x, bv.y, bv.z, bv.w};
-      dft_bf16x4 ah, al, bh, bl;
+  for (int ks = 0; ks < DFT_KC; ks += 2)
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(t.A[wm + r][ks + kq], t.B[wn + r][ks + kq], acc, 0, 0, 0);
+}
+__device__ __forceinline__ void dft_mfma_chunk(const DftTiles<DFT_X3>& t, int wm, int wn, int lane,
+                                               dft_f32x16& acc) {
+  const int r = lane % 32, kq = (lane / 32) * 4;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const unsigned short h1 = dft_f2bf(aa[i]);
-        const unsigned short h2 = dft_f2bf(bb[i]);
-        ah[i] = (short)h1;
-        al[i] = (short)dft_f2bf(aa[i] - dft_bf2f(h1));
-        bh[i] = (short)h2;
-        bl[i] = (short)dft_f2bf(bb[i] - dft_bf2f(h2));
-      }
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc, 0, 0, 0);
-    }
+  for (int ks = 0; ks < DFT_KC; ks += 8) {
+    const dft_bf16x4 ah = *reinterpret_cast<const dft_bf16x4*>(&t.Ah[wm + r][ks + kq]);
+    const dft_bf16x4 al = *reinterpret_cast<const dft_bf16x4*>(&t.Al[wm + r][ks + kq]);
+    const dft_bf16x4 bh = *reinterpret_cast<const dft_bf16x4*>(&t.Bh[wn + r][ks + kq]);
+    const dft_bf16x4 bl = *reinterpret_cast<const dft_bf16x4*>(&t.Bl[wn + r][ks + kq]);
+    // smallest products first
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc, 0, 0, 0);
   }
 }
 
@@ -89,14 +109,20 @@ __device__ __forceinline__ void dft_tables(const PlanDev& P, cpx<float>* T, int*
   for (int t = threadIdx.x; t < nlast; t += blockDim.x) lk[t] = P.last_k[t];
 }
 
+// Twiddle index (k x) mod L for k, x < L <= 512 (the product fits 32 bits);
+// a mask when L is a power of two (uniform across the launch).
+__device__ __forceinline__ int dft_twi(int k, int x, int L) {
+  const unsigned p = (unsigned)k * (unsigned)x;
+  return (int)((L & (L - 1)) == 0 ? (p & (unsigned)(L - 1)) : p % (unsigned)L);
+}
+
 // Inverse: Yl (spectra, [C][nlast][rows]) -> E ([C*rows][L] real field).
 // grid (L / 64, C rows / 64, RVEs); LMAX >= L.
 template <int PREC, int LMAX>
 __global__ __launch_bounds__(256) void k_dft_inv(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
                                                  const RveState* __restrict__ st, const cpx<float>* __restrict__ Yl,
                                                  Offs off, float* __restrict__ E, int C, int mode_iter) {
-  __shared__ float As[DFT_T][DFT_LD];
-  __shared__ float Bs[DFT_T][DFT_LD];
+  __shared__ __attribute__((aligned(16))) DftTiles<PREC> tl;
   __shared__ cpx<float> T[LMAX];
   __shared__ int lk[LMAX / 2 + 1];
   const int b = rve_list[blockIdx.z];
@@ -114,35 +140,51 @@ __global__ __launch_bounds__(256) void k_dft_inv(const PlanDev* __restrict__ pla
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
   const int K = 2 * nlast;
+  // A: 64 rows x 16 spectrum entries (complex -> two k columns), two
+  // entries (four k columns) per item; the next chunk's entries are loaded
+  // into registers before this chunk's MFMAs
+  constexpr int AI = DFT_T * (DFT_KC / 4) / 256;
+  float4 pa[AI];
+  auto load_a = [&](int j0) {
+#pragma unroll
+    for (int q = 0; q < AI; ++q) {
+      const int t = tid + q * 256;
+      const int mm = t % DFT_T, j = j0 + 2 * (t / DFT_T);
+      cpx<float> v0 = {0.f, 0.f}, v1 = {0.f, 0.f};
+      if (j < nlast) v0 = Y[(int64_t)j * rows + mm];
+      if (j + 1 < nlast) v1 = Y[(int64_t)(j + 1) * rows + mm];
+      pa[q] = make_float4(v0.x, v0.y, v1.x, v1.y);
+    }
+  };
+  load_a(0);
   __syncthreads();
   for (int k0 = 0; k0 < K; k0 += DFT_KC) {
     const int j0 = k0 / 2;
-    // A: 64 rows x 16 spectrum entries (complex -> two k columns)
-    for (int t = tid; t < DFT_T * (DFT_KC / 2); t += 256) {
-      const int mm = t % DFT_T, jj = t / DFT_T;
-      const int j = j0 + jj;
-      cpx<float> v = {0.f, 0.f};
-      if (j < nlast) v = Y[(int64_t)j * rows + mm];
-      As[mm][2 * jj] = v.x;
-      As[mm][2 * jj + 1] = v.y;
+#pragma unroll
+    for (int q = 0; q < AI; ++q) {
+      const int t = tid + q * 256;
+      tl.put_a(t % DFT_T, 4 * (t / DFT_T), pa[q]);
     }
     // B: Binv[k][x] for x in the tile
-    for (int t = tid; t < DFT_T * (DFT_KC / 2); t += 256) {
-      const int nn = t % DFT_T, jj = t / DFT_T;
-      const int j = j0 + jj;
-      float cr = 0.f, ci = 0.f;
-      if (j < nlast) {
-        const int k = lk[j];
-        const float w = (k == 0 || 2 * k == L) ? 1.f : 2.f;
-        const cpx<float> tw = T[(int)(((int64_t)k * (n0 + nn)) % L)];
-        cr = w * tw.x;
-        ci = w * tw.y;
+    for (int t = tid; t < DFT_T * (DFT_KC / 4); t += 256) {
+      const int nn = t % DFT_T, jg = t / DFT_T;
+      float c[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int j = j0 + 2 * jg + h;
+        if (j < nlast) {
+          const int k = lk[j];
+          const float w = (k == 0 || 2 * k == L) ? 1.f : 2.f;
+          const cpx<float> tw = T[dft_twi(k, n0 + nn, L)];
+          c[2 * h] = w * tw.x;
+          c[2 * h + 1] = w * tw.y;
+        }
       }
-      Bs[nn][2 * jj] = cr;
-      Bs[nn][2 * jj + 1] = ci;
+      tl.put_b(nn, 4 * jg, make_float4(c[0], c[1], c[2], c[3]));
     }
     __syncthreads();
-    dft_mfma_chunk<PREC>(As, Bs, wm, wn, lane, acc);
+    if (k0 + DFT_KC < K) load_a(j0 + DFT_KC / 2);
+    dft_mfma_chunk(tl, wm, wn, lane, acc);
     __syncthreads();
   }
   // D layout: lane -> column n = lane % 32; element i -> row (i/4)*8 + (lane/32)*4 + i%4
@@ -161,8 +203,7 @@ template <int PREC, int LMAX>
 __global__ __launch_bounds__(256) void k_dft_fwd(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
                                                  const RveState* __restrict__ st, cpx<float>* __restrict__ Yl,
                                                  Offs off, const float* __restrict__ E, int C) {
-  __shared__ float As[DFT_T][DFT_LD];
-  __shared__ float Bs[DFT_T][DFT_LD];
+  __shared__ __attribute__((aligned(16))) DftTiles<PREC> tl;
   __shared__ cpx<float> T[LMAX];
   __shared__ int lk[LMAX / 2 + 1];
   __shared__ float Cs[DFT_T][DFT_T + 1];
@@ -180,25 +221,45 @@ __global__ __launch_bounds__(256) void k_dft_fwd(const PlanDev* __restrict__ pla
   dft_f32x16 acc;
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  // four consecutive x per item (16-byte loads; L and k0 are multiples of 32);
+  // the next chunk's items are loaded into registers before this chunk's
+  // MFMAs, so their latency overlaps the products
+  constexpr int AI = DFT_T * (DFT_KC / 4) / 256;
+  float4 pa[AI];
+  auto load_a = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < AI; ++q) {
+      const int t = tid + q * 256;
+      const int kq = (t % (DFT_KC / 4)) * 4, mm = t / (DFT_KC / 4);
+      pa[q] = *reinterpret_cast<const float4*>(&A[(int64_t)mm * L + k0 + kq]);
+    }
+  };
+  load_a(0);
   __syncthreads();
   for (int k0 = 0; k0 < L; k0 += DFT_KC) {
-    for (int t = tid; t < DFT_T * DFT_KC; t += 256) {
-      const int kk = t % DFT_KC, mm = t / DFT_KC;
-      As[mm][kk] = A[(int64_t)mm * L + k0 + kk];
+#pragma unroll
+    for (int q = 0; q < AI; ++q) {
+      const int t = tid + q * 256;
+      tl.put_a(t / (DFT_KC / 4), (t % (DFT_KC / 4)) * 4, pa[q]);
     }
     // B: Bfwd[x][n], n = 2j + p
-    for (int t = tid; t < DFT_T * DFT_KC; t += 256) {
-      const int kk = t % DFT_KC, nn = t / DFT_KC;
+    for (int t = tid; t < DFT_T * (DFT_KC / 4); t += 256) {
+      const int kq = (t % (DFT_KC / 4)) * 4, nn = t / (DFT_KC / 4);
       const int n = n0 + nn, j = n / 2;
-      float v = 0.f;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
       if (j < nlast) {
-        const cpx<float> tw = T[(int)(((int64_t)lk[j] * (k0 + kk)) % L)];
-        v = (n & 1) ? tw.y : tw.x;
+        const int k = lk[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const cpx<float> tw = T[dft_twi(k, k0 + kq + q, L)];
+          v[q] = (n & 1) ? tw.y : tw.x;
+        }
       }
-      Bs[nn][kk] = v;
+      tl.put_b(nn, kq, make_float4(v[0], v[1], v[2], v[3]));
     }
     __syncthreads();
-    dft_mfma_chunk<PREC>(As, Bs, wm, wn, lane, acc);
+    if (k0 + DFT_KC < L) load_a(k0 + DFT_KC);
+    dft_mfma_chunk(tl, wm, wn, lane, acc);
     __syncthreads();
   }
 #pragma unroll
