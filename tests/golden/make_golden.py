@@ -5,6 +5,7 @@ This script calls only the oracle (``oracle/``) and the seeded generators
 workload recipe and the passage of the paper it exercises.  Usage:
 
     python tests/golden/make_golden.py [c2_j2_512] [c3_stiffness] [c4_128] [disk64_stiffness]
+        [headline_sample]
 """
 import json
 import math
@@ -143,7 +144,35 @@ def make_disk64():
             "C_eff": np.stack(cols, axis=1).tolist()}
 
 
-MAKERS = {"c2_j2_512": make_c2, "c3_stiffness": make_c3, "c4_128": make_c4, "disk64_stiffness": make_disk64}
+HEADLINE_SAMPLE = (0, 137, 300, 511, 512, 700, 901, 1023)
+
+
+def _headline_case(i):
+    import hashlib
+    g, eb = synth.metric_rve(i)
+    p = pattern.build_pattern(g, 3277)
+    r = solver.solve(g, PH, solver.macro_tensor(eb, 2), mask=p.mask(), tol=1e-10, max_iter=5000)
+    r6 = solver.solve(g, PH, solver.macro_tensor(eb, 2), mask=p.mask(), tol=1e-6, max_iter=5000)
+    return {"index": i, "sigma_bar": solver.tensor_comps(r.sigma_bar, 2, with_s33=True).tolist(),
+            "iterations_1e-6": int(r6.iterations), "unstable": bool(p.unstable),
+            "sorted_idx_sha256": hashlib.sha256(p.sorted_idx.astype("<i8").tobytes()).hexdigest()}
+
+
+def make_headline():
+    """Sampled RVEs of the headline batch (held-out 256^2 fibre RVEs 0..1023,
+    M = 3277, Sec. 4 reduced scheme): effective stress at oracle residual
+    1e-10, the oracle's iteration count at 1e-6 and a digest of the pattern."""
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        cases = list(ex.map(_headline_case, HEADLINE_SAMPLE))
+    return {"recipe": "synth.metric_rve(i) for i in 0..1023 (256^2, seeds 1000000 + i); M = 3277; "
+                      "oracle tol 1e-10 (sigma_bar) and 1e-6 (iterations); pattern digest = sha256 of the "
+                      "sorted linear indices as little-endian int64",
+            "cite": "Sec. 4 steps a-d, Sec. 4.2 (pattern)", "M": 3277, "cases": cases}
+
+
+MAKERS = {"c2_j2_512": make_c2, "c3_stiffness": make_c3, "c4_128": make_c4, "disk64_stiffness": make_disk64,
+          "headline_sample": make_headline}
 
 if __name__ == "__main__":
     names = sys.argv[1:] or list(MAKERS)

@@ -7,7 +7,9 @@ values that `tests/golden/make_golden.py` wrote from the FP64 oracle:
 * 128³ spheres at M = 2 %: effective stress and sampled strains, for the FFT
   path, the FP32-MFMA DFT and the bf16x3 DFT;
 * 512² J2 fibres, 20 load steps to 2 %, M = 1, 5, 20 %: effective stress per
-  step and the accumulated plastic strain at sampled points.
+  step and the accumulated plastic strain at sampled points;
+* the benchmarked launch itself (1024 held-out 256² RVEs, M = 5 %, one call):
+  sampled RVEs' patterns, effective stresses and iteration counts.
 """
 import json
 import math
@@ -109,3 +111,46 @@ def test_c2_j2_512_load_path(R):
         assert _rel_l2(ep[pts], case["eps_p11_sample"]) < 1e-4
     if "plastic_count" in case:
         assert abs(int(np.count_nonzero(alpha > 0.0)) - case["plastic_count"]) <= 0.001 * g.size
+
+
+def _held_out(i):
+    return synth.metric_rve(i)
+
+
+def test_headline_batch_launch_configuration():
+    """The benchmarked launch: 1024 held-out 256² RVEs at M = 3277 in one
+    mor_solve_multi call (cut into cache-sized sub-batches), cold and with
+    the Born-prior warm start.  Sampled RVEs against the oracle: pattern
+    digest bit-exact, effective stress rel. 1e-5 of the oracle's fixed point,
+    iteration count within one of the oracle's at residual 1e-6; every RVE
+    converged, and the warm start changes no result beyond the tolerance."""
+    import hashlib
+    from concurrent.futures import ProcessPoolExecutor
+
+    import paper_2103_10203_amd as mor
+    from paper_2103_10203_amd import warm
+    G = _golden("headline_sample")
+    B = 1024
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        items = list(ex.map(_held_out, range(B), chunksize=16))
+    gs = [g for g, _ in items]
+    ebs = np.stack([e for _, e in items])
+    plans = mor.make_plans(gs, G["M"])
+    po = np.arange(B)
+    ph = native_phases()
+    cold = mor.solve_multi(plans, po, ebs, ph, 1e-6)
+    assert cold.status == mor.MOR_OK and bool(np.all(cold.residual < 1e-6))
+    born = mor.solve_multi(plans, po, ebs, ph, 1e-6, warm_start=warm.born_warm(plans, po, ebs, ph, 256))
+    assert born.status == mor.MOR_OK
+    assert born.iterations.mean() < cold.iterations.mean()
+    d = np.max(np.abs(born.eff_stress - cold.eff_stress), axis=1) / np.max(np.abs(cold.eff_stress), axis=1)
+    assert np.max(d) < 1e-5
+    for case in G["cases"]:
+        i = case["index"]
+        s, _ = plans[i].pattern()
+        if not case["unstable"]:
+            assert hashlib.sha256(np.asarray(s, dtype="<i8").tobytes()).hexdigest() == case["sorted_idx_sha256"], i
+        want = np.array(case["sigma_bar"])
+        err = np.max(np.abs(cold.eff_stress[i][:4] - want)) / np.max(np.abs(want))
+        assert err < 1e-5, (i, err)
+        assert abs(int(cold.iterations[i]) - case["iterations_1e-6"]) <= 1, i
