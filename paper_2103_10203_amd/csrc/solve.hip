@@ -1844,10 +1844,6 @@ extern "C" mor_status mor_tune_set(int32_t kernel, int32_t ndim, int32_t length,
   return MOR_OK;
 }
 
-// Autotuner: for every distinct row length among the plans, time `reps`
-// batched solves of the given workload with each variant (the other sizes
-// keep their current choice) and keep the fastest.  The workload's results
-// are discarded; the tuned choice applies to later solves in this process.
 extern "C" mor_status mor_tune_subbatch(int64_t bytes, int64_t min_rves, int64_t* prev_bytes, int64_t* prev_min) {
   if (bytes < -1 || min_rves < -1 || min_rves == 0) {
     mor_set_error("mor_tune_subbatch: bytes must be >= 0 and min_rves >= 1 (or -1 to keep)");
@@ -1860,6 +1856,10 @@ extern "C" mor_status mor_tune_subbatch(int64_t bytes, int64_t min_rves, int64_t
   return MOR_OK;
 }
 
+// Autotuner: for every distinct row length among the plans, time `reps`
+// batched solves of the given workload with each variant (the other sizes
+// keep their current choice) and keep the fastest.  The workload's results
+// are discarded; the tuned choice applies to later solves in this process.
 extern "C" mor_status mor_autotune(const mor_plan_t* plans, int64_t nplans, const int64_t* plan_of_rve,
                                    const double* macro_strain_packed, int64_t B, const mor_phase phase[2],
                                    double tol, int32_t reps, void* stream) {
