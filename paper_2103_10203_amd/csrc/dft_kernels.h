@@ -47,19 +47,20 @@ constexpr int DFT_LH = DFT_KC + 8;  // split-bf16 staging row (bf16 values, 16-b
 // Staged operand tiles of one K chunk: FP32 for PREC_F32; for PREC_X3 every
 // value is split once, when it is staged, into its bf16 high part and the
 // bf16 rounding of the remainder (no conversions in the MFMA loop).
-template <int PREC>
+template <int PREC, int MT>
 struct DftTiles;
 // Values are staged four consecutive k at a time (k a multiple of 4), so
 // every LDS store is 16 bytes (FP32) or two of 8 bytes (bf16 high and low).
-template <>
-struct DftTiles<DFT_F32> {
-  float A[DFT_T][DFT_LD], B[DFT_T][DFT_LD];
+// MT rows of A (64 or 128), 64 rows of B.
+template <int MT>
+struct DftTiles<DFT_F32, MT> {
+  float A[MT][DFT_LD], B[DFT_T][DFT_LD];
   __device__ __forceinline__ void put_a(int m, int k, float4 v) { *reinterpret_cast<float4*>(&A[m][k]) = v; }
   __device__ __forceinline__ void put_b(int n, int k, float4 v) { *reinterpret_cast<float4*>(&B[n][k]) = v; }
 };
-template <>
-struct DftTiles<DFT_X3> {
-  unsigned short Ah[DFT_T][DFT_LH], Al[DFT_T][DFT_LH], Bh[DFT_T][DFT_LH], Bl[DFT_T][DFT_LH];
+template <int MT>
+struct DftTiles<DFT_X3, MT> {
+  unsigned short Ah[MT][DFT_LH], Al[MT][DFT_LH], Bh[DFT_T][DFT_LH], Bl[DFT_T][DFT_LH];
   __device__ __forceinline__ static void split(float4 v, unsigned short (*H)[DFT_LH], unsigned short (*Lo)[DFT_LH],
                                                int r, int k) {
     const float a[4] = {v.x, v.y, v.z, v.w};
@@ -77,28 +78,38 @@ struct DftTiles<DFT_X3> {
   __device__ __forceinline__ void put_b(int n, int k, float4 v) { split(v, Bh, Bl, n, k); }
 };
 
-// Accumulate the wave's 32x32 block over one staged K chunk (A[m][k],
-// B[n][k], k contiguous).
-__device__ __forceinline__ void dft_mfma_chunk(const DftTiles<DFT_F32>& t, int wm, int wn, int lane,
-                                               dft_f32x16& acc) {
+// Accumulate the wave's MB 32x32 blocks (rows wm + 32 i, columns wn) over
+// one staged K chunk (A[m][k], B[n][k], k contiguous): each B fragment read
+// serves MB products.
+template <int MT, int MB>
+__device__ __forceinline__ void dft_mfma_chunk(const DftTiles<DFT_F32, MT>& t, int wm, int wn, int lane,
+                                               dft_f32x16 (&acc)[MB]) {
   const int r = lane % 32, kq = lane / 32;
 #pragma unroll
-  for (int ks = 0; ks < DFT_KC; ks += 2)
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(t.A[wm + r][ks + kq], t.B[wn + r][ks + kq], acc, 0, 0, 0);
+  for (int ks = 0; ks < DFT_KC; ks += 2) {
+    const float b = t.B[wn + r][ks + kq];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+      acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(t.A[wm + 32 * i + r][ks + kq], b, acc[i], 0, 0, 0);
+  }
 }
-__device__ __forceinline__ void dft_mfma_chunk(const DftTiles<DFT_X3>& t, int wm, int wn, int lane,
-                                               dft_f32x16& acc) {
+template <int MT, int MB>
+__device__ __forceinline__ void dft_mfma_chunk(const DftTiles<DFT_X3, MT>& t, int wm, int wn, int lane,
+                                               dft_f32x16 (&acc)[MB]) {
   const int r = lane % 32, kq = (lane / 32) * 4;
 #pragma unroll
   for (int ks = 0; ks < DFT_KC; ks += 8) {
-    const dft_bf16x4 ah = *reinterpret_cast<const dft_bf16x4*>(&t.Ah[wm + r][ks + kq]);
-    const dft_bf16x4 al = *reinterpret_cast<const dft_bf16x4*>(&t.Al[wm + r][ks + kq]);
     const dft_bf16x4 bh = *reinterpret_cast<const dft_bf16x4*>(&t.Bh[wn + r][ks + kq]);
     const dft_bf16x4 bl = *reinterpret_cast<const dft_bf16x4*>(&t.Bl[wn + r][ks + kq]);
-    // smallest products first
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const dft_bf16x4 ah = *reinterpret_cast<const dft_bf16x4*>(&t.Ah[wm + 32 * i + r][ks + kq]);
+      const dft_bf16x4 al = *reinterpret_cast<const dft_bf16x4*>(&t.Al[wm + 32 * i + r][ks + kq]);
+      // smallest products first
+      acc[i] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[i], 0, 0, 0);
+      acc[i] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[i], 0, 0, 0);
+      acc[i] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc[i], 0, 0, 0);
+    }
   }
 }
 
@@ -117,39 +128,43 @@ __device__ __forceinline__ int dft_twi(int k, int x, int L) {
 }
 
 // Inverse: Yl (spectra, [C][nlast][rows]) -> E ([C*rows][L] real field).
-// grid (L / 64, C rows / 64, RVEs); LMAX >= L.
-template <int PREC, int LMAX>
+// Workgroup tile (64 MB rows) x 64 columns, MB 32x32 blocks per wavefront.
+// grid (L / 64, C rows / (64 MB), RVEs); LMAX >= L; rows % (64 MB) == 0.
+template <int PREC, int LMAX, int MB>
 __global__ __launch_bounds__(256) void k_dft_inv(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
                                                  const RveState* __restrict__ st, const cpx<float>* __restrict__ Yl,
                                                  Offs off, float* __restrict__ E, int C, int mode_iter) {
-  __shared__ __attribute__((aligned(16))) DftTiles<PREC> tl;
+  constexpr int MT = DFT_T * MB;
+  __shared__ __attribute__((aligned(16))) DftTiles<PREC, MT> tl;
   __shared__ cpx<float> T[LMAX];
   __shared__ int lk[LMAX / 2 + 1];
   const int b = rve_list[blockIdx.z];
   if (mode_iter && !st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
   const int rows = P.rows, L = P.nlen, nlast = P.nlast;
-  const int n0 = blockIdx.x * DFT_T, m0 = blockIdx.y * DFT_T;
+  const int n0 = blockIdx.x * DFT_T, m0 = blockIdx.y * MT;
   if (n0 >= L || m0 >= C * rows) return;
   dft_tables(P, T, lk, L, nlast);
   const int c = m0 / rows, row0 = m0 % rows;
   const cpx<float>* Y = Yl + off.yl[b] + (int64_t)c * nlast * rows + row0;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
-  dft_f32x16 acc;
+  const int wm = (wave / 2) * 32 * MB, wn = (wave % 2) * 32;
+  dft_f32x16 acc[MB];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int q = 0; q < MB; ++q)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[q][i] = 0.f;
   const int K = 2 * nlast;
-  // A: 64 rows x 16 spectrum entries (complex -> two k columns), two
+  // A: MT rows x 16 spectrum entries (complex -> two k columns), two
   // entries (four k columns) per item; the next chunk's entries are loaded
   // into registers before this chunk's MFMAs
-  constexpr int AI = DFT_T * (DFT_KC / 4) / 256;
+  constexpr int AI = MT * (DFT_KC / 4) / 256;
   float4 pa[AI];
   auto load_a = [&](int j0) {
 #pragma unroll
     for (int q = 0; q < AI; ++q) {
       const int t = tid + q * 256;
-      const int mm = t % DFT_T, j = j0 + 2 * (t / DFT_T);
+      const int mm = t % MT, j = j0 + 2 * (t / MT);
       cpx<float> v0 = {0.f, 0.f}, v1 = {0.f, 0.f};
       if (j < nlast) v0 = Y[(int64_t)j * rows + mm];
       if (j + 1 < nlast) v1 = Y[(int64_t)(j + 1) * rows + mm];
@@ -163,12 +178,12 @@ __global__ __launch_bounds__(256) void k_dft_inv(const PlanDev* __restrict__ pla
 #pragma unroll
     for (int q = 0; q < AI; ++q) {
       const int t = tid + q * 256;
-      tl.put_a(t % DFT_T, 4 * (t / DFT_T), pa[q]);
+      tl.put_a(t % MT, 4 * (t / MT), pa[q]);
     }
     // B: Binv[k][x] for x in the tile
     for (int t = tid; t < DFT_T * (DFT_KC / 4); t += 256) {
       const int nn = t % DFT_T, jg = t / DFT_T;
-      float c[4] = {0.f, 0.f, 0.f, 0.f};
+      float cv[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int j = j0 + 2 * jg + h;
@@ -176,55 +191,66 @@ __global__ __launch_bounds__(256) void k_dft_inv(const PlanDev* __restrict__ pla
           const int k = lk[j];
           const float w = (k == 0 || 2 * k == L) ? 1.f : 2.f;
           const cpx<float> tw = T[dft_twi(k, n0 + nn, L)];
-          c[2 * h] = w * tw.x;
-          c[2 * h + 1] = w * tw.y;
+          cv[2 * h] = w * tw.x;
+          cv[2 * h + 1] = w * tw.y;
         }
       }
-      tl.put_b(nn, 4 * jg, make_float4(c[0], c[1], c[2], c[3]));
+      tl.put_b(nn, 4 * jg, make_float4(cv[0], cv[1], cv[2], cv[3]));
     }
     __syncthreads();
     if (k0 + DFT_KC < K) load_a(j0 + DFT_KC / 2);
-    dft_mfma_chunk(tl, wm, wn, lane, acc);
+    dft_mfma_chunk<MT, MB>(tl, wm, wn, lane, acc);
     __syncthreads();
   }
   // D layout: lane -> column n = lane % 32; element i -> row (i/4)*8 + (lane/32)*4 + i%4
   float* Eb = E + off.field[b] * C;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int mm = wm + (i / 4) * 8 + (lane / 32) * 4 + (i % 4);
-    const int x = n0 + wn + lane % 32;
-    Eb[(int64_t)(m0 + mm) * L + x] = acc[i];
-  }
+  for (int q = 0; q < MB; ++q)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int mm = wm + 32 * q + (i / 4) * 8 + (lane / 32) * 4 + (i % 4);
+      const int x = n0 + wn + lane % 32;
+      Eb[(int64_t)(m0 + mm) * L + x] = acc[q][i];
+    }
 }
 
 // Forward: tau ([C*rows][L]) -> Yl spectra at the sampled frequencies.
-// grid (ceil(2 nlast / 64), C rows / 64, RVEs).
-template <int PREC, int LMAX>
+// Workgroup tile (64 MB rows) x 64 columns; grid (ceil(2 nlast / 64),
+// C rows / (64 MB), RVEs).
+template <int PREC, int LMAX, int MB>
 __global__ __launch_bounds__(256) void k_dft_fwd(const PlanDev* __restrict__ plans, const int* __restrict__ rve_list,
                                                  const RveState* __restrict__ st, cpx<float>* __restrict__ Yl,
                                                  Offs off, const float* __restrict__ E, int C) {
-  __shared__ __attribute__((aligned(16))) DftTiles<PREC> tl;
+  constexpr int MT = DFT_T * MB;
+  // the operand tiles and the result tile are never live together
+  union Smem {
+    DftTiles<PREC, MT> tl;
+    float Cs[MT][DFT_T + 1];
+  };
+  __shared__ __attribute__((aligned(16))) Smem sm;
+  DftTiles<PREC, MT>& tl = sm.tl;
   __shared__ cpx<float> T[LMAX];
   __shared__ int lk[LMAX / 2 + 1];
-  __shared__ float Cs[DFT_T][DFT_T + 1];
   const int b = rve_list[blockIdx.z];
   if (!st[b].active) return;
   const PlanDev& P = plans[st[b].plan];
   const int rows = P.rows, L = P.nlen, nlast = P.nlast;
-  const int n0 = blockIdx.x * DFT_T, m0 = blockIdx.y * DFT_T;
+  const int n0 = blockIdx.x * DFT_T, m0 = blockIdx.y * MT;
   if (n0 >= 2 * nlast || m0 >= C * rows) return;
   dft_tables(P, T, lk, L, nlast);
   const int c = m0 / rows, row0 = m0 % rows;
   const float* A = E + off.field[b] * C + (int64_t)m0 * L;
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int wm = (wave / 2) * 32, wn = (wave % 2) * 32;
-  dft_f32x16 acc;
+  const int wm = (wave / 2) * 32 * MB, wn = (wave % 2) * 32;
+  dft_f32x16 acc[MB];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  for (int q = 0; q < MB; ++q)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[q][i] = 0.f;
   // four consecutive x per item (16-byte loads; L and k0 are multiples of 32);
   // the next chunk's items are loaded into registers before this chunk's
   // MFMAs, so their latency overlaps the products
-  constexpr int AI = DFT_T * (DFT_KC / 4) / 256;
+  constexpr int AI = MT * (DFT_KC / 4) / 256;
   float4 pa[AI];
   auto load_a = [&](int k0) {
 #pragma unroll
@@ -259,21 +285,24 @@ __global__ __launch_bounds__(256) void k_dft_fwd(const PlanDev* __restrict__ pla
     }
     __syncthreads();
     if (k0 + DFT_KC < L) load_a(k0 + DFT_KC);
-    dft_mfma_chunk(tl, wm, wn, lane, acc);
+    dft_mfma_chunk<MT, MB>(tl, wm, wn, lane, acc);
     __syncthreads();
   }
+  // (the loop ended with a barrier: every wave is done with the tiles)
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int mm = wm + (i / 4) * 8 + (lane / 32) * 4 + (i % 4);
-    Cs[mm][wn + lane % 32] = acc[i];
-  }
+  for (int q = 0; q < MB; ++q)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int mm = wm + 32 * q + (i / 4) * 8 + (lane / 32) * 4 + (i % 4);
+      sm.Cs[mm][wn + lane % 32] = acc[q][i];
+    }
   __syncthreads();
   // store complex Y[c][j][row]: rows fastest, 8-byte entries
   cpx<float>* Y = Yl + off.yl[b] + (int64_t)c * nlast * rows + row0;
-  for (int t = tid; t < DFT_T * (DFT_T / 2); t += 256) {
-    const int mm = t % DFT_T, jj = t / DFT_T;
+  for (int t = tid; t < MT * (DFT_T / 2); t += 256) {
+    const int mm = t % MT, jj = t / MT;
     const int j = n0 / 2 + jj;
-    if (j < nlast) Y[(int64_t)j * rows + mm] = {Cs[mm][2 * jj], Cs[mm][2 * jj + 1]};
+    if (j < nlast) Y[(int64_t)j * rows + mm] = {sm.Cs[mm][2 * jj], sm.Cs[mm][2 * jj + 1]};
   }
 }
 

@@ -687,17 +687,33 @@ mor_status launch_init(SolveCtx& cx, Group& g, const cpx<float>* warm) {
 constexpr int kDftLmax = 512;
 constexpr int kDftRb = 8;  // rows per block of the pointwise kernel
 
+// Workgroup tiles of 128 field rows where every component's rows split
+// evenly into them (two 32x32 blocks per wavefront share each twiddle
+// fragment), else 64.
 template <int PREC>
 void dft_inverse(SolveCtx& cx, Group& g, int C, int rows, int L, int mode_iter) {
-  dim3 gi(L / DFT_T, C * rows / DFT_T, (unsigned)g.rves.size());
-  k_dft_inv<PREC, kDftLmax><<<gi, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.d_dfte, C,
-                                                   mode_iter);
+  if (rows % (2 * DFT_T) == 0) {
+    dim3 gi(L / DFT_T, C * rows / (2 * DFT_T), (unsigned)g.rves.size());
+    k_dft_inv<PREC, kDftLmax, 2><<<gi, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.d_dfte,
+                                                        C, mode_iter);
+  } else {
+    dim3 gi(L / DFT_T, C * rows / DFT_T, (unsigned)g.rves.size());
+    k_dft_inv<PREC, kDftLmax, 1><<<gi, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.d_dfte,
+                                                        C, mode_iter);
+  }
 }
 
 template <int PREC>
 void dft_forward(SolveCtx& cx, Group& g, int C, int rows) {
-  dim3 gf((2 * g.nlast_max + DFT_T - 1) / DFT_T, C * rows / DFT_T, (unsigned)g.rves.size());
-  k_dft_fwd<PREC, kDftLmax><<<gf, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.d_dfte, C);
+  if (rows % (2 * DFT_T) == 0) {
+    dim3 gf((2 * g.nlast_max + DFT_T - 1) / DFT_T, C * rows / (2 * DFT_T), (unsigned)g.rves.size());
+    k_dft_fwd<PREC, kDftLmax, 2><<<gf, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.d_dfte,
+                                                        C);
+  } else {
+    dim3 gf((2 * g.nlast_max + DFT_T - 1) / DFT_T, C * rows / DFT_T, (unsigned)g.rves.size());
+    k_dft_fwd<PREC, kDftLmax, 1><<<gf, 256, 0, cx.st>>>(cx.d_plans, g.d_list, cx.d_st, cx.d_yl, cx.off, cx.d_dfte,
+                                                        C);
+  }
 }
 
 template <int C, int MAT>
