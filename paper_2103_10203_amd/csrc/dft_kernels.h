@@ -30,6 +30,7 @@ namespace mor_k {
 enum { DFT_F32 = 0, DFT_X3 = 1 };
 
 typedef short dft_bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 dft_bf16x8 __attribute__((ext_vector_type(8)));
 typedef float dft_f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ unsigned short dft_f2bf(float f) {
@@ -93,22 +94,24 @@ __device__ __forceinline__ void dft_mfma_chunk(const DftTiles<DFT_F32, MT>& t, i
       acc[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(t.A[wm + 32 * i + r][ks + kq], b, acc[i], 0, 0, 0);
   }
 }
+// gfx950's 32x32x16 bf16 MFMA: lane l holds row l % 32 and the eight
+// consecutive k (l / 32) * 8 .. + 7 of each operand (16-byte LDS reads).
 template <int MT, int MB>
 __device__ __forceinline__ void dft_mfma_chunk(const DftTiles<DFT_X3, MT>& t, int wm, int wn, int lane,
                                                dft_f32x16 (&acc)[MB]) {
-  const int r = lane % 32, kq = (lane / 32) * 4;
+  const int r = lane % 32, kq = (lane / 32) * 8;
 #pragma unroll
-  for (int ks = 0; ks < DFT_KC; ks += 8) {
-    const dft_bf16x4 bh = *reinterpret_cast<const dft_bf16x4*>(&t.Bh[wn + r][ks + kq]);
-    const dft_bf16x4 bl = *reinterpret_cast<const dft_bf16x4*>(&t.Bl[wn + r][ks + kq]);
+  for (int ks = 0; ks < DFT_KC; ks += 16) {
+    const dft_bf16x8 bh = *reinterpret_cast<const dft_bf16x8*>(&t.Bh[wn + r][ks + kq]);
+    const dft_bf16x8 bl = *reinterpret_cast<const dft_bf16x8*>(&t.Bl[wn + r][ks + kq]);
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
-      const dft_bf16x4 ah = *reinterpret_cast<const dft_bf16x4*>(&t.Ah[wm + 32 * i + r][ks + kq]);
-      const dft_bf16x4 al = *reinterpret_cast<const dft_bf16x4*>(&t.Al[wm + 32 * i + r][ks + kq]);
+      const dft_bf16x8 ah = *reinterpret_cast<const dft_bf16x8*>(&t.Ah[wm + 32 * i + r][ks + kq]);
+      const dft_bf16x8 al = *reinterpret_cast<const dft_bf16x8*>(&t.Al[wm + 32 * i + r][ks + kq]);
       // smallest products first
-      acc[i] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(al, bh, acc[i], 0, 0, 0);
-      acc[i] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bl, acc[i], 0, 0, 0);
-      acc[i] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(ah, bh, acc[i], 0, 0, 0);
+      acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[i], 0, 0, 0);
+      acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[i], 0, 0, 0);
+      acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[i], 0, 0, 0);
     }
   }
 }
