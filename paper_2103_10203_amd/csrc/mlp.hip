@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
 }
 
 // ------------------------------------------------------------------ bf16 helpers
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
@@ -127,7 +127,7 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 // ------------------------------------------------------------------ BF16 MFMA GEMM (inference)
 // C[m][n] = act(sum_k A[m][k] Bt[n][k] + bias[n]) with A bf16 [M][Kp] and Bt
 // bf16 [N][Kp] (K padded with zeros to a multiple of 32), FP32 accumulation
-// on v_mfma_f32_32x32x8_bf16.  Workgroup = 4 wavefronts on a 128 x 128
+// on v_mfma_f32_32x32x16_bf16.  Workgroup = 4 wavefronts on a 128 x 128
 // output tile (2 x 2 wavefronts of 64 x 64, each 2 x 2 MFMA blocks).  K is
 // staged 128 at a time through LDS, the next stage's global loads issued
 // before the current stage's MFMAs: at the inference batch (1024 rows) the
@@ -183,19 +183,21 @@ __global__ __launch_bounds__(256) void k_mm_bf16(int M, int N, int Kp, const uns
     if (k0 + MM_K < Kp) {
       MM_FETCH(k0 + MM_K)
     }
-    const int r = lane % 32, kq = (lane / 32) * 4;
+    // gfx950's 32x32x16 bf16 MFMA: lane l holds row l % 32 and the eight
+    // consecutive k (l / 32) * 8 .. + 7 of each operand
+    const int r = lane % 32, kq = (lane / 32) * 8;
 #pragma unroll
-    for (int ks = 0; ks < MM_K; ks += 8) {
-      bf16x4 a[2], b[2];
+    for (int ks = 0; ks < MM_K; ks += 16) {
+      bf16x8 a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        a[i] = *reinterpret_cast<const bf16x4*>(&As[wm + i * 32 + r][ks + kq]);
-        b[i] = *reinterpret_cast<const bf16x4*>(&Bs[wn + i * 32 + r][ks + kq]);
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + i * 32 + r][ks + kq]);
+        b[i] = *reinterpret_cast<const bf16x8*>(&Bs[wn + i * 32 + r][ks + kq]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
 #undef MM_FETCH
