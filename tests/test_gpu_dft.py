@@ -30,7 +30,7 @@ def _fields(res, dim):
 
 
 CASES = [
-    ("disk64", 2), ("fibres256", 2), ("box3d", 3),
+    ("disk64", 2), ("fibres256", 2), ("box3d", 3), ("rect192x384", 2),
 ]
 
 
@@ -41,6 +41,11 @@ def _case(name):
     if name == "fibres256":
         g, eb = synth.metric_rve(5)
         return g, list(eb), 3277
+    if name == "rect192x384":
+        # a last axis that is not a power of two (twiddle indices reduced
+        # modulo 384) and rows that split into 64-row tiles only
+        g = synth.rsa_fibres(192, 384, 8.0, 16.0, seed=19, target_vf=0.35).g
+        return g, [1e-3, -4e-4, 6e-4], int(math.ceil(0.05 * g.size))
     g = synth.rsa_spheres(32, 64, 64, 5.0, 9.0, seed=3, target_vf=0.25).g
     eb = [1e-3, -5e-4, 2e-4, 3e-4, -1e-4, 4e-4]
     return g, eb, int(math.ceil(0.02 * g.size))
