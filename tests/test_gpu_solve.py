@@ -398,9 +398,9 @@ def test_extreme_grid_shapes(shape, R):
 def test_subbatches_match_one_batch():
     """Cutting the batch into cache-sized sub-batches (iterated one after the
     other) changes no result: uneven grids with different iteration counts,
-    fields, 3D, the persistent schedule, hipGraph replay and batched J2 paths,
-    each bit for bit against the same call with the limit off; the split
-    runs also match the oracle."""
+    fields, 3D, the persistent schedule, hipGraph replay, the FP64 path, the
+    split-bf16 DFT path and batched J2 paths, each bit for bit against the
+    same call with the limit off; the split runs also match the oracle."""
     import torch
     mor = _mor()
     gs = [synth.fibre_rve_256(90 + i, n).g for i, n in enumerate((64, 128, 256, 128, 64))]
@@ -420,6 +420,8 @@ def test_subbatches_match_one_batch():
         res = {"multi": mor.solve_multi(plans, po, ebs, native_phases(), 1e-6, want_fields=True),
                "pers": mor.solve_multi(plans, po, ebs, native_phases(), 1e-6, schedule=mor.SCHED_PERSISTENT),
                "graph": mor.solve_multi(plans, po, ebs, native_phases(), 1e-6, use_graph=1),
+               "fp64": mor.solve_multi(plans, po, ebs, native_phases(), 1e-9, precision=mor.PREC_FP64),
+               "dft": mor.solve_multi(plans, po, ebs, native_phases(), 1e-5, precision=mor.PREC_BF16X3),
                "3d": mor.solve(p3, e3, native_phases(), 1e-6)}
         state = torch.zeros(5 * 5 * g2.size, dtype=torch.float32, device="cuda")
         res["j2"] = mor.solve_path_multi([plan2], np.zeros(5, dtype=np.int64), paths, native_phases(j2=True), 1e-6,
@@ -437,7 +439,7 @@ def test_subbatches_match_one_batch():
     finally:
         mor.tune_subbatch(*keep)
     for split in (ones, some):
-        for key in ("multi", "pers", "graph", "3d", "j2"):
+        for key in ("multi", "pers", "graph", "fp64", "dft", "3d", "j2"):
             assert np.array_equal(split[key].eff_stress, whole[key].eff_stress), key
             assert np.array_equal(split[key].iterations, whole[key].iterations), key
         assert bool(torch.equal(split["multi"].strain, whole["multi"].strain))
