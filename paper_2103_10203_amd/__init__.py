@@ -5,7 +5,7 @@ The product is ``libmor.so`` (HIP kernels for gfx950 behind the C ABI in
 script (``build.py``) and the thin ctypes binding (``_native``).
 """
 from ._native import (  # noqa: F401
-    Phase, Plan, SolveResult, MorError, make_plans, solve, solve_multi, solve_path, solve_path_multi, compat, stress_error,
+    Phase, Plan, PlanList, SolveResult, MorError, make_plans, solve, solve_multi, solve_path, solve_path_multi, compat, stress_error,
     PATTERN_ADAPTED, PATTERN_RADIAL,
     profile_enable, profile_reset, profile_query, version, lib,
     GAMMA_ROTATED, GAMMA_CONTINUOUS, PREC_FP32, PREC_BF16X3, PREC_FP64,

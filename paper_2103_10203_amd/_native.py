@@ -205,6 +205,9 @@ def _grid_of(shape):
     return grid
 
 
+_plans_closed = 0  # plans destroyed so far (invalidates cached handle arrays)
+
+
 class Plan:
     """Sampling pattern of one microstructure (mor_plan_create): the adapted
     pattern of M frequencies, or with radial_lines=L the fixed radial pattern
@@ -272,9 +275,11 @@ class Plan:
         return out
 
     def close(self):
+        global _plans_closed
         if getattr(self, "_h", None):
             lib.mor_plan_destroy(self._h)
             self._h = None
+            _plans_closed += 1
 
     def __del__(self):
         try:
@@ -286,6 +291,38 @@ class Plan:
 def _plan_opts(gamma_kind, stream, radial_lines):
     kind = PATTERN_RADIAL if radial_lines else PATTERN_ADAPTED
     return mor_plan_opts(int(gamma_kind), kind, _stream_ptr(stream), int(radial_lines), 0)
+
+
+class PlanList(list):
+    """The list make_plans returns.  It keeps the arrays the batched calls
+    pass to the library (plan handles, grid points and coefficient counts per
+    plan), built on first use and rebuilt whenever the list's members change,
+    so that repeated calls on the same plans marshal them once."""
+
+    _arrays = None
+
+
+def _plan_arrays(plans):
+    """(handles, N, n_coeff) of a sequence of plans: a ctypes array of the
+    handles and two int64 arrays; cached on a PlanList while its members stay
+    the same objects."""
+    members = tuple(plans)
+    cached = getattr(plans, "_arrays", None)
+    # same member objects (plans define no equality: identity) and no plan
+    # closed since (a closed member must fail below, not pass a stale handle)
+    if cached is not None and cached[0] == _plans_closed and cached[1] == members:
+        return cached[2]
+    arrs = ((ct.c_void_p * len(members))(*[p.handle.value for p in members]),
+            np.fromiter((p.N for p in members), np.int64, len(members)),
+            np.fromiter((p.n_coeff for p in members), np.int64, len(members)))
+    if isinstance(plans, PlanList):
+        plans._arrays = (_plans_closed, members, arrs)
+    return arrs
+
+
+def _plan_sum(counts, po):
+    """Sum of a per-plan count over the RVEs' plans."""
+    return int(counts[po].sum()) if len(po) else 0
 
 
 def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, stream=None, radial_lines: int = 0):
@@ -301,7 +338,7 @@ def make_plans(grids, M, gamma_kind: int = GAMMA_ROTATED, stream=None, radial_li
     groups = {}
     for i, g in enumerate(grids):
         groups.setdefault(g.shape, []).append(i)
-    out = [None] * len(grids)
+    out = PlanList([None] * len(grids))
     opts = _plan_opts(gamma_kind, stream, radial_lines)
     for shape, idx in groups.items():
         grid = _grid_of(shape)
@@ -412,10 +449,10 @@ def solve_multi(plans, plan_of, macro_strain, phases, tol: float, max_iter: int 
     po = np.ascontiguousarray(plan_of, dtype=np.int64)
     if po.shape != (B,) or (B and (po.min() < 0 or po.max() >= len(plans))):
         raise ValueError("plan_of needs one index into plans per RVE")
-    handles = (ct.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    handles, n_pts, n_coef = _plan_arrays(plans)
     S = plans[0].nstress
-    npts = int(sum(plans[i].N for i in po))
-    ncoef = int(sum(plans[i].n_coeff for i in po)) * C
+    npts = _plan_sum(n_pts, po)
+    ncoef = _plan_sum(n_coef, po) * C
     _check_tensor(warm_start, "warm_start", "complex64", ncoef)
     out, eff, its, res, strain, stress, coeffs = _outputs(B, S, B, want_fields, want_coeffs, npts, C, ncoef)
     opts = _opts(max_iter, check_every, warm_start, stream, precision, transform, use_graph, schedule)
@@ -466,10 +503,10 @@ def solve_path_multi(plans, plan_of, macro_strains, phases, tol: float, state, m
     if C != plans[0].ncomp:
         raise ValueError(f"macro strains need {plans[0].ncomp} components")
     nst = 5 if plans[0].ndim == 2 else 7
-    npts = int(sum(plans[i].N for i in po))
+    handles, n_pts, n_coef = _plan_arrays(plans)
+    npts = _plan_sum(n_pts, po)
     _check_tensor(state, "state", "float32", nst * npts)
-    handles = (ct.c_void_p * len(plans))(*[p.handle.value for p in plans])
-    ncoef = int(sum(plans[i].n_coeff for i in po)) * C
+    ncoef = _plan_sum(n_coef, po) * C
     out, eff, its, res, strain, stress, coeffs = _outputs(B * steps, 6, B * steps, False, want_coeffs,
                                                           npts, C, ncoef)
     if want_fields:  # field outputs hold the last step of each RVE
@@ -637,7 +674,7 @@ class MLP:
 
 
 def _plan_array(plans):
-    return (ct.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    return _plan_arrays(plans)[0]
 
 
 def warm_features(plans, plan_of, nslots: int, stream=None):
@@ -652,7 +689,7 @@ def warm_features(plans, plan_of, nslots: int, stream=None):
 def warm_targets(plans, plan_of, nslots: int, phases, coeffs, stream=None):
     torch = _torch()
     po = np.ascontiguousarray(plan_of, dtype=np.int64)
-    _check_tensor(coeffs, "coeffs", "complex64", 9 * int(sum(plans[i].n_coeff for i in po)))
+    _check_tensor(coeffs, "coeffs", "complex64", 9 * _plan_sum(_plan_arrays(plans)[2], po))
     T = torch.empty((len(po), 18 * nslots), dtype=torch.float32, device="cuda")
     _check(lib.mor_warm_targets(_plan_array(plans), len(plans), _np_ptr(po), len(po), nslots, _phases(phases),
                                 ct.c_void_p(coeffs.data_ptr()), ct.c_void_p(T.data_ptr()), _stream_ptr(stream)))
@@ -666,7 +703,7 @@ def warm_apply(plans, plan_of, nslots: int, phases, Y, macro_strain, stream=None
     if eb.shape != (len(po), 3):
         raise ValueError("macro_strain must be [B][3]")
     _check_tensor(Y, "Y", "float32", len(po) * 18 * int(nslots))
-    n = int(sum(plans[i].n_coeff for i in po)) * 3
+    n = _plan_sum(_plan_arrays(plans)[2], po) * 3
     W = torch.empty(n, dtype=torch.complex64, device="cuda")
     _check(lib.mor_warm_apply(_plan_array(plans), len(plans), _np_ptr(po), len(po), nslots, _phases(phases),
                               ct.c_void_p(Y.data_ptr()), _np_ptr(eb), ct.c_void_p(W.data_ptr()),

@@ -53,6 +53,15 @@ struct Workspace {
   hipStream_t cap = nullptr;         // private stream for hipGraph capture
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
+  // Pinned host staging of the solve's small transfers (plan table, offsets,
+  // states, effective stresses): copies from pinned memory are queued without
+  // a host-side staging copy.  Sized to the largest total one solve asked for
+  // (the first solve of a new size stages through pageable memory instead);
+  // pin_ev follows the last copy that used it.
+  unsigned char* pin = nullptr;
+  size_t pin_cap = 0, pin_need = 0;
+  hipEvent_t pin_ev = nullptr;
+  bool pin_busy = false;
   ~Workspace() {}
   template <typename T>
   mor_status get(const char* name, size_t count, T** out) {
@@ -298,6 +307,8 @@ struct SolveCtx {
   unsigned char* arena = nullptr;
   size_t arena_cap = 0, arena_used = 0;
   unsigned int h_active_local = 0;
+  size_t pin_used = 0;       // bytes of the workspace's pinned staging taken by this solve
+  bool pin_claimed = false;  // the staging was made ready for this solve
   cpx<double>* yl64() const { return reinterpret_cast<cpx<double>*>(d_yl); }
   cpx<double>* yc64() const { return reinterpret_cast<cpx<double>*>(d_yc); }
   cpx<double>* coef64() const { return reinterpret_cast<cpx<double>*>(d_coef); }
@@ -325,11 +336,60 @@ __global__ void k_zero_f32(float* __restrict__ p, int64_t n) {
     p[i] = 0.f;
 }
 
-// Asynchronous upload from a host copy kept alive until the solve ends.
+// nb bytes of the workspace's pinned staging for one transfer of this
+// solve, or nullptr (no workspace, or the staging is too small this time).
+// Each transfer gets its own range: the solve never reuses one while a copy
+// may still read or write it, and the next solve on the stream waits for
+// the last copy before it starts over.
+unsigned char* pin_slot(SolveCtx& cx, size_t nb) {
+  if (!cx.ws) return nullptr;
+  Workspace& w = *cx.ws;
+  if (!cx.pin_claimed) {
+    cx.pin_claimed = true;
+    if (w.pin_busy) {
+      (void)hipEventSynchronize(w.pin_ev);
+      w.pin_busy = false;
+    }
+    if (w.pin_need > w.pin_cap) {
+      if (w.pin) (void)hipHostFree(w.pin);
+      w.pin = nullptr;
+      w.pin_cap = 0;
+      if (hipHostMalloc((void**)&w.pin, w.pin_need, hipHostMallocDefault) == hipSuccess) {
+        w.pin_cap = w.pin_need;
+      } else {
+        (void)hipGetLastError();
+        w.pin = nullptr;
+      }
+    }
+    if (!w.pin_ev && hipEventCreateWithFlags(&w.pin_ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      w.pin_ev = nullptr;
+    }
+  }
+  const size_t off = (cx.pin_used + 255) / 256 * 256;
+  cx.pin_used = off + nb;
+  w.pin_need = std::max(w.pin_need, cx.pin_used);
+  return (w.pin && w.pin_ev && cx.pin_used <= w.pin_cap) ? w.pin + off : nullptr;
+}
+
+// The last queued copy through the pinned staging.
+mor_status pin_mark(SolveCtx& cx) {
+  MOR_HIP_TRY(hipEventRecord(cx.ws->pin_ev, cx.st));
+  cx.ws->pin_busy = true;
+  return MOR_OK;
+}
+
+// Asynchronous upload from pinned staging, else from a host copy kept alive
+// until the solve ends.
 template <typename T>
 mor_status upload(SolveCtx& cx, T* dst, const std::vector<T>& src) {
   if (src.empty()) return MOR_OK;
   const size_t nb = src.size() * sizeof(T);
+  if (unsigned char* pin = pin_slot(cx, nb)) {
+    std::memcpy(pin, src.data(), nb);
+    MOR_HIP_TRY(hipMemcpyAsync(dst, pin, nb, hipMemcpyHostToDevice, cx.st));
+    return pin_mark(cx);
+  }
   cx.keep.emplace_back(nb);
   std::memcpy(cx.keep.back().data(), src.data(), nb);
   MOR_HIP_TRY(hipMemcpyAsync(dst, cx.keep.back().data(), nb, hipMemcpyHostToDevice, cx.st));
@@ -1250,10 +1310,19 @@ void account(SolveCtx& cx, const std::vector<RveState>& hs, int passes = 1);
 
 mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<RveState>* states_out) {
   std::vector<RveState> hs(cx.B);
-  MOR_HIP_TRY(hipMemcpyAsync(hs.data(), cx.d_st, cx.B * sizeof(RveState), hipMemcpyDeviceToHost, cx.st));
   std::vector<double> eff((size_t)cx.B * cx.S);
+  const size_t hs_nb = hs.size() * sizeof(RveState), eff_nb = eff.size() * sizeof(double);
+  unsigned char* hs_pin = pin_slot(cx, hs_nb);
+  unsigned char* eff_pin = (out && out->eff_stress) ? pin_slot(cx, eff_nb) : nullptr;
+  MOR_HIP_TRY(hipMemcpyAsync(hs_pin ? (void*)hs_pin : (void*)hs.data(), cx.d_st, hs_nb, hipMemcpyDeviceToHost,
+                             cx.st));
   if (out && out->eff_stress)
-    MOR_HIP_TRY(hipMemcpyAsync(eff.data(), cx.d_eff, eff.size() * sizeof(double), hipMemcpyDeviceToHost, cx.st));
+    MOR_HIP_TRY(hipMemcpyAsync(eff_pin ? (void*)eff_pin : (void*)eff.data(), cx.d_eff, eff_nb,
+                               hipMemcpyDeviceToHost, cx.st));
+  if (hs_pin || eff_pin) {
+    mor_status ms = pin_mark(cx);
+    if (ms != MOR_OK) return ms;
+  }
   if (out && out->coeffs) {
     int64_t tot = 0;
     for (int64_t b = 0; b < cx.B; ++b) tot += (int64_t)cx.C * cx.ncoef_h[b];
@@ -1267,6 +1336,9 @@ mor_status collect(SolveCtx& cx, mor_outputs* out, int eff_stride, std::vector<R
     }
   }
   MOR_HIP_TRY(hipStreamSynchronize(cx.st));
+  if (cx.ws) cx.ws->pin_busy = false;
+  if (hs_pin) std::memcpy(hs.data(), hs_pin, hs_nb);
+  if (eff_pin) std::memcpy(eff.data(), eff_pin, eff_nb);
   account(cx, hs);
   mor_status worst = MOR_OK;
   for (int64_t b = 0; b < cx.B; ++b) {

@@ -153,3 +153,35 @@ def test_make_plans_checks_its_arguments():
     with pytest.raises(ValueError):
         mor.make_plans([g, g], [5])
     assert mor.make_plans([], 5) == []
+
+
+def test_plan_arrays_cached_on_plan_lists():
+    """The handle and size arrays of a PlanList are built once and rebuilt
+    when a member changes or a plan is closed; a plain list is marshalled on
+    every call.  (Stand-in plan objects: no device needed.)"""
+    import ctypes as ct
+
+    from paper_2103_10203_amd import _native
+
+    class FakePlan:
+        def __init__(self, h, n, nc):
+            self.handle, self.N, self.n_coeff = ct.c_void_p(h), n, nc
+
+    plans = _native.PlanList([FakePlan(16 * (i + 1), 100 + i, 7 + i) for i in range(5)])
+    a = _native._plan_arrays(plans)
+    assert [a[0][i] for i in range(5)] == [16 * (i + 1) for i in range(5)]
+    assert a[1].tolist() == [100 + i for i in range(5)] and a[2].tolist() == [7 + i for i in range(5)]
+    assert _native._plan_arrays(plans) is a
+    po = np.array([4, 0, 0, 2], np.int64)
+    assert _native._plan_sum(a[1], po) == 104 + 100 + 100 + 102
+    assert _native._plan_sum(a[2], np.zeros(0, np.int64)) == 0
+    plans[2] = FakePlan(999, 1, 2)  # a member replaced: rebuilt
+    b = _native._plan_arrays(plans)
+    assert b is not a and b[0][2] == 999 and b[1][2] == 1
+    _native._plans_closed += 1  # as Plan.close() does: rebuilt
+    try:
+        assert _native._plan_arrays(plans) is not b
+    finally:
+        _native._plans_closed -= 1
+    plain = list(plans)
+    assert _native._plan_arrays(plain) is not _native._plan_arrays(plain)
