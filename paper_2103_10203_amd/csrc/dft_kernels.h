@@ -16,10 +16,10 @@
 // operands are generated per tile from a table of exp(-2 pi i t / L) in LDS.
 // Precision: PREC_F32 uses the FP32 MFMA (32x32x2); PREC_X3 splits every
 // operand a = a_hi + a_lo into two bfloat16 numbers and accumulates
-// a_hi b_hi + a_hi b_lo + a_lo b_hi in FP32 with the bf16 MFMA (32x32x8).
+// a_hi b_hi + a_hi b_lo + a_lo b_hi in FP32 with the bf16 MFMA (32x32x16).
 //
-// Workgroup = 4 wavefronts computing a 64 (m) x 64 (n) output tile, each
-// wavefront one 32 x 32 block; K is staged through LDS 32 at a time.
+// Workgroup = 4 wavefronts computing a (64 MB) (m) x 64 (n) output tile,
+// each wavefront MB blocks of 32 x 32; K is staged through LDS 32 at a time.
 // Requires rows % 64 == 0 and L % 64 == 0 (checked by the host).
 #pragma once
 

@@ -482,3 +482,31 @@ def test_large_laminates_exact(shape):
     emin = e.amin(dim=2).cpu().numpy()
     assert np.max(np.abs(emax - ref)) < 5e-8 and np.max(np.abs(emin - ref)) < 5e-8
     assert np.max(np.abs(out.eff_stress[0] - stress_comps(sbar, dim))) < 1e-5 * np.max(np.abs(sbar))
+
+
+def test_plan_list_member_replaced_and_staging_reused():
+    """Batched solves on a PlanList (make_plans) whose member is replaced
+    between calls use the new plan (the cached handle array is rebuilt), and
+    a run of solves of changing batch size on one stream (pinned staging of
+    the small transfers grown, then reused) repeats each result bit for bit."""
+    mor = _mor()
+    gs = [synth.rsa_fibres(64, 64, 2.0, 4.0, seed=90 + k, target_vf=0.35).g for k in range(3)]
+    plans = mor.make_plans(gs[:2], 205)
+    assert isinstance(plans, mor.PlanList)
+    po = np.array([0, 1, 1, 0])
+    ebs = synth.macro_strains(len(po), 3, 5e-3, seed=17)
+    first = mor.solve_multi(plans, po, ebs, native_phases(), 1e-6)
+    plans[1] = mor.Plan(gs[2], 205)
+    swapped = mor.solve_multi(plans, po, ebs, native_phases(), 1e-6)
+    fresh = mor.solve_multi([mor.Plan(gs[0], 205), mor.Plan(gs[2], 205)], po, ebs, native_phases(), 1e-6)
+    assert np.array_equal(swapped.eff_stress, fresh.eff_stress)
+    assert np.array_equal(swapped.eff_stress[0], first.eff_stress[0])
+    assert not np.array_equal(swapped.eff_stress[1], first.eff_stress[1])
+    # sizes 4, 64, 4, 64: the 64-RVE call outgrows the staging of the first
+    big_po = np.arange(64) % 2
+    big_eb = synth.macro_strains(64, 3, 5e-3, seed=18)
+    runs = [(po, ebs), (big_po, big_eb), (po, ebs), (big_po, big_eb)]
+    outs = [mor.solve_multi(plans, p, e, native_phases(), 1e-6) for p, e in runs]
+    for a, b in ((outs[0], outs[2]), (outs[1], outs[3])):
+        assert np.array_equal(a.eff_stress, b.eff_stress) and np.array_equal(a.iterations, b.iterations)
+    assert np.array_equal(outs[0].eff_stress, swapped.eff_stress)
