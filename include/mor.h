@@ -22,6 +22,10 @@
  *  - The caller owns every buffer it passes; the library owns plans.
  *  - All work is issued on the stream given in the options (NULL = the null
  *    stream).  Calls that return host results synchronise that stream.
+ *  - The solve calls keep a workspace per (device, stream): device buffers
+ *    and a pinned host staging buffer (at most 64 MiB) for their small
+ *    transfers, grown on demand and held until the process ends
+ *    (mor_solve_noalloc uses none of it).
  */
 #ifndef MOR_H
 #define MOR_H

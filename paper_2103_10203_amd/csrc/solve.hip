@@ -55,9 +55,10 @@ struct Workspace {
   size_t evnext = 0;
   // Pinned host staging of the solve's small transfers (plan table, offsets,
   // states, effective stresses): copies from pinned memory are queued without
-  // a host-side staging copy.  Sized to the largest total one solve asked for
-  // (the first solve of a new size stages through pageable memory instead);
-  // pin_ev follows the last copy that used it.
+  // a host-side staging copy.  Sized to the largest total one solve asked for,
+  // up to kPinStageMax (the first solve of a new size, and whatever does not
+  // fit, stages through pageable memory instead); pin_ev follows the last copy
+  // that used it.
   unsigned char* pin = nullptr;
   size_t pin_cap = 0, pin_need = 0;
   hipEvent_t pin_ev = nullptr;
@@ -336,6 +337,8 @@ __global__ void k_zero_f32(float* __restrict__ p, int64_t n) {
     p[i] = 0.f;
 }
 
+constexpr size_t kPinStageMax = (size_t)64 << 20;
+
 // nb bytes of the workspace's pinned staging for one transfer of this
 // solve, or nullptr (no workspace, or the staging is too small this time).
 // Each transfer gets its own range: the solve never reuses one while a copy
@@ -350,7 +353,7 @@ unsigned char* pin_slot(SolveCtx& cx, size_t nb) {
       (void)hipEventSynchronize(w.pin_ev);
       w.pin_busy = false;
     }
-    if (w.pin_need > w.pin_cap) {
+    if (w.pin_need > w.pin_cap && w.pin_need <= kPinStageMax) {
       if (w.pin) (void)hipHostFree(w.pin);
       w.pin = nullptr;
       w.pin_cap = 0;
