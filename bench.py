@@ -568,9 +568,9 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the batched RVE solves would shard across GPUs without per-iteration "
-              "communication; see the design notes).", file=sys.stderr)
+              "communication).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -44,7 +44,7 @@ typedef enum {
   MOR_E_DEVICE = 3,        /* a HIP runtime call or kernel launch failed      */
   MOR_E_NOT_CONVERGED = 4, /* max_iter reached; outputs hold the last iterate */
   MOR_E_NONFINITE = 5,     /* a NaN/Inf appeared in the iteration             */
-  MOR_E_UNSUPPORTED = 6    /* valid input this build does not handle          */
+  MOR_E_UNSUPPORTED = 6    /* valid input the library does not handle         */
 } mor_status;
 
 /* Opaque plan: the adapted sampling pattern of one microstructure and the
