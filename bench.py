@@ -367,6 +367,29 @@ def _max_rel(got, want):
     return float(np.max(d / np.max(np.abs(want), axis=1)))
 
 
+def cube128(mor, ph, timed, reps=1, variants=("fft", "dft_bf16x3")):
+    """3D: 128^3 spheres (vf 0.25), M = 2 %, 8 macro strains in one
+    mor_solve call, with the FFT and (if listed) the split-bf16 MFMA DFT."""
+    res = {}
+    g3 = synth.rsa_spheres(128, 128, 128, 8.0, 14.0, seed=7, target_vf=0.25).g
+    p3 = mor.Plan(g3, int(math.ceil(0.02 * g3.size)))
+    e3 = synth.macro_strains(8, 6, 1e-3, seed=3)
+    G4 = _golden("c4_128")
+    runs = {"fft": ({}, 1e-6), "dft_bf16x3": ({"precision": mor.PREC_BF16X3}, 1e-5)}
+    for name in variants:
+        kw, tol = runs[name]
+        el, out = timed(lambda: mor.solve(p3, e3, ph, tol, **kw), reps)
+        res[f"cube128_{name}"] = {"workload": "128³ spheres (vf 0.25), M = 2 %, 8 macro strains in one call, "
+                                              f"residual {tol:g}",
+                                  "solves_per_s": 8 / el, "ms": el * 1e3,
+                                  "mean_iterations": float(out.iterations.mean())}
+        if G4:
+            e_one = np.array([G4["macro_strain"]])
+            one = mor.solve(p3, e_one, ph, tol, **kw)
+            res[f"cube128_{name}"]["oracle_rel_err"] = _max_rel(one.eff_stress, [G4["sigma_bar"]])
+    return res
+
+
 def other_configs(mor, ph):
     """Throughput of the other configured workloads (one timed call each,
     after one untimed call): the 4096-RVE uneven batch (also autotuned with
@@ -415,21 +438,7 @@ def other_configs(mor, ph):
     for (k, n), v in keep.items():
         mor.tune_set(2, n, v, k)
     del plans
-    g3 = synth.rsa_spheres(128, 128, 128, 8.0, 14.0, seed=7, target_vf=0.25).g
-    p3 = mor.Plan(g3, int(math.ceil(0.02 * g3.size)))
-    e3 = synth.macro_strains(8, 6, 1e-3, seed=3)
-    G4 = _golden("c4_128")
-    for name, kw, tol in (("fft", {}, 1e-6), ("dft_bf16x3", {"precision": mor.PREC_BF16X3}, 1e-5)):
-        el, out = timed(lambda: mor.solve(p3, e3, ph, tol, **kw))
-        res[f"cube128_{name}"] = {"workload": "128³ spheres (vf 0.25), M = 2 %, 8 macro strains in one call, "
-                                              f"residual {tol:g}",
-                                  "solves_per_s": 8 / el, "ms": el * 1e3,
-                                  "mean_iterations": float(out.iterations.mean())}
-        if G4:
-            e_one = np.array([G4["macro_strain"]])
-            one = mor.solve(p3, e_one, ph, tol, **kw)
-            res[f"cube128_{name}"]["oracle_rel_err"] = _max_rel(one.eff_stress, [G4["sigma_bar"]])
-    del p3
+    res.update(cube128(mor, ph, timed))
     # the paper's 64^2 centred disk (M = 205) to its residual 1e-8, FP64 throughout
     n1 = 64
     g1 = synth.disk(n1, n1, math.sqrt(0.3 * n1 * n1 / math.pi))
@@ -559,7 +568,7 @@ def main():
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the timings of the other configured workloads")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--only", choices=["j2paths"], default=None,
+    ap.add_argument("--only", choices=["j2paths", "cube128"], default=None,
                     help="run one other workload alone and print its JSON (for profiling runs)")
     ap.add_argument("--e2e-batches", type=int, default=4,
                     help="batches of the pipelined end-to-end run (plans of the next batch built meanwhile)")
@@ -583,6 +592,17 @@ def main():
         lm, mm = synth.phase_lame(synth.MATRIX_E, synth.MATRIX_NU)
         li, mi = synth.phase_lame(synth.FIBRE_E, synth.FIBRE_NU)
         print(json.dumps(j2_paths_batched(mor, [mor.Phase(lm, mm, 0.25, 1.0, True), mor.Phase(li, mi)])))
+        return
+    if args.only == "cube128":
+        def timed_only(fn, reps=1):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                r = fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / reps, r
+        print(json.dumps(cube128(mor, phases(), timed_only, reps=3, variants=("fft",))))
         return
 
     def log(msg):
